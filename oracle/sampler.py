@@ -1,0 +1,168 @@
+"""Block schedule of Alg. 5 / Alg. 6 (oracle side; test infrastructure only).
+
+The schedule depends only on the density table, the parameters and the seed
+(never on x or r), so it is drawn up front.  Readings of the paper used here:
+
+* C2  ``select J randomly``: a uniform permutation of the column blocks,
+      of which the first ceil(gamma*n) are used (gamma = 1 -> all).
+* C3  ``without replacement with probability P(I,J)``: successive weighted
+      draws renormalised over the row blocks not yet drawn; blocks of zero
+      weight are never drawn, and the draw count is clamped to their number.
+* C4  the group loop draws ceil(alpha*m) row blocks in total, cut into
+      consecutive groups of s (the last one may be shorter).
+* C5  a group's relaxation is beta_G = b * sum_{I in G} P(I,J).
+* C6  P(I,J) = nnz(A_I^J) / sum_I' nnz(A_I'^J).
+* Mixed sampling (Sec. III-F): weight P_I + theta (P_max - P_I) for the row
+  blocks with P_I > 0, theta = min(1, epoch * theta_step).
+
+Random numbers come from SplitMix64 (Steele, Lea and Flood, 2014) used as a
+counter-based generator: the k-th output for key ``seed`` is
+``mix(seed + (k+1) * 0x9E3779B97F4A7C15)``; a uniform double is the top 53
+bits times 2^-53.  Within epoch e (0-based) the counter is ``e * 2^32 + k``
+where k counts the draws of that epoch in the order they are made.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List
+
+import numpy as np
+
+MASK = (1 << 64) - 1
+GOLDEN = 0x9E3779B97F4A7C15
+
+DENSITY, UNIFORM, MIXED = 0, 1, 2
+
+
+def splitmix64(seed: int, ctr: int) -> int:
+    z = (seed + (ctr + 1) * GOLDEN) & MASK
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK
+    return z ^ (z >> 31)
+
+
+def uniform(seed: int, ctr: int) -> float:
+    return (splitmix64(seed, ctr) >> 11) * (1.0 / 9007199254740992.0)
+
+
+def count_of(frac: float, total: int) -> int:
+    """ceil(frac * total) guarded against FP noise, clamped to [1, total]."""
+    k = int(math.ceil(frac * total - 1e-9))
+    return max(1, min(total, k))
+
+
+def density(nnz: np.ndarray) -> np.ndarray:
+    """P(I,J) = nnz[I,J] / sum_I nnz[I,J] (zero column -> zero P)."""
+    nnz = np.asarray(nnz, dtype=np.int64)
+    col = nnz.sum(axis=0)
+    P = np.zeros(nnz.shape, dtype=np.float64)
+    for J in range(nnz.shape[1]):
+        if col[J] > 0:
+            P[:, J] = nnz[:, J].astype(np.float64) / float(col[J])
+    return P
+
+
+@dataclasses.dataclass
+class Schedule:
+    """Flat schedule arrays (epoch -> columns -> groups -> row blocks)."""
+    epoch_col_ptr: np.ndarray
+    cols: np.ndarray
+    col_group_ptr: np.ndarray
+    group_rb_ptr: np.ndarray
+    rbs: np.ndarray
+    beta: np.ndarray
+
+    @property
+    def n_epochs(self) -> int:
+        return len(self.epoch_col_ptr) - 1
+
+    def steps(self, e: int):
+        """Yield ``(J, [(row_blocks, beta), ...])`` for epoch ``e``."""
+        for c in range(self.epoch_col_ptr[e], self.epoch_col_ptr[e + 1]):
+            groups = []
+            for g in range(self.col_group_ptr[c], self.col_group_ptr[c + 1]):
+                rb = self.rbs[self.group_rb_ptr[g]:self.group_rb_ptr[g + 1]]
+                groups.append((list(int(t) for t in rb), float(self.beta[g])))
+            yield int(self.cols[c]), groups
+
+
+def make_schedule(P: np.ndarray, epochs: int, alpha: float, gamma: float, s: int, b: float,
+                  seed: int, sampling: int = DENSITY, theta_step: float = 0.0) -> Schedule:
+    """Draw the whole schedule (Alg. 5 with s = 1, Alg. 6 in general)."""
+    P = np.asarray(P, dtype=np.float64)
+    m, n = P.shape
+    ecp, cols, cgp, grp, rbs, beta = [0], [], [0], [0], [], []
+    for e in range(epochs):
+        k = 0
+        base = e << 32
+
+        def u():
+            nonlocal k
+            val = uniform(seed, base + k)
+            k += 1
+            return val
+
+        perm = list(range(n))
+        for i in range(n - 1, 0, -1):
+            j = int(math.floor(u() * (i + 1)))
+            perm[i], perm[j] = perm[j], perm[i]
+        theta = min(1.0, e * theta_step)
+        for J in perm[:count_of(gamma, n)]:
+            if sampling == UNIFORM:
+                w = [1.0] * m
+            elif sampling == MIXED:
+                pos = [P[I, J] for I in range(m) if P[I, J] > 0]
+                pmax = max(pos) if pos else 0.0
+                w = [(P[I, J] + theta * (pmax - P[I, J])) if P[I, J] > 0 else 0.0
+                     for I in range(m)]
+            else:
+                w = [P[I, J] for I in range(m)]
+            avail = [I for I in range(m) if w[I] > 0]
+            K = min(count_of(alpha, m), len(avail))
+            draws: List[int] = []
+            for _ in range(K):
+                W = 0.0
+                for I in avail:
+                    W += w[I]
+                target = u() * W
+                acc = 0.0
+                pick = avail[-1]
+                for I in avail:
+                    acc += w[I]
+                    if acc > target:
+                        pick = I
+                        break
+                draws.append(pick)
+                avail.remove(pick)
+            for g0 in range(0, K, s):
+                G = draws[g0:g0 + s]
+                bsum = 0.0
+                for I in G:
+                    bsum += P[I, J]
+                rbs.extend(G)
+                grp.append(len(rbs))
+                beta.append(b * bsum)
+            cols.append(J)
+            cgp.append(len(grp) - 1)
+        ecp.append(len(cols))
+    i32 = lambda a: np.asarray(a, dtype=np.int32)
+    return Schedule(i32(ecp), i32(cols), i32(cgp), i32(grp), i32(rbs),
+                    np.asarray(beta, dtype=np.float64))
+
+
+def full_sweep_schedule(m: int, n: int, epochs: int, beta: float) -> Schedule:
+    """Alg. 4 literally: every column block in order, every row block in
+    order, one row block per update, constant beta."""
+    ecp, cols, cgp, grp, rbs, bet = [0], [], [0], [0], [], []
+    for _ in range(epochs):
+        for J in range(n):
+            for I in range(m):
+                rbs.append(I)
+                grp.append(len(rbs))
+                bet.append(beta)
+            cols.append(J)
+            cgp.append(len(grp) - 1)
+        ecp.append(len(cols))
+    i32 = lambda a: np.asarray(a, dtype=np.int32)
+    return Schedule(i32(ecp), i32(cols), i32(cgp), i32(grp), i32(rbs), np.asarray(bet))

@@ -1,0 +1,306 @@
+"""Pins of the FP64 oracle against closed forms, textbook routines and
+invariants the paper fixes (CPU only).
+
+Each test would fail on a plausible slip in the oracle: a wrong voxel index
+or sign in the Siddon traversal (dense clip comparison, axis-aligned rows),
+a dropped or doubled segment (row sums = chord), a wrong step formula
+(line-search orthogonality, residual identity, one-block steepest descent,
+least-squares limit), a wrong epoch structure (block additivity, fixed point,
+untouched blocks).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.stats
+
+from oracle import csgd, rays, sampler, siddon
+from paper_1709_00953_amd import inputs
+
+
+def tiny_geoms():
+    return {
+        "par2d": inputs.par2d(8, 1.0, 12, 180.0, 14, 0.9, m=3, bx=2, by=2),
+        "fan_flat": inputs.fan2d(8, 1.0, 10, 16, 0.04, 20.0, 40.0, m=2, bx=2, by=2,
+                                 curved=False, pu_flat=1.5),
+        "fan_curved": inputs.fan2d(8, 1.0, 10, 16, 0.04, 20.0, 40.0, m=2, bx=2, by=2),
+        "cone": inputs.cone3d(6, 1.0, 8, 10, 1.6, 20.0, 40.0, m=2, bz=2),
+    }
+
+
+def dense_clip(geom):
+    """A by the closed-form clip of every (ray, voxel) pair."""
+    org, dirn, div = rays.rays(geom)
+    D = 3 if geom.is3d else 2
+    org, dirn = org[:, :D], dirn[:, :D]
+    M, N = len(org), geom.n_vox
+    iz, iy, ix = np.meshgrid(np.arange(geom.nz), np.arange(geom.ny), np.arange(geom.nx), indexing="ij")
+    lo3 = np.stack([geom.ox + ix.ravel() * geom.vx, geom.oy + iy.ravel() * geom.vy,
+                    geom.oz + iz.ravel() * geom.vz], 1)[:, :D]
+    h = np.array([geom.vx, geom.vy, geom.vz])[:D]
+    ri = np.repeat(np.arange(M), N)
+    vj = np.tile(np.arange(N), M)
+    L = siddon.clip_length(org[ri], dirn[ri], div, lo3[vj], lo3[vj] + h)
+    return L.reshape(M, N)
+
+
+@pytest.mark.parametrize("name", ["par2d", "fan_flat", "fan_curved", "cone"])
+def test_siddon_matches_pairwise_clip(name):
+    g = tiny_geoms()[name]
+    A = siddon.system_matrix(g).toarray()
+    C = dense_clip(g)
+    C[C <= 1e-12] = 0.0
+    assert A.shape == C.shape
+    assert np.count_nonzero(A) > 0.2 * A.shape[0]
+    np.testing.assert_allclose(A, C, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["par2d", "fan_flat", "fan_curved", "cone"])
+def test_row_sums_equal_chord_through_volume(name):
+    g = tiny_geoms()[name]
+    A = siddon.system_matrix(g)
+    org, dirn, div = rays.rays(g)
+    D = 3 if g.is3d else 2
+    lo = np.array([g.ox, g.oy, g.oz])[:D]
+    hi = lo + np.array([g.nx * g.vx, g.ny * g.vy, g.nz * g.vz])[:D]
+    K = len(org)
+    chord = siddon.clip_length(org[:, :D], dirn[:, :D], div, np.tile(lo, (K, 1)), np.tile(hi, (K, 1)))
+    np.testing.assert_allclose(np.asarray(A.sum(axis=1)).ravel(), chord, rtol=1e-12, atol=1e-12)
+
+
+def test_axis_aligned_rows_config_c1():
+    """At 0 and 90 degrees the C1 bins pass through pixel centres: each ray
+    that meets the image has exactly 64 entries of 1 mm in one column / row."""
+    g = inputs.config_c1()
+    A = siddon.system_matrix(g)
+    nu = g.nu
+    for view, axis in ((0, "col"), (45, "row")):
+        for b in range(nu):
+            row = A.getrow(view * nu + b)
+            k = b - 16
+            if 0 <= k < 64:
+                expect = (np.arange(64) * 64 + k) if axis == "col" else (k * 64 + np.arange(64))
+                assert sorted(row.indices.tolist()) == sorted(expect.tolist()), (view, b)
+                np.testing.assert_allclose(row.data, 1.0, rtol=0, atol=1e-12)
+            else:
+                assert row.nnz == 0
+    x = inputs.phantom_for(g, 1, n_ell=10)
+    img = x.reshape(64, 64)
+    p = A @ x
+    np.testing.assert_allclose(p[16:80], img.sum(axis=0), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(p[45 * nu + 16:45 * nu + 80], img.sum(axis=1), rtol=1e-12, atol=1e-12)
+
+
+def _disk_error(n):
+    g = inputs.par2d(n, 64.0 / n, 8, 180.0, 90, 0.6, m=1, bx=1, by=1)
+    R, mu, cx, cy = 20.0, 0.7, 3.3, -2.1
+    ss = 8
+    off = (np.arange(ss) + 0.5) / ss
+    xs = g.ox + (np.arange(n)[:, None] + off[None, :]).ravel() * g.vx
+    X, Y = np.meshgrid(xs, xs, indexing="xy")
+    inside = ((X - cx) ** 2 + (Y - cy) ** 2 <= R * R).astype(float)
+    frac = inside.reshape(n, ss, n, ss).mean(axis=(1, 3))
+    x = mu * frac.ravel()
+    A = siddon.system_matrix(g)
+    p = A @ x
+    org, dirn, _ = rays.rays(g)
+    d = dirn[:, :2] / np.linalg.norm(dirn[:, :2], axis=1, keepdims=True)
+    q = org[:, :2] - np.array([cx, cy])
+    dist = q[:, 0] * d[:, 1] - q[:, 1] * d[:, 0]
+    ref = 2 * mu * np.sqrt(np.maximum(R * R - dist ** 2, 0.0))
+    return np.abs(p - ref).sum() / np.abs(ref).sum()
+
+
+def test_disk_projection_closed_form_first_order():
+    e128, e256 = _disk_error(128), _disk_error(256)
+    assert e256 < 1e-2
+    assert 1.4 < e128 / e256 < 3.0
+
+
+def _system(name):
+    g = tiny_geoms()[name]
+    return g, csgd.BlockSystem(siddon.system_matrix(g), g)
+
+
+@pytest.mark.parametrize("name", ["par2d", "cone"])
+def test_block_additivity(name):
+    g, S = _system(name)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0, 1, g.n_vox)
+    for I in range(g.m):
+        full = S.A[S.rows[I]] @ x
+        parts = sum(csgd.block_fwd(S, [I], J, x) for J in range(g.n))
+        np.testing.assert_allclose(parts, full, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["fan_curved", "cone"])
+def test_adjoint_against_pairwise_columns(name):
+    """<A x, r> with A from Siddon rows equals <x, A^T r> with A^T r built
+    from the independent clip columns."""
+    g, S = _system(name)
+    C = dense_clip(g)
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=g.n_vox)
+    r = rng.normal(size=g.n_rays)
+    lhs = float((S.A @ x) @ r)
+    rhs = float(x @ (C.T @ r))
+    assert abs(lhs - rhs) <= 1e-12 * (np.abs(S.A @ x) @ np.abs(r))
+
+
+def test_exact_line_search_orthogonality():
+    """beta = 1 on one block: the new partial residual is orthogonal to A g
+    (the defining condition of the step length, Eq. 10-11)."""
+    g, S = _system("fan_curved")
+    rng = np.random.default_rng(7)
+    y = rng.uniform(0, 2, g.n_rays)
+    st = csgd.State(S, y)
+    I, J = 1, 2
+    rows = S.rows[I]
+    r0 = st.r[rows].copy()
+    _, mu, _ = csgd.step_group(st, [I], J, 1.0)
+    AG = S.block(I, J).toarray()
+    gvec = AG.T @ r0
+    q = AG @ gvec
+    r1 = r0 - mu * q
+    assert mu > 0
+    assert abs(q @ r1) <= 1e-12 * np.linalg.norm(q) * np.linalg.norm(r0)
+
+
+def test_residual_update_identity():
+    """Eq. 13: after one update from an exact residual,
+    y_I - A_I x^{n+1} = r_I^n - mu A_I^J g."""
+    g, S = _system("par2d")
+    rng = np.random.default_rng(11)
+    x0 = rng.uniform(0, 1, g.n_vox)
+    y = S.A @ rng.uniform(0, 1, g.n_vox)
+    st = csgd.State(S, y, x0=x0)
+    I, J = 0, 3
+    rows, vox = S.rows[I], S.vox[J]
+    r_before = st.r[rows].copy()
+    xnew, mu, _ = csgd.step_group(st, [I], J, 0.8)
+    x1 = x0.copy()
+    x1[vox] = xnew
+    AG = S.block(I, J).toarray()
+    gvec = AG.T @ r_before
+    lhs = y[rows] - S.A[rows] @ x1
+    np.testing.assert_allclose(lhs, r_before - mu * (AG @ gvec), rtol=1e-12, atol=1e-12)
+    # and the oracle's partial projections reproduce it
+    np.testing.assert_allclose(y[rows] - st.z[:, rows].sum(axis=0), lhs, rtol=1e-12, atol=1e-12)
+
+
+def test_one_block_is_relaxed_steepest_descent():
+    g = inputs.par2d(12, 1.0, 16, 180.0, 18, 0.8, m=1, bx=1, by=1)
+    S = csgd.BlockSystem(siddon.system_matrix(g), g)
+    rng = np.random.default_rng(13)
+    y = S.A @ rng.uniform(0, 1, g.n_vox) + rng.normal(0, 0.05, g.n_rays)
+    beta = 0.7
+    sched = sampler.full_sweep_schedule(1, 1, 12, beta)
+    st = csgd.State(S, y)
+    Ad = S.A.toarray()
+    x = np.zeros(g.n_vox)
+    for e in range(12):
+        csgd.epoch(st, sched, e)
+        r = y - Ad @ x
+        gvec = Ad.T @ r
+        mu = beta * (gvec @ gvec) / np.sum((Ad @ gvec) ** 2)
+        x = x + mu * gvec
+        np.testing.assert_allclose(st.x, x, rtol=1e-12, atol=1e-13)
+
+
+def test_one_block_converges_to_least_squares():
+    # 16 x 16 unknowns, 3600 rays: full column rank, condition number ~7.4,
+    # so exact-line-search steepest descent needs a few hundred steps for 1e-8
+    g = inputs.par2d(16, 1.0, 90, 180.0, 40, 0.5, m=1, bx=1, by=1)
+    S = csgd.BlockSystem(siddon.system_matrix(g), g)
+    rng = np.random.default_rng(17)
+    y = S.A @ rng.uniform(0, 1, g.n_vox) + rng.normal(0, 0.1, g.n_rays)
+    x_ls = np.linalg.lstsq(S.A.toarray(), y, rcond=None)[0]
+    st = csgd.run(S, y, sampler.full_sweep_schedule(1, 1, 800, 1.0))
+    assert np.linalg.norm(st.x - x_ls) / np.linalg.norm(x_ls) < 1e-8
+
+
+def test_consistent_solution_is_fixed_point_and_attractor():
+    g, S = _system("par2d")
+    rng = np.random.default_rng(19)
+    xt = rng.uniform(0, 1, g.n_vox)
+    y = S.A @ xt
+    sched = sampler.make_schedule(sampler.density(S.nnz_table(0.0)), 30, 0.67, 1.0, 1, 1.5, 5)
+    st = csgd.run(S, y, sched, epochs=3, x0=xt)
+    np.testing.assert_allclose(st.x, xt, rtol=1e-12, atol=1e-12)
+    st = csgd.run(S, y, sched)
+    res = [csgd.true_rel_residual(S, y, np.zeros(g.n_vox))]
+    assert csgd.true_rel_residual(S, y, st.x) < 0.05 * res[0]
+
+
+def test_unscheduled_blocks_untouched():
+    g, S = _system("par2d")
+    rng = np.random.default_rng(23)
+    y = S.A @ rng.uniform(0, 1, g.n_vox)
+    sched = sampler.make_schedule(sampler.density(S.nnz_table(0.0)), 1, 1.0, 0.5, 1, 1.0, 9)
+    st = csgd.State(S, y, x0=rng.uniform(0, 1, g.n_vox))
+    x_before = st.x.copy()
+    csgd.epoch(st, sched, 0)
+    used = set(int(J) for J in sched.cols)
+    assert len(used) == 2
+    for J in range(g.n):
+        if J not in used:
+            assert np.array_equal(st.x[S.vox[J]], x_before[S.vox[J]])
+        else:
+            assert not np.array_equal(st.x[S.vox[J]], x_before[S.vox[J]])
+
+
+# ----------------------------------------------------------------------------
+# sampler
+# ----------------------------------------------------------------------------
+def test_splitmix64_reference_values():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "splitmix64_seed0.txt")
+    vals = [int(l, 16) for l in open(path) if l.strip() and not l.startswith("#")]
+    assert [sampler.splitmix64(0, k) for k in range(len(vals))] == vals
+
+
+def test_first_draw_frequencies_follow_density():
+    P = np.array([[0.1], [0.2], [0.3], [0.4], [0.0]])
+    sched = sampler.make_schedule(P, 20000, 0.2, 1.0, 1, 1.0, 31)
+    first = sched.rbs[sched.group_rb_ptr[sched.col_group_ptr[:-1]]]
+    counts = np.bincount(first, minlength=5)
+    assert counts[4] == 0
+    _, p = scipy.stats.chisquare(counts[:4], 20000 * P[:4, 0])
+    assert p > 1e-3
+
+
+def test_draw_counts_groups_and_beta():
+    rng = np.random.default_rng(37)
+    nnz = rng.integers(1, 100, size=(10, 6))
+    nnz[2, :] = 0
+    nnz[:, 5] = 0
+    P = sampler.density(nnz)
+    s = sampler.make_schedule(P, 5, 0.55, 0.5, 3, 2.0, 41)
+    for e in range(5):
+        cols = s.cols[s.epoch_col_ptr[e]:s.epoch_col_ptr[e + 1]]
+        assert len(cols) == 3 and len(set(cols.tolist())) == 3
+        for J, groups in s.steps(e):
+            drawn = [I for G, _ in groups for I in G]
+            assert 2 not in drawn
+            if J == 5:
+                assert drawn == []
+                continue
+            assert len(drawn) == math.ceil(0.55 * 10) and len(set(drawn)) == len(drawn)
+            assert [len(G) for G, _ in groups] == [3, 3]
+            for G, b in groups:
+                assert b == pytest.approx(2.0 * sum(P[I, J] for I in G), rel=1e-15)
+
+
+def test_mixed_sampling_reaches_uniform_and_uniform_mode():
+    P = np.array([[0.7], [0.2], [0.1], [0.0]])
+    s = sampler.make_schedule(P, 6000, 0.25, 1.0, 1, 1.0, 43, sampler.MIXED, theta_step=1.0)
+    first = s.rbs[s.group_rb_ptr[s.col_group_ptr[:-1]]][1:]      # epochs >= 1: theta = 1
+    counts = np.bincount(first, minlength=4)
+    assert counts[3] == 0
+    _, p = scipy.stats.chisquare(counts[:3])
+    assert p > 1e-3
+    u = sampler.make_schedule(P, 4000, 0.25, 1.0, 1, 1.0, 47, sampler.UNIFORM)
+    cu = np.bincount(u.rbs, minlength=4)
+    assert cu[3] > 0
+    _, p = scipy.stats.chisquare(cu)
+    assert p > 1e-3
