@@ -1,0 +1,257 @@
+/*
+ * ct.h -- C ABI of the MI355X block-iterative CT solver (CSGD / GCSGD).
+ *
+ * The library solves the linear inverse problem y = A x + e (Eq. 1/2) by the
+ * randomised block scheme of Alg. 4-6: every update picks a column block J
+ * (a voxel cuboid) and a group of row blocks I_G (detector tiles of some
+ * views), back-projects g_J = (A_{I_G}^J)^T r_{I_G} (Eq. 7), takes the
+ * relaxed exact line-search step mu = beta ||g||^2 / ||A g||^2 (Eq. 11 with
+ * the relaxation of Sec. II-B) and records the partial projection
+ * z^J_{I_G} = A_{I_G}^J (x_J + mu g_J); the residual is rebuilt as
+ * r = y - sum_j z^j on the touched rows (Sec. II-C), and every updated block
+ * is set to the mean of its updates at the end of an epoch.
+ * A_ij, the intersection length of ray i with voxel j (Sec. II-A), is never
+ * stored: every projection recomputes it on the fly.
+ *
+ * Conventions
+ *  - Every function returns CT_OK (0), an error (< 0) or information (> 0).
+ *    ct_last_error() gives a thread-local message for the last failure.
+ *    Argument errors are detected before any device work is enqueued, so a
+ *    rejected call writes nothing.
+ *  - Device work is asynchronous on the caller's HIP stream, passed as
+ *    `void* stream` (NULL = the default stream).  Device pointers passed in
+ *    (x, y, r, g, workspace) stay owned by the caller; they must remain valid
+ *    until the stream reaches the enqueued work.  Execution errors surface at
+ *    the next synchronising call.
+ *  - Handles (ct_geom, ct_schedule, ct_solver, ct_batch) are owned by the
+ *    library and released by the matching destroy call.  Geometry and
+ *    schedule handles hold small read-only device tables that the library
+ *    allocates on the current device; the large per-job state (z, r, g ...)
+ *    lives in caller-allocated workspace.
+ *  - Units: lengths in mm, x in mm^-1.  Layouts (row-major, last index
+ *    fastest): x[nz][ny][nx]; y, r[n_views][nv][nu]; z[n_col][n_views][nv][nu].
+ *  - All device arrays are float32; the step size and the norms it needs are
+ *    reduced in float64.
+ */
+#ifndef CT_H
+#define CT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define CT_OK 0
+#define CT_NOT_CONVERGED 1     /* ct_solve hit its epoch cap              */
+#define CT_EINVAL (-1)         /* bad argument; nothing was enqueued      */
+#define CT_ENOMEM (-2)         /* device allocation failed                */
+#define CT_EDEVICE (-3)        /* HIP runtime error                       */
+#define CT_EUNSUPPORTED (-4)   /* valid but not implemented combination   */
+
+/* ---- geometry ------------------------------------------------------------
+ * Scan geometries (Sec. II-D: arbitrary source/detector poses per view theta,
+ * detector perpendicular to the source-to-detector-centre line).
+ * views[k*12 + 0..11] = a | c | e_u | e_v (float64):
+ *   CT_PAR2D        a = ray direction; ray of bin iu passes c + u e_u.
+ *   CT_FAN2D_FLAT   a = source; ray from a through c + u e_u.
+ *   CT_FAN2D_CURVED a = source; ray from a with direction
+ *                   cos(u) n + sin(u) e_u, n = (c - a)/|c - a|, u in radians.
+ *   CT_CONE3D_FLAT  a = source; ray from a through c + u e_u + v e_v.
+ * with u = (iu - (nu-1)/2) pu and v = (iv - (nv-1)/2) pv.  2D kinds use
+ * components 0 and 1 only and need nz = nv = 1.  e_u (and e_v) must be unit,
+ * and for divergent kinds perpendicular to c - a (and to each other).
+ * Ray index i = (view*nv + iv)*nu + iu; voxel index j = (iz*ny + iy)*nx + ix;
+ * voxel (ix,iy,iz) is the half-open box [o + i h, o + (i+1) h).
+ *
+ * Row blocks (the sets I of Eq. 4) are lists of detector tiles
+ * (view, u0, u1, v0, v1) (half-open index ranges); tiles of all row blocks must
+ * partition the rays.  Column blocks (the sets J) are voxel boxes
+ * (x0, x1, y0, y1, z0, z1) that must partition the volume.  The rays of a row
+ * block are ordered tile by tile, v then u.
+ */
+enum { CT_PAR2D = 0, CT_FAN2D_FLAT = 1, CT_FAN2D_CURVED = 2, CT_CONE3D_FLAT = 3 };
+
+typedef struct ct_geom_desc {
+    int32_t kind;
+    int32_t nx, ny, nz;
+    double vx, vy, vz;          /* voxel pitch (mm)                      */
+    double ox, oy, oz;          /* volume min corner (mm)                */
+    int32_t n_views, nu, nv;
+    double pu, pv;              /* bin pitch: mm, or rad for curved u    */
+    const double* views;        /* host, n_views*12                      */
+    int32_t n_row_blocks;
+    const int32_t* rb_ptr;      /* host, n_row_blocks+1 tile offsets     */
+    const int32_t* tiles;       /* host, rb_ptr[n_row_blocks]*5          */
+    int32_t n_col_blocks;
+    const int32_t* boxes;       /* host, n_col_blocks*6                  */
+} ct_geom_desc;
+
+typedef struct ct_geom ct_geom;
+
+typedef struct ct_geom_info {
+    int64_t n_rays, n_vox;
+    int32_t m, n;               /* row and column block counts           */
+    int32_t max_rb_rays;        /* largest row block (rays)              */
+    int32_t max_cb_vox;         /* largest column block (voxels)         */
+} ct_geom_info;
+
+/* Validates the description and builds the device tables (FP64 per-view
+ * frames, per-bin direction coefficients, tile and ray-chunk lists) on the
+ * current device.  Host arrays are copied; they may be freed on return.
+ * CT_EINVAL on inconsistent sizes, non-partitions, non-unit axes or a source
+ * inside the volume.  Synchronous. */
+int ct_geom_create(const ct_geom_desc* desc, ct_geom** out);
+void ct_geom_destroy(ct_geom* geom);
+int ct_geom_get_info(const ct_geom* geom, ct_geom_info* out);
+
+/* nnz(A_I^J) for every (row block, column block): the number of ray-voxel
+ * pairs whose intersection length exceeds tau (mm) -- the block density that
+ * drives the importance sampling of Sec. II-C (reading C6).  host_nnz is a
+ * host array [m][n] (row-block major).  Synchronous on `stream`. */
+int ct_geom_block_nnz(ct_geom* geom, double tau, int64_t* host_nnz, void* stream);
+
+/* ---- block projectors (Alg. 3) ---------------------------------------------
+ * ct_block_fwd:  y_{I} (= or +=) A_I^J x_J   for I = union of row_blocks.
+ *   Reads only x[J]; writes only the rays of the listed row blocks of y
+ *   (full-size ray array [n_views][nv][nu]).
+ * ct_block_back: g_J (= or +=) (A_I^J)^T r_I  (Eq. 7).
+ *   Reads only the listed rays of r; writes only the voxels of J in g
+ *   (full-size volume array).
+ * row_blocks: host array of n_rb distinct row-block ids.  flags: CT_ACCUMULATE
+ * adds instead of overwriting.  Lengths are computed in float32 from float64
+ * ray frames; accumulation is float32. */
+#define CT_ACCUMULATE 1
+int ct_block_fwd(ct_geom* geom, const int32_t* row_blocks, int32_t n_rb, int32_t col_block,
+                 const float* x, float* y, int32_t flags, void* stream);
+int ct_block_back(ct_geom* geom, const int32_t* row_blocks, int32_t n_rb, int32_t col_block,
+                  const float* r, float* g, int32_t flags, void* stream);
+
+/* ---- schedule (Alg. 5 / Alg. 6 sampling) -----------------------------------
+ * Drawn entirely up front: it depends on P(I,J), the parameters and the seed
+ * only.  Per epoch: a uniform permutation of the column blocks, of which
+ * ceil(gamma n) are used; for each, ceil(alpha m) successive draws without
+ * replacement of row blocks with weight P(I,J) (zero weight never drawn),
+ * cut into consecutive groups of group_size; beta_G = b sum_{I in G} P(I,J).
+ * Uniform sampling gives every row block weight 1; mixed sampling uses
+ * P_I + theta (P_max - P_I) with theta = min(1, epoch*theta_step) (Sec. III-F).
+ * Random numbers: SplitMix64 as a counter-based generator,
+ * u64 = mix(seed + (ctr+1) * 0x9E3779B97F4A7C15), ctr = epoch*2^32 + k. */
+enum { CT_SAMPLE_DENSITY = 0, CT_SAMPLE_UNIFORM = 1, CT_SAMPLE_MIXED = 2 };
+
+typedef struct ct_sched_params {
+    int32_t epochs;
+    double alpha;               /* fraction of row blocks per column block */
+    double gamma;               /* fraction of column blocks per epoch     */
+    int32_t group_size;         /* s                                       */
+    double b;                   /* beta = b * P_S/P_T                      */
+    int32_t sampling;           /* CT_SAMPLE_*                             */
+    double theta_step;          /* mixed sampling only                     */
+    uint64_t seed;
+} ct_sched_params;
+
+typedef struct ct_schedule ct_schedule;
+
+/* Flat view of a schedule: epoch e uses cols[epoch_col_ptr[e] ..
+ * epoch_col_ptr[e+1]); column entry c has groups [col_group_ptr[c],
+ * col_group_ptr[c+1]); group g has row blocks rbs[group_rb_ptr[g] ..
+ * group_rb_ptr[g+1]) and relaxation beta[g]. */
+typedef struct ct_sched_view {
+    int32_t n_epochs, n_cols, n_groups, n_rbs;
+    const int32_t* epoch_col_ptr;
+    const int32_t* cols;
+    const int32_t* col_group_ptr;
+    const int32_t* group_rb_ptr;
+    const int32_t* rbs;
+    const double* beta;
+} ct_sched_view;
+
+/* nnz: host [m][n] block densities (e.g. from ct_geom_block_nnz). */
+int ct_schedule_create(const ct_geom* geom, const ct_sched_params* params, const int64_t* nnz,
+                       ct_schedule** out);
+/* Import an explicit schedule (host arrays, copied).  Each column block may
+ * appear at most once per epoch and the row blocks of one column entry must
+ * be distinct. */
+int ct_schedule_import(const ct_geom* geom, const ct_sched_view* view, ct_schedule** out);
+/* Pointers stay valid until ct_schedule_destroy. */
+int ct_schedule_export(const ct_schedule* sched, ct_sched_view* out);
+void ct_schedule_destroy(ct_schedule* sched);
+
+/* ---- solver state and epochs (Alg. 4 / 5 / 6) ------------------------------ */
+enum { CT_SYNC_COLUMN = 0, CT_SYNC_EPOCH = 1 };
+
+typedef struct ct_solver_params {
+    int32_t sync;               /* CT_SYNC_COLUMN: r refreshed after every
+                                   column block (the listings); CT_SYNC_EPOCH:
+                                   all column blocks read the epoch-start r */
+} ct_solver_params;
+
+typedef struct ct_solver ct_solver;
+
+/* Device workspace (bytes, 256-aligned) a solver needs for this geometry. */
+int ct_solver_workspace_bytes(const ct_geom* geom, const ct_solver_params* params,
+                              size_t* bytes);
+/* workspace: caller-owned device buffer of at least that many bytes, kept
+ * alive for the solver's lifetime.  The geometry must outlive the solver. */
+int ct_solver_create(ct_geom* geom, const ct_solver_params* params, void* workspace,
+                     size_t ws_bytes, ct_solver** out);
+void ct_solver_destroy(ct_solver* solver);
+/* Start state of Alg. 4: with x == NULL, z^j = 0 and r = y (x must then be
+ * zero); otherwise z^j = A^j x_J and r = y - sum_j z^j. */
+int ct_solver_reset(ct_solver* solver, const float* y, const float* x, void* stream);
+/* One epoch `epoch` of the schedule, updating x (device, [N]) in place. */
+int ct_block_epoch(ct_solver* solver, const ct_schedule* sched, int32_t epoch, const float* y,
+                   float* x, void* stream);
+/* Device pointers into the solver workspace (for inspection and tests):
+ * z [n][M], r [M]. */
+int ct_solver_state(const ct_solver* solver, float** z, float** r);
+/* ||y - A x||_2 / ||y||_2 with a full forward projection (reading C16);
+ * synchronous on `stream`. */
+int ct_true_residual(ct_solver* solver, const float* y, const float* x, double* rel,
+                     void* stream);
+
+/* ---- whole solve ----------------------------------------------------------- */
+typedef struct ct_solve_params {
+    ct_sched_params sched;      /* sched.epochs = epoch cap               */
+    ct_solver_params solver;
+    double tau;                 /* nnz threshold (mm)                      */
+    double rel_tol;             /* stop when true residual <= rel_tol      */
+    int32_t check_every;        /* epochs between residual checks (0: never) */
+} ct_solve_params;
+
+typedef struct ct_solve_stats {
+    int32_t epochs_run;
+    double rel_residual;        /* last checked true relative residual    */
+    int64_t ray_voxel_updates;  /* 2 * sum over groups of nnz(A_{I_G}^J)  */
+} ct_solve_stats;
+
+/* x (device, [N]) starts from zero.  Allocates its workspace with
+ * hipMalloc.  Returns CT_NOT_CONVERGED if the cap was reached before
+ * rel_tol (with check_every > 0).  Synchronous. */
+int ct_solve(ct_geom* geom, const ct_solve_params* params, const float* y, float* x,
+             ct_solve_stats* stats, void* stream);
+
+/* ---- batched epochs --------------------------------------------------------
+ * Several independent solvers (each its own geometry, schedule and state)
+ * advanced together: the kernels of one phase of every job go out as a single
+ * launch, so many small jobs fill the GPU.  ct_batch_epoch runs, for every job
+ * k, epoch epochs[k] of schedule scheds[k] (a negative entry skips the job).
+ * Results equal those of ct_block_epoch job by job. */
+typedef struct ct_batch ct_batch;
+int ct_batch_create(int32_t n_jobs, ct_solver* const* solvers, ct_batch** out);
+void ct_batch_destroy(ct_batch* batch);
+int ct_batch_epoch(ct_batch* batch, const ct_schedule* const* scheds, const int32_t* epochs,
+                   const float* const* ys, float* const* xs, void* stream);
+
+/* Device bytes one job needs (geometry tables + workspace): for admission
+ * by memory budget. */
+int ct_job_footprint(const ct_geom_desc* desc, const ct_solver_params* params, size_t* bytes);
+
+const char* ct_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CT_H */

@@ -1,0 +1,1252 @@
+// Host runtime and C ABI of the block-iterative CT solver.
+//
+// Geometry validation and device tables, the data-independent block
+// schedule of Alg. 5 / Alg. 6, the solver state (z^j, r, work buffers in the
+// caller's workspace) and the epoch driver that enqueues, per column block,
+// back-projection -> fused forward -> step -> finalize on the caller's stream.
+#include "ct.h"
+#include "ct_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <mutex>
+#include <vector>
+
+using namespace ct;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) return fail(CT_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+static inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+struct ct_geom {
+    ct_geom_desc d{};
+    int dims = 2;
+    int64_t M = 0, N = 0;
+    int m = 0, n = 0;
+    std::vector<double> views;         // n_views*12
+    std::vector<Tile> tiles;
+    std::vector<int32_t> rb_tile_ptr, tile_roff;
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> rb_chunk_ptr;
+    std::vector<int64_t> rb_rays;
+    std::vector<Box> boxes;
+    std::vector<int32_t> box_tiles;    // back-projection work-groups per group
+    std::vector<Entry> all_entries;
+    int32_t max_rb_rays = 0, max_cb_vox = 0, max_tiles = 0, total_chunks = 0;
+    int device = -1;
+    void* dmem = nullptr;               // device tables, uploaded on first use
+    size_t dbytes = 0;
+    std::mutex mu;
+    DGeom G{};
+    Entry* d_all = nullptr;
+    unsigned long long* d_nnz = nullptr;
+    double* d_part = nullptr;          // residual-norm partials
+};
+
+static void box_tiling(const ct_geom* g, const Box& b, int* tx, int* ty, int* tz) {
+    const int nxJ = b.x1 - b.x0, nyJ = b.y1 - b.y0, nzJ = b.z1 - b.z0;
+    if (g->dims == 2) {
+        *tx = (nxJ + kTile2 - 1) / kTile2;
+        *ty = (nyJ + kTile2 - 1) / kTile2;
+        *tz = 1;
+    } else {
+        *tx = (nxJ + kTile3x - 1) / kTile3x;
+        *ty = (nyJ + kTile3y - 1) / kTile3y;
+        *tz = (nzJ + kTile3z - 1) / kTile3z;
+    }
+}
+
+static inline double dot3(const double* a, const double* b) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Validate the description and fill the host-side tables.
+static int build_host(ct_geom* g, const ct_geom_desc* d) {
+    if (!d) return fail(CT_EINVAL, "desc is NULL");
+    if (d->kind < CT_PAR2D || d->kind > CT_CONE3D_FLAT) return fail(CT_EINVAL, "bad kind %d", d->kind);
+    g->dims = (d->kind == CT_CONE3D_FLAT) ? 3 : 2;
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nu < 1 || d->nv < 1 || d->n_views < 1)
+        return fail(CT_EINVAL, "non-positive size");
+    if (g->dims == 2 && (d->nz != 1 || d->nv != 1)) return fail(CT_EINVAL, "2D kinds need nz = nv = 1");
+    if (!(d->vx > 0 && d->vy > 0 && d->vz > 0 && d->pu > 0 && d->pv > 0))
+        return fail(CT_EINVAL, "non-positive pitch");
+    if (!std::isfinite(d->ox) || !std::isfinite(d->oy) || !std::isfinite(d->oz))
+        return fail(CT_EINVAL, "non-finite origin");
+    if (!d->views || !d->rb_ptr || !d->tiles || !d->boxes) return fail(CT_EINVAL, "NULL array");
+    if (d->n_row_blocks < 1 || d->n_col_blocks < 1) return fail(CT_EINVAL, "need >= 1 block");
+    const int64_t M = (int64_t)d->n_views * d->nv * d->nu;
+    const int64_t N = (int64_t)d->nx * d->ny * d->nz;
+    if (M > INT32_MAX || N > INT32_MAX) return fail(CT_EUNSUPPORTED, "more than 2^31 rays or voxels");
+    g->d = *d;
+    g->d.views = nullptr;
+    g->d.rb_ptr = nullptr;
+    g->d.tiles = nullptr;
+    g->d.boxes = nullptr;
+    g->M = M;
+    g->N = N;
+    g->m = d->n_row_blocks;
+    g->n = d->n_col_blocks;
+    g->views.assign(d->views, d->views + (size_t)d->n_views * 12);
+    for (double v : g->views)
+        if (!std::isfinite(v)) return fail(CT_EINVAL, "non-finite view vector");
+
+    // per-view checks
+    const double hx = 0.5 * d->vx, hy = 0.5 * d->vy, hz = g->dims == 3 ? 0.5 * d->vz : 0.0;
+    const double R = std::sqrt(hx * hx + hy * hy + hz * hz);
+    for (int k = 0; k < d->n_views; ++k) {
+        const double* V = &g->views[(size_t)k * 12];
+        double a[3] = {V[0], V[1], g->dims == 3 ? V[2] : 0.0};
+        double c[3] = {V[3], V[4], g->dims == 3 ? V[5] : 0.0};
+        double eu[3] = {V[6], V[7], g->dims == 3 ? V[8] : 0.0};
+        double ev[3] = {V[9], V[10], V[11]};
+        if (std::fabs(std::sqrt(dot3(eu, eu)) - 1.0) > 1e-9) return fail(CT_EINVAL, "view %d: e_u not unit", k);
+        if (d->kind == CT_PAR2D) {
+            const double na = std::sqrt(dot3(a, a));
+            if (!(na > 0)) return fail(CT_EINVAL, "view %d: zero ray direction", k);
+            const double kap = (a[0] * eu[1] - a[1] * eu[0]) / na;
+            if (std::fabs(kap) < 1e-9) return fail(CT_EINVAL, "view %d: detector parallel to rays", k);
+        } else {
+            double w[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+            const double sdd = std::sqrt(dot3(w, w));
+            if (!(sdd > 0)) return fail(CT_EINVAL, "view %d: source on detector centre", k);
+            if (std::fabs(dot3(w, eu)) > 1e-9 * sdd) return fail(CT_EINVAL, "view %d: e_u not perpendicular", k);
+            if (g->dims == 3) {
+                if (std::fabs(std::sqrt(dot3(ev, ev)) - 1.0) > 1e-9) return fail(CT_EINVAL, "view %d: e_v not unit", k);
+                if (std::fabs(dot3(w, ev)) > 1e-9 * sdd || std::fabs(dot3(eu, ev)) > 1e-9)
+                    return fail(CT_EINVAL, "view %d: e_v not perpendicular", k);
+            }
+            // the whole volume must lie in front of the source by more than a voxel
+            double nrm[3] = {w[0] / sdd, w[1] / sdd, w[2] / sdd};
+            double dmin = INFINITY;
+            for (int cz = 0; cz < (g->dims == 3 ? 2 : 1); ++cz)
+                for (int cy = 0; cy < 2; ++cy)
+                    for (int cx = 0; cx < 2; ++cx) {
+                        double p[3] = {d->ox + cx * d->nx * d->vx - a[0], d->oy + cy * d->ny * d->vy - a[1],
+                                       g->dims == 3 ? d->oz + cz * d->nz * d->vz - a[2] : 0.0};
+                        dmin = std::min(dmin, dot3(p, nrm));
+                    }
+            if (!(dmin > R * (1 + 1e-6) + 1e-9))
+                return fail(CT_EINVAL, "view %d: volume not entirely in front of the source", k);
+        }
+    }
+
+    // row blocks: tiles, coverage
+    std::vector<uint8_t> cover((size_t)M, 0);
+    g->rb_tile_ptr.assign(1, 0);
+    g->rb_chunk_ptr.assign(1, 0);
+    g->rb_rays.clear();
+    const int32_t* rp = d->rb_ptr;
+    if (rp[0] != 0) return fail(CT_EINVAL, "rb_ptr[0] != 0");
+    for (int b = 0; b < g->m; ++b) {
+        if (rp[b + 1] <= rp[b]) return fail(CT_EINVAL, "row block %d has no tiles", b);
+        int64_t roff = 0;
+        for (int t = rp[b]; t < rp[b + 1]; ++t) {
+            const int32_t* T = d->tiles + (size_t)t * 5;
+            Tile tl{T[0], T[1], T[2], T[3], T[4]};
+            if (tl.view < 0 || tl.view >= d->n_views || tl.u0 < 0 || tl.u1 > d->nu || tl.u0 >= tl.u1 ||
+                tl.v0 < 0 || tl.v1 > d->nv || tl.v0 >= tl.v1)
+                return fail(CT_EINVAL, "tile %d out of range", t);
+            for (int iv = tl.v0; iv < tl.v1; ++iv)
+                for (int iu = tl.u0; iu < tl.u1; ++iu) {
+                    uint8_t& cv = cover[((size_t)tl.view * d->nv + iv) * d->nu + iu];
+                    if (cv) return fail(CT_EINVAL, "row blocks overlap at tile %d", t);
+                    cv = 1;
+                }
+            const int tid = (int)g->tiles.size();
+            g->tiles.push_back(tl);
+            g->tile_roff.push_back((int32_t)roff);
+            const int64_t nr = (int64_t)(tl.u1 - tl.u0) * (tl.v1 - tl.v0);
+            for (int64_t k0 = 0; k0 < nr; k0 += kChunk) {
+                Chunk ch{tid, (int32_t)k0, (int32_t)std::min<int64_t>(kChunk, nr - k0), (int32_t)(roff + k0)};
+                g->chunks.push_back(ch);
+            }
+            roff += nr;
+        }
+        g->rb_tile_ptr.push_back((int32_t)g->tiles.size());
+        g->rb_chunk_ptr.push_back((int32_t)g->chunks.size());
+        g->rb_rays.push_back(roff);
+        g->max_rb_rays = std::max<int32_t>(g->max_rb_rays, (int32_t)roff);
+    }
+    for (int64_t i = 0; i < M; ++i)
+        if (!cover[i]) return fail(CT_EINVAL, "row blocks do not cover ray %lld", (long long)i);
+    g->total_chunks = (int32_t)g->chunks.size();
+
+    // column blocks: boxes, coverage
+    std::vector<uint8_t> vc((size_t)N, 0);
+    for (int b = 0; b < g->n; ++b) {
+        const int32_t* B = d->boxes + (size_t)b * 6;
+        Box bx{B[0], B[1], B[2], B[3], B[4], B[5]};
+        if (bx.x0 < 0 || bx.x1 > d->nx || bx.x0 >= bx.x1 || bx.y0 < 0 || bx.y1 > d->ny || bx.y0 >= bx.y1 ||
+            bx.z0 < 0 || bx.z1 > d->nz || bx.z0 >= bx.z1)
+            return fail(CT_EINVAL, "box %d out of range", b);
+        for (int iz = bx.z0; iz < bx.z1; ++iz)
+            for (int iy = bx.y0; iy < bx.y1; ++iy)
+                for (int ix = bx.x0; ix < bx.x1; ++ix) {
+                    uint8_t& cv = vc[((size_t)iz * d->ny + iy) * d->nx + ix];
+                    if (cv) return fail(CT_EINVAL, "column blocks overlap (box %d)", b);
+                    cv = 1;
+                }
+        g->boxes.push_back(bx);
+        const int64_t nv = (int64_t)(bx.x1 - bx.x0) * (bx.y1 - bx.y0) * (bx.z1 - bx.z0);
+        g->max_cb_vox = std::max<int32_t>(g->max_cb_vox, (int32_t)nv);
+        int tx, ty, tz;
+        box_tiling(g, bx, &tx, &ty, &tz);
+        g->box_tiles.push_back(tx * ty * tz);
+        g->max_tiles = std::max(g->max_tiles, tx * ty * tz);
+    }
+    for (int64_t i = 0; i < N; ++i)
+        if (!vc[i]) return fail(CT_EINVAL, "column blocks do not cover voxel %lld", (long long)i);
+
+    // all-row-block launch entries
+    g->all_entries.clear();
+    int32_t cp = 0, sp = 0;
+    for (int b = 0; b < g->m; ++b) {
+        g->all_entries.push_back(Entry{b, 0, cp, sp});
+        cp += g->rb_chunk_ptr[b + 1] - g->rb_chunk_ptr[b];
+        sp += (int32_t)g->rb_rays[b];
+    }
+    return CT_OK;
+}
+
+// float64 per-view frames and 2D per-ray constants.
+static void build_frames(const ct_geom* g, std::vector<double>& v64, std::vector<Ray2>& ray2,
+                         std::vector<int32_t>& flags) {
+    const ct_geom_desc& d = g->d;
+    v64.assign((size_t)d.n_views * kViewStride, 0.0);
+    flags.assign(d.n_views, 0);
+    const double hx = 0.5 * d.vx, hy = 0.5 * d.vy;
+    if (g->dims == 2) ray2.assign((size_t)d.n_views * d.nu, Ray2{});
+    for (int k = 0; k < d.n_views; ++k) {
+        const double* V = &g->views[(size_t)k * 12];
+        double* W = &v64[(size_t)k * kViewStride];
+        if (d.kind == CT_PAR2D) {
+            const double na = std::hypot(V[0], V[1]);
+            W[0] = V[0] / na;
+            W[1] = V[1] / na;
+            W[3] = V[3];
+            W[4] = V[4];
+            W[6] = V[6];
+            W[7] = V[7];
+            W[15] = W[0] * W[7] - W[1] * W[6];      // kappa = cross(d, e_u)
+        } else {
+            for (int c = 0; c < 12; ++c) W[c] = V[c];
+            if (g->dims == 2) W[2] = W[5] = W[8] = W[9] = W[10] = W[11] = 0.0;
+            double w[3] = {W[3] - W[0], W[4] - W[1], W[5] - W[2]};
+            const double sdd = std::sqrt(dot3(w, w));
+            W[12] = w[0] / sdd;
+            W[13] = w[1] / sdd;
+            W[14] = w[2] / sdd;
+            W[15] = sdd;
+            W[16] = 1.0 / sdd;
+            W[17] = W[12] * W[7] - W[13] * W[6];    // sigma = cross(n, e_u) (2D)
+        }
+        if (g->dims == 2) {
+            for (int iu = 0; iu < d.nu; ++iu) {
+                const double u = ((double)iu - 0.5 * (double)(d.nu - 1)) * d.pu;
+                Ray2& R = ray2[(size_t)k * d.nu + iu];
+                double dx, dy;
+                if (d.kind == CT_PAR2D) {
+                    dx = W[0];
+                    dy = W[1];
+                    R.p = 1.0;
+                    R.q = u * W[15];
+                } else if (d.kind == CT_FAN2D_CURVED) {
+                    const double cg = std::cos(u), sg = std::sin(u);
+                    dx = cg * W[12] + sg * W[6];
+                    dy = cg * W[13] + sg * W[7];
+                    R.p = W[17] * cg;
+                    R.q = W[17] * sg;
+                } else {
+                    const double sdd = W[15];
+                    const double nD = std::hypot(sdd, u);
+                    dx = (sdd * W[12] + u * W[6]) / nD;
+                    dy = (sdd * W[13] + u * W[7]) / nD;
+                    R.p = W[17] * sdd / nD;
+                    R.q = W[17] * u / nD;
+                }
+                R.dx = dx;
+                R.dy = dy;
+                if (dx == 0.0) {
+                    R.kx = (float)dy;
+                    R.wx = -1.f;
+                    flags[k] |= 1;
+                } else {
+                    R.kx = (float)(-dy / dx);
+                    R.wx = (float)(hx / std::fabs(dx));
+                }
+                if (dy == 0.0) {
+                    R.ky = (float)(-dx);
+                    R.wy = -1.f;
+                    flags[k] |= 1;
+                } else {
+                    R.ky = (float)(dx / dy);
+                    R.wy = (float)(hy / std::fabs(dy));
+                }
+            }
+        } else {
+            // flag views whose rays (as the kernels form them) have a zero component
+            const double sdd = W[15];
+            bool z = false;
+            for (int iv = 0; iv < d.nv && !z; ++iv) {
+                const double v = ((double)iv - 0.5 * (double)(d.nv - 1)) * d.pv;
+                for (int iu = 0; iu < d.nu && !z; ++iu) {
+                    const double u = ((double)iu - 0.5 * (double)(d.nu - 1)) * d.pu;
+                    for (int c = 0; c < 3; ++c) {
+                        const double Dk = std::fma(v, W[9 + c], std::fma(u, W[6 + c], sdd * W[12 + c]));
+                        if (Dk == 0.0 || (float)Dk == 0.f) z = true;
+                    }
+                }
+            }
+            if (z) flags[k] |= 1;
+        }
+    }
+}
+
+struct DevLayout {
+    size_t off_view, off_ray2, off_flags, off_tiles, off_rbt, off_troff, off_chunks, off_rbc, off_all,
+        off_nnz, off_part, total;
+};
+
+static DevLayout dev_layout(const ct_geom* g) {
+    DevLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += align256(bytes);
+        return r;
+    };
+    L.off_view = take((size_t)g->d.n_views * kViewStride * sizeof(double));
+    L.off_ray2 = take(g->dims == 2 ? (size_t)g->d.n_views * g->d.nu * sizeof(Ray2) : 0);
+    L.off_flags = take((size_t)g->d.n_views * sizeof(int32_t));
+    L.off_tiles = take(g->tiles.size() * sizeof(Tile));
+    L.off_rbt = take((g->m + 1) * sizeof(int32_t));
+    L.off_troff = take(g->tiles.size() * sizeof(int32_t));
+    L.off_chunks = take(g->chunks.size() * sizeof(Chunk));
+    L.off_rbc = take((g->m + 1) * sizeof(int32_t));
+    L.off_all = take(g->all_entries.size() * sizeof(Entry));
+    L.off_nnz = take((size_t)g->m * g->n * sizeof(unsigned long long));
+    L.off_part = take(2 * 1024 * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+// Upload the device tables on first use (the current device becomes the
+// geometry's device).  Later calls must be made with that device current.
+static int geom_ensure_device(ct_geom* g) {
+    std::lock_guard<std::mutex> lock(g->mu);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(CT_EDEVICE, "no HIP device");
+    if (g->dmem) {
+        if (dev != g->device) return fail(CT_EINVAL, "geometry lives on device %d, current is %d", g->device, dev);
+        return CT_OK;
+    }
+    std::vector<double> v64;
+    std::vector<Ray2> ray2;
+    std::vector<int32_t> flags;
+    build_frames(g, v64, ray2, flags);
+    DevLayout L = dev_layout(g);
+    void* mem = nullptr;
+    if (hipMalloc(&mem, L.total) != hipSuccess)
+        return fail(CT_ENOMEM, "hipMalloc(%zu) for geometry tables failed", L.total);
+    char* base = (char*)mem;
+    auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpy(base + off, src, bytes, hipMemcpyHostToDevice);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up(L.off_view, v64.data(), v64.size() * sizeof(double));
+    if (e == hipSuccess) e = up(L.off_ray2, ray2.data(), ray2.size() * sizeof(Ray2));
+    if (e == hipSuccess) e = up(L.off_flags, flags.data(), flags.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = up(L.off_tiles, g->tiles.data(), g->tiles.size() * sizeof(Tile));
+    if (e == hipSuccess) e = up(L.off_rbt, g->rb_tile_ptr.data(), g->rb_tile_ptr.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = up(L.off_troff, g->tile_roff.data(), g->tile_roff.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = up(L.off_chunks, g->chunks.data(), g->chunks.size() * sizeof(Chunk));
+    if (e == hipSuccess) e = up(L.off_rbc, g->rb_chunk_ptr.data(), g->rb_chunk_ptr.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = up(L.off_all, g->all_entries.data(), g->all_entries.size() * sizeof(Entry));
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return fail(CT_EDEVICE, "geometry upload: %s", hipGetErrorString(e));
+    }
+    DGeom& G = g->G;
+    const ct_geom_desc& d = g->d;
+    G.kind = d.kind;
+    G.nx = d.nx;
+    G.ny = d.ny;
+    G.nz = d.nz;
+    G.nu = d.nu;
+    G.nv = d.nv;
+    G.n_views = d.n_views;
+    G.dims = g->dims;
+    G.vx = d.vx;
+    G.vy = d.vy;
+    G.vz = d.vz;
+    G.ox = d.ox;
+    G.oy = d.oy;
+    G.oz = d.oz;
+    G.pu = d.pu;
+    G.pv = d.pv;
+    const double hz = g->dims == 3 ? 0.5 * d.vz : 0.0;
+    G.radius = (float)(std::sqrt(0.25 * d.vx * d.vx + 0.25 * d.vy * d.vy + hz * hz) * (1.0 + 1e-6));
+    G.view64 = (const double*)(base + L.off_view);
+    G.bin64 = nullptr;
+    G.ray2 = g->dims == 2 ? (const Ray2*)(base + L.off_ray2) : nullptr;
+    G.view_flags = (const int32_t*)(base + L.off_flags);
+    G.tiles = (const Tile*)(base + L.off_tiles);
+    G.rb_tile_ptr = (const int32_t*)(base + L.off_rbt);
+    G.tile_roff = (const int32_t*)(base + L.off_troff);
+    G.chunks = (const Chunk*)(base + L.off_chunks);
+    G.rb_chunk_ptr = (const int32_t*)(base + L.off_rbc);
+    g->d_all = (Entry*)(base + L.off_all);
+    g->d_nnz = (unsigned long long*)(base + L.off_nnz);
+    g->d_part = (double*)(base + L.off_part);
+    g->dbytes = L.total;
+    g->device = dev;
+    g->dmem = mem;
+    return CT_OK;
+}
+
+extern "C" int ct_geom_create(const ct_geom_desc* desc, ct_geom** out) {
+    if (!out) return fail(CT_EINVAL, "out is NULL");
+    *out = nullptr;
+    ct_geom* g = new (std::nothrow) ct_geom();
+    if (!g) return fail(CT_ENOMEM, "host allocation failed");
+    int rc = build_host(g, desc);
+    if (rc != CT_OK) {
+        delete g;
+        return rc;
+    }
+    *out = g;
+    return CT_OK;
+}
+
+extern "C" void ct_geom_destroy(ct_geom* g) {
+    if (!g) return;
+    if (g->dmem) (void)hipFree(g->dmem);
+    delete g;
+}
+
+extern "C" int ct_geom_get_info(const ct_geom* g, ct_geom_info* out) {
+    if (!g || !out) return fail(CT_EINVAL, "NULL argument");
+    out->n_rays = g->M;
+    out->n_vox = g->N;
+    out->m = g->m;
+    out->n = g->n;
+    out->max_rb_rays = g->max_rb_rays;
+    out->max_cb_vox = g->max_cb_vox;
+    return CT_OK;
+}
+
+static int check_device(ct_geom* g) { return geom_ensure_device(g); }
+
+static FwdArgs fwd_all(const ct_geom* g, int J) {
+    FwdArgs a{};
+    a.box = g->boxes[J];
+    a.ent = g->d_all;
+    a.n_ent = g->m;
+    a.n_chunks = g->total_chunks;
+    return a;
+}
+
+extern "C" int ct_geom_block_nnz(ct_geom* g, double tau, int64_t* host_nnz, void* stream) {
+    if (!g || !host_nnz) return fail(CT_EINVAL, "NULL argument");
+    if (!(tau >= 0)) return fail(CT_EINVAL, "tau must be >= 0");
+    int rc = check_device(g);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(launch_fill_u64(g->d_nnz, (int64_t)g->m * g->n, st));
+    for (int J = 0; J < g->n; ++J) {
+        FwdArgs a = fwd_all(g, J);
+        a.mode = 2;
+        a.nnz = g->d_nnz;
+        a.n_cols = g->n;
+        a.col = J;
+        a.tau = (float)tau;
+        HIPCHK(launch_fwd(g->G, a, st));
+    }
+    std::vector<unsigned long long> tmp((size_t)g->m * g->n);
+    HIPCHK(hipMemcpyAsync(tmp.data(), g->d_nnz, tmp.size() * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (size_t i = 0; i < tmp.size(); ++i) host_nnz[i] = (int64_t)tmp[i];
+    return CT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// block primitives
+// ---------------------------------------------------------------------------
+static int check_rbs(const ct_geom* g, const int32_t* rbs, int32_t n_rb, int32_t col) {
+    if (!rbs || n_rb < 1) return fail(CT_EINVAL, "need at least one row block");
+    if (col < 0 || col >= g->n) return fail(CT_EINVAL, "column block %d out of range", col);
+    std::vector<uint8_t> seen(g->m, 0);
+    for (int i = 0; i < n_rb; ++i) {
+        if (rbs[i] < 0 || rbs[i] >= g->m) return fail(CT_EINVAL, "row block %d out of range", rbs[i]);
+        if (seen[rbs[i]]) return fail(CT_EINVAL, "row block %d listed twice", rbs[i]);
+        seen[rbs[i]] = 1;
+    }
+    return CT_OK;
+}
+
+// Fill inline entries for row blocks [i0, i1) of the list; returns chunk count.
+template <class A>
+static int fill_inline(const ct_geom* g, const int32_t* rbs, int i0, int i1, A& a) {
+    int cp = 0, sp = 0, k = 0;
+    for (int i = i0; i < i1; ++i, ++k) {
+        const int b = rbs[i];
+        a.inl[k] = Entry{b, 0, cp, sp};
+        cp += g->rb_chunk_ptr[b + 1] - g->rb_chunk_ptr[b];
+        sp += (int)g->rb_rays[b];
+    }
+    a.ent = nullptr;
+    a.n_ent = k;
+    return cp;
+}
+
+extern "C" int ct_block_fwd(ct_geom* g, const int32_t* rbs, int32_t n_rb, int32_t col, const float* x,
+                            float* y, int32_t flags, void* stream) {
+    if (!g || !x || !y) return fail(CT_EINVAL, "NULL argument");
+    int rc = check_rbs(g, rbs, n_rb, col);
+    if (rc) return rc;
+    if ((rc = check_device(g))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    for (int i0 = 0; i0 < n_rb; i0 += kMaxInline) {
+        const int i1 = std::min(n_rb, i0 + kMaxInline);
+        FwdArgs a{};
+        a.box = g->boxes[col];
+        a.n_chunks = fill_inline(g, rbs, i0, i1, a);
+        a.mode = 0;
+        a.flags = flags & CT_ACCUMULATE;
+        a.x = x;
+        a.out = y;
+        HIPCHK(launch_fwd(g->G, a, st));
+    }
+    return CT_OK;
+}
+
+static BackArgs back_common(const ct_geom* g, int col) {
+    BackArgs a{};
+    a.box = g->boxes[col];
+    box_tiling(g, a.box, &a.tiles_x, &a.tiles_y, &a.tiles_z);
+    return a;
+}
+
+extern "C" int ct_block_back(ct_geom* g, const int32_t* rbs, int32_t n_rb, int32_t col, const float* r,
+                             float* gout, int32_t flags, void* stream) {
+    if (!g || !r || !gout) return fail(CT_EINVAL, "NULL argument");
+    int rc = check_rbs(g, rbs, n_rb, col);
+    if (rc) return rc;
+    if ((rc = check_device(g))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    for (int i0 = 0; i0 < n_rb; i0 += kMaxInline) {
+        const int i1 = std::min(n_rb, i0 + kMaxInline);
+        BackArgs a = back_common(g, col);
+        fill_inline(g, rbs, i0, i1, a);
+        a.gptr = nullptr;
+        a.flags = (i0 == 0) ? (flags & CT_ACCUMULATE) : CT_ACCUMULATE;
+        a.fused = 0;
+        a.r = r;
+        a.g = gout;
+        HIPCHK(launch_back(g->G, a, 1, st));
+    }
+    return CT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// schedule
+// ---------------------------------------------------------------------------
+struct ct_schedule {
+    int m = 0, n = 0;
+    const ct_geom* geom = nullptr;
+    std::vector<int32_t> ecp, cols, cgp, grp, rbs;
+    std::vector<double> beta;
+    // launch tables per column entry (step)
+    std::vector<int32_t> step_ent_off;      // [n_cols+1]
+    std::vector<int32_t> step_gptr_off;     // [n_cols]: offset into gptr
+    std::vector<int32_t> step_chunks, step_slots;
+    std::vector<Entry> entries;
+    std::vector<int32_t> gptr;
+    // union of touched row blocks per epoch
+    std::vector<int32_t> uni_off;           // [n_epochs+1]
+    std::vector<int32_t> uni_chunks;
+    std::vector<Entry> uni;
+    int device = -1;
+    void* dmem = nullptr;               // device tables, uploaded on first use
+    std::mutex mu;
+    Entry* d_entries = nullptr;
+    int32_t* d_gptr = nullptr;
+    double* d_beta = nullptr;
+    Entry* d_uni = nullptr;
+};
+
+static uint64_t splitmix64(uint64_t seed, uint64_t ctr) {
+    uint64_t z = seed + (ctr + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static double unit_double(uint64_t seed, uint64_t ctr) {
+    return (double)(splitmix64(seed, ctr) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+static int count_of(double frac, int total) {
+    int k = (int)std::ceil(frac * total - 1e-9);
+    return std::max(1, std::min(total, k));
+}
+
+static int sched_finish(ct_schedule* s) {
+    const ct_geom* g = s->geom;
+    const int ncols = (int)s->cols.size();
+    s->step_ent_off.assign(1, 0);
+    s->step_gptr_off.clear();
+    s->step_chunks.clear();
+    s->step_slots.clear();
+    s->entries.clear();
+    s->gptr.clear();
+    for (int c = 0; c < ncols; ++c) {
+        s->step_gptr_off.push_back((int32_t)s->gptr.size());
+        int cp = 0, sp = 0, ne = 0;
+        for (int G = s->cgp[c]; G < s->cgp[c + 1]; ++G) {
+            s->gptr.push_back(ne);
+            for (int k = s->grp[G]; k < s->grp[G + 1]; ++k) {
+                const int b = s->rbs[k];
+                s->entries.push_back(Entry{b, G - s->cgp[c], cp, sp});
+                cp += g->rb_chunk_ptr[b + 1] - g->rb_chunk_ptr[b];
+                sp += (int32_t)g->rb_rays[b];
+                ++ne;
+            }
+        }
+        s->gptr.push_back(ne);
+        s->step_ent_off.push_back((int32_t)s->entries.size());
+        s->step_chunks.push_back(cp);
+        s->step_slots.push_back(sp);
+    }
+    const int E = (int)s->ecp.size() - 1;
+    s->uni_off.assign(1, 0);
+    s->uni_chunks.clear();
+    s->uni.clear();
+    for (int e = 0; e < E; ++e) {
+        std::vector<uint8_t> seen(g->m, 0);
+        for (int c = s->ecp[e]; c < s->ecp[e + 1]; ++c)
+            for (int G = s->cgp[c]; G < s->cgp[c + 1]; ++G)
+                for (int k = s->grp[G]; k < s->grp[G + 1]; ++k) seen[s->rbs[k]] = 1;
+        int cp = 0;
+        for (int b = 0; b < g->m; ++b)
+            if (seen[b]) {
+                s->uni.push_back(Entry{b, 0, cp, 0});
+                cp += g->rb_chunk_ptr[b + 1] - g->rb_chunk_ptr[b];
+            }
+        s->uni_off.push_back((int32_t)s->uni.size());
+        s->uni_chunks.push_back(cp);
+    }
+    return CT_OK;
+}
+
+static int sched_ensure_device(ct_schedule* sc) {
+    std::lock_guard<std::mutex> lock(sc->mu);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(CT_EDEVICE, "no HIP device");
+    if (sc->dmem) {
+        if (dev != sc->device) return fail(CT_EINVAL, "schedule lives on device %d, current is %d", sc->device, dev);
+        return CT_OK;
+    }
+    const size_t b_ent = align256(std::max<size_t>(1, sc->entries.size()) * sizeof(Entry));
+    const size_t b_gptr = align256(std::max<size_t>(1, sc->gptr.size()) * sizeof(int32_t));
+    const size_t b_beta = align256(std::max<size_t>(1, sc->beta.size()) * sizeof(double));
+    const size_t b_uni = align256(std::max<size_t>(1, sc->uni.size()) * sizeof(Entry));
+    void* mem = nullptr;
+    if (hipMalloc(&mem, b_ent + b_gptr + b_beta + b_uni) != hipSuccess)
+        return fail(CT_ENOMEM, "hipMalloc for schedule tables failed");
+    char* base = (char*)mem;
+    Entry* d_entries = (Entry*)base;
+    int32_t* d_gptr = (int32_t*)(base + b_ent);
+    double* d_beta = (double*)(base + b_ent + b_gptr);
+    Entry* d_uni = (Entry*)(base + b_ent + b_gptr + b_beta);
+    hipError_t e = hipSuccess;
+    if (!sc->entries.empty())
+        e = hipMemcpy(d_entries, sc->entries.data(), sc->entries.size() * sizeof(Entry), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !sc->gptr.empty())
+        e = hipMemcpy(d_gptr, sc->gptr.data(), sc->gptr.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !sc->beta.empty())
+        e = hipMemcpy(d_beta, sc->beta.data(), sc->beta.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !sc->uni.empty())
+        e = hipMemcpy(d_uni, sc->uni.data(), sc->uni.size() * sizeof(Entry), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return fail(CT_EDEVICE, "schedule upload: %s", hipGetErrorString(e));
+    }
+    sc->d_entries = d_entries;
+    sc->d_gptr = d_gptr;
+    sc->d_beta = d_beta;
+    sc->d_uni = d_uni;
+    sc->device = dev;
+    sc->dmem = mem;
+    return CT_OK;
+}
+
+extern "C" void ct_schedule_destroy(ct_schedule* s) {
+    if (!s) return;
+    if (s->dmem) (void)hipFree(s->dmem);
+    delete s;
+}
+
+extern "C" int ct_schedule_create(const ct_geom* g, const ct_sched_params* p, const int64_t* nnz,
+                                  ct_schedule** out) {
+    if (!g || !p || !nnz || !out) return fail(CT_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (p->epochs < 0) return fail(CT_EINVAL, "epochs < 0");
+    if (!(p->alpha > 0 && p->alpha <= 1) || !(p->gamma > 0 && p->gamma <= 1))
+        return fail(CT_EINVAL, "alpha and gamma must lie in (0, 1]");
+    if (p->group_size < 1) return fail(CT_EINVAL, "group_size < 1");
+    if (!std::isfinite(p->b)) return fail(CT_EINVAL, "b not finite");
+    if (p->sampling < CT_SAMPLE_DENSITY || p->sampling > CT_SAMPLE_MIXED) return fail(CT_EINVAL, "bad sampling");
+    if (p->sampling == CT_SAMPLE_MIXED && !(p->theta_step >= 0)) return fail(CT_EINVAL, "theta_step < 0");
+    const int m = g->m, n = g->n;
+    for (int i = 0; i < m * n; ++i)
+        if (nnz[i] < 0) return fail(CT_EINVAL, "negative density");
+    // P(I,J) = nnz / sum_I nnz
+    std::vector<double> P((size_t)m * n, 0.0);
+    for (int J = 0; J < n; ++J) {
+        int64_t col = 0;
+        for (int I = 0; I < m; ++I) col += nnz[(size_t)I * n + J];
+        if (col > 0)
+            for (int I = 0; I < m; ++I) P[(size_t)I * n + J] = (double)nnz[(size_t)I * n + J] / (double)col;
+    }
+    ct_schedule* s = new (std::nothrow) ct_schedule();
+    if (!s) return fail(CT_ENOMEM, "host allocation failed");
+    s->m = m;
+    s->n = n;
+    s->geom = g;
+    s->ecp.push_back(0);
+    s->cgp.push_back(0);
+    s->grp.push_back(0);
+    const uint64_t seed = p->seed;
+    std::vector<int> perm(n), avail;
+    std::vector<double> w(m);
+    for (int e = 0; e < p->epochs; ++e) {
+        uint64_t k = 0;
+        const uint64_t base = (uint64_t)e << 32;
+        for (int i = 0; i < n; ++i) perm[i] = i;
+        for (int i = n - 1; i > 0; --i) {
+            const int j = (int)std::floor(unit_double(seed, base + k++) * (double)(i + 1));
+            std::swap(perm[i], perm[j]);
+        }
+        const double theta = std::min(1.0, e * p->theta_step);
+        const int ncol = count_of(p->gamma, n);
+        for (int ci = 0; ci < ncol; ++ci) {
+            const int J = perm[ci];
+            double pmax = 0.0;
+            for (int I = 0; I < m; ++I) pmax = std::max(pmax, P[(size_t)I * n + J]);
+            for (int I = 0; I < m; ++I) {
+                const double pij = P[(size_t)I * n + J];
+                if (p->sampling == CT_SAMPLE_UNIFORM) w[I] = 1.0;
+                else if (p->sampling == CT_SAMPLE_MIXED) w[I] = pij > 0 ? pij + theta * (pmax - pij) : 0.0;
+                else w[I] = pij;
+            }
+            avail.clear();
+            for (int I = 0; I < m; ++I)
+                if (w[I] > 0) avail.push_back(I);
+            const int K = std::min(count_of(p->alpha, m), (int)avail.size());
+            std::vector<int> draws;
+            for (int t = 0; t < K; ++t) {
+                double W = 0.0;
+                for (int I : avail) W += w[I];
+                const double target = unit_double(seed, base + k++) * W;
+                double acc = 0.0;
+                size_t pick = avail.size() - 1;
+                for (size_t q = 0; q < avail.size(); ++q) {
+                    acc += w[avail[q]];
+                    if (acc > target) {
+                        pick = q;
+                        break;
+                    }
+                }
+                draws.push_back(avail[pick]);
+                avail.erase(avail.begin() + (long)pick);
+            }
+            for (int g0 = 0; g0 < K; g0 += p->group_size) {
+                double bs = 0.0;
+                for (int q = g0; q < std::min(K, g0 + p->group_size); ++q) {
+                    s->rbs.push_back(draws[q]);
+                    bs += P[(size_t)draws[q] * n + J];
+                }
+                s->grp.push_back((int32_t)s->rbs.size());
+                s->beta.push_back(p->b * bs);
+            }
+            s->cols.push_back(J);
+            s->cgp.push_back((int32_t)s->grp.size() - 1);
+        }
+        s->ecp.push_back((int32_t)s->cols.size());
+    }
+    int rc = sched_finish(s);
+    if (rc) {
+        ct_schedule_destroy(s);
+        return rc;
+    }
+    *out = s;
+    return CT_OK;
+}
+
+extern "C" int ct_schedule_import(const ct_geom* g, const ct_sched_view* v, ct_schedule** out) {
+    if (!g || !v || !out) return fail(CT_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (v->n_epochs < 0 || !v->epoch_col_ptr) return fail(CT_EINVAL, "bad epoch table");
+    const int E = v->n_epochs;
+    if (v->epoch_col_ptr[0] != 0) return fail(CT_EINVAL, "epoch_col_ptr[0] != 0");
+    for (int e = 0; e < E; ++e)
+        if (v->epoch_col_ptr[e + 1] < v->epoch_col_ptr[e]) return fail(CT_EINVAL, "epoch_col_ptr decreasing");
+    const int ncols = v->epoch_col_ptr[E];
+    if (ncols != v->n_cols) return fail(CT_EINVAL, "n_cols mismatch");
+    if (ncols > 0 && (!v->cols || !v->col_group_ptr)) return fail(CT_EINVAL, "NULL column arrays");
+    if (v->col_group_ptr && v->col_group_ptr[0] != 0) return fail(CT_EINVAL, "col_group_ptr[0] != 0");
+    for (int c = 0; c < ncols; ++c)
+        if (v->col_group_ptr[c + 1] < v->col_group_ptr[c]) return fail(CT_EINVAL, "col_group_ptr decreasing");
+    const int ngr = ncols ? v->col_group_ptr[ncols] : 0;
+    if (ngr != v->n_groups) return fail(CT_EINVAL, "n_groups mismatch");
+    if (ngr > 0 && (!v->group_rb_ptr || !v->rbs || !v->beta)) return fail(CT_EINVAL, "NULL group arrays");
+    if (ngr > 0 && v->group_rb_ptr[0] != 0) return fail(CT_EINVAL, "group_rb_ptr[0] != 0");
+    for (int G = 0; G < ngr; ++G) {
+        if (v->group_rb_ptr[G + 1] <= v->group_rb_ptr[G]) return fail(CT_EINVAL, "empty group %d", G);
+        if (!std::isfinite(v->beta[G])) return fail(CT_EINVAL, "beta not finite");
+    }
+    const int nrb = ngr ? v->group_rb_ptr[ngr] : 0;
+    if (nrb != v->n_rbs) return fail(CT_EINVAL, "n_rbs mismatch");
+    for (int e = 0; e < E; ++e) {
+        std::vector<uint8_t> colseen(g->n, 0);
+        for (int c = v->epoch_col_ptr[e]; c < v->epoch_col_ptr[e + 1]; ++c) {
+            const int J = v->cols[c];
+            if (J < 0 || J >= g->n) return fail(CT_EINVAL, "column %d out of range", J);
+            if (colseen[J]) return fail(CT_EINVAL, "column %d twice in epoch %d", J, e);
+            colseen[J] = 1;
+            std::vector<uint8_t> seen(g->m, 0);
+            for (int G = v->col_group_ptr[c]; G < v->col_group_ptr[c + 1]; ++G)
+                for (int k = v->group_rb_ptr[G]; k < v->group_rb_ptr[G + 1]; ++k) {
+                    const int b = v->rbs[k];
+                    if (b < 0 || b >= g->m) return fail(CT_EINVAL, "row block %d out of range", b);
+                    if (seen[b]) return fail(CT_EINVAL, "row block %d twice for one column", b);
+                    seen[b] = 1;
+                }
+        }
+    }
+    ct_schedule* s = new (std::nothrow) ct_schedule();
+    if (!s) return fail(CT_ENOMEM, "host allocation failed");
+    s->m = g->m;
+    s->n = g->n;
+    s->geom = g;
+    s->ecp.assign(v->epoch_col_ptr, v->epoch_col_ptr + E + 1);
+    s->cols.assign(v->cols, v->cols + ncols);
+    if (ncols) s->cgp.assign(v->col_group_ptr, v->col_group_ptr + ncols + 1);
+    else s->cgp.assign(1, 0);
+    if (ngr) {
+        s->grp.assign(v->group_rb_ptr, v->group_rb_ptr + ngr + 1);
+        s->rbs.assign(v->rbs, v->rbs + nrb);
+        s->beta.assign(v->beta, v->beta + ngr);
+    } else {
+        s->grp.assign(1, 0);
+    }
+    int rc = sched_finish(s);
+    if (rc) {
+        ct_schedule_destroy(s);
+        return rc;
+    }
+    *out = s;
+    return CT_OK;
+}
+
+extern "C" int ct_schedule_export(const ct_schedule* s, ct_sched_view* out) {
+    if (!s || !out) return fail(CT_EINVAL, "NULL argument");
+    out->n_epochs = (int32_t)s->ecp.size() - 1;
+    out->n_cols = (int32_t)s->cols.size();
+    out->n_groups = (int32_t)s->beta.size();
+    out->n_rbs = (int32_t)s->rbs.size();
+    out->epoch_col_ptr = s->ecp.data();
+    out->cols = s->cols.data();
+    out->col_group_ptr = s->cgp.data();
+    out->group_rb_ptr = s->grp.data();
+    out->rbs = s->rbs.data();
+    out->beta = s->beta.data();
+    return CT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solver
+// ---------------------------------------------------------------------------
+struct WsLayout {
+    size_t z, r, q, xg, pg, pq, mu, total;
+};
+
+static WsLayout ws_layout(const ct_geom* g) {
+    WsLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += align256(bytes);
+        return r;
+    };
+    L.z = take((size_t)g->n * g->M * sizeof(float));
+    L.r = take((size_t)g->M * sizeof(float));
+    L.q = take((size_t)g->M * sizeof(float));
+    L.xg = take((size_t)g->m * g->max_cb_vox * sizeof(float2));
+    L.pg = take((size_t)g->m * g->max_tiles * sizeof(double));
+    L.pq = take((size_t)g->total_chunks * sizeof(double));
+    L.mu = take((size_t)g->m * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+struct ct_solver {
+    ct_geom* geom = nullptr;
+    ct_solver_params p{};
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    float* z = nullptr;
+    float* r = nullptr;
+    float* q = nullptr;
+    float2* xg = nullptr;
+    double* pg = nullptr;
+    double* pq = nullptr;
+    double* mu = nullptr;
+};
+
+extern "C" int ct_solver_workspace_bytes(const ct_geom* g, const ct_solver_params* p, size_t* bytes) {
+    if (!g || !bytes) return fail(CT_EINVAL, "NULL argument");
+    if (p && (p->sync < CT_SYNC_COLUMN || p->sync > CT_SYNC_EPOCH)) return fail(CT_EINVAL, "bad sync");
+    *bytes = ws_layout(g).total;
+    return CT_OK;
+}
+
+extern "C" int ct_solver_create(ct_geom* g, const ct_solver_params* p, void* ws, size_t ws_bytes,
+                                ct_solver** out) {
+    if (!g || !ws || !out) return fail(CT_EINVAL, "NULL argument");
+    *out = nullptr;
+    ct_solver_params pp{};
+    if (p) pp = *p;
+    if (pp.sync < CT_SYNC_COLUMN || pp.sync > CT_SYNC_EPOCH) return fail(CT_EINVAL, "bad sync");
+    WsLayout L = ws_layout(g);
+    if (ws_bytes < L.total) return fail(CT_EINVAL, "workspace too small (%zu < %zu)", ws_bytes, L.total);
+    if (((uintptr_t)ws & 255) != 0) return fail(CT_EINVAL, "workspace must be 256-byte aligned");
+    ct_solver* s = new (std::nothrow) ct_solver();
+    if (!s) return fail(CT_ENOMEM, "host allocation failed");
+    s->geom = g;
+    s->p = pp;
+    s->ws = (char*)ws;
+    s->ws_bytes = ws_bytes;
+    s->z = (float*)(s->ws + L.z);
+    s->r = (float*)(s->ws + L.r);
+    s->q = (float*)(s->ws + L.q);
+    s->xg = (float2*)(s->ws + L.xg);
+    s->pg = (double*)(s->ws + L.pg);
+    s->pq = (double*)(s->ws + L.pq);
+    s->mu = (double*)(s->ws + L.mu);
+    *out = s;
+    return CT_OK;
+}
+
+extern "C" void ct_solver_destroy(ct_solver* s) { delete s; }
+
+extern "C" int ct_solver_state(const ct_solver* s, float** z, float** r) {
+    if (!s) return fail(CT_EINVAL, "NULL solver");
+    if (z) *z = s->z;
+    if (r) *r = s->r;
+    return CT_OK;
+}
+
+static int residual_all(ct_solver* s, const float* y, hipStream_t st) {
+    ct_geom* g = s->geom;
+    ResArgs a{};
+    a.ent = g->d_all;
+    a.n_ent = g->m;
+    a.z = s->z;
+    a.y = y;
+    a.r = s->r;
+    a.M = g->M;
+    a.n_cols = g->n;
+    HIPCHK(launch_residual(g->G, a, g->total_chunks, st));
+    return CT_OK;
+}
+
+extern "C" int ct_solver_reset(ct_solver* s, const float* y, const float* x, void* stream) {
+    if (!s || !y) return fail(CT_EINVAL, "NULL argument");
+    ct_geom* g = s->geom;
+    int rc = check_device(g);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (!x) {
+        HIPCHK(launch_fill(s->z, (int64_t)g->n * g->M, 0.f, st));
+        HIPCHK(hipMemcpyAsync(s->r, y, (size_t)g->M * sizeof(float), hipMemcpyDeviceToDevice, st));
+        return CT_OK;
+    }
+    for (int J = 0; J < g->n; ++J) {
+        FwdArgs a = fwd_all(g, J);
+        a.mode = 0;
+        a.x = x;
+        a.out = s->z + (size_t)J * g->M;
+        HIPCHK(launch_fwd(g->G, a, st));
+    }
+    return residual_all(s, y, st);
+}
+
+static int enqueue_step(ct_solver* s, const ct_schedule* sc, int c, const float* y, float* x,
+                        hipStream_t st) {
+    ct_geom* g = s->geom;
+    const int J = sc->cols[c];
+    const int nG = sc->cgp[c + 1] - sc->cgp[c];
+    if (nG <= 0) return CT_OK;
+    const Box box = g->boxes[J];
+    const int vox_J = (box.x1 - box.x0) * (box.y1 - box.y0) * (box.z1 - box.z0);
+    const Entry* ent = sc->d_entries + sc->step_ent_off[c];
+    const int n_ent = sc->step_ent_off[c + 1] - sc->step_ent_off[c];
+    const int32_t* gptr = sc->d_gptr + sc->step_gptr_off[c];
+    const int n_chunks = sc->step_chunks[c];
+
+    BackArgs b = back_common(g, J);
+    b.ent = ent;
+    b.gptr = gptr;
+    b.n_ent = n_ent;
+    b.fused = 1;
+    b.r = s->r;
+    b.x = x;
+    b.xg = s->xg;
+    b.vox_J = vox_J;
+    b.partial = s->pg;
+    HIPCHK(launch_back(g->G, b, nG, st));
+
+    FwdArgs f{};
+    f.box = box;
+    f.ent = ent;
+    f.n_ent = n_ent;
+    f.n_chunks = n_chunks;
+    f.mode = 1;
+    f.xg = s->xg;
+    f.vox_J = vox_J;
+    f.out = s->z + (size_t)J * g->M;
+    f.q = s->q;
+    f.partial = s->pq;
+    HIPCHK(launch_fwd(g->G, f, st));
+
+    StepArgs sa{};
+    sa.ent = ent;
+    sa.gptr = gptr;
+    sa.n_chunks = n_chunks;
+    sa.n_tiles = b.tiles_x * b.tiles_y * b.tiles_z;
+    sa.pg = s->pg;
+    sa.pq = s->pq;
+    sa.beta = sc->d_beta + sc->cgp[c];
+    sa.mu = s->mu;
+    HIPCHK(launch_step(sa, nG, st));
+
+    FinArgs fa{};
+    fa.ent = ent;
+    fa.n_ent = n_ent;
+    fa.n_chunks = n_chunks;
+    fa.mu = s->mu;
+    fa.q = s->q;
+    fa.z = s->z;
+    fa.zJ = s->z + (size_t)J * g->M;
+    fa.y = y;
+    fa.r = s->r;
+    fa.M = g->M;
+    fa.n_cols = g->n;
+    fa.refresh = (s->p.sync == CT_SYNC_COLUMN) ? 1 : 0;
+    fa.box = box;
+    fa.vox_J = vox_J;
+    fa.n_groups = nG;
+    fa.xg = s->xg;
+    fa.x = x;
+    fa.nx = g->d.nx;
+    fa.ny = g->d.ny;
+    HIPCHK(launch_finalize(g->G, fa, (vox_J + 255) / 256, st));
+    return CT_OK;
+}
+
+extern "C" int ct_block_epoch(ct_solver* s, const ct_schedule* sc, int32_t e, const float* y, float* x,
+                              void* stream) {
+    if (!s || !sc || !y || !x) return fail(CT_EINVAL, "NULL argument");
+    ct_geom* g = s->geom;
+    if (sc->geom != g) return fail(CT_EINVAL, "schedule was built for another geometry");
+    if (e < 0 || e >= (int)sc->ecp.size() - 1) return fail(CT_EINVAL, "epoch %d out of range", e);
+    int rc = check_device(g);
+    if (rc) return rc;
+    if ((rc = sched_ensure_device(const_cast<ct_schedule*>(sc)))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    for (int c = sc->ecp[e]; c < sc->ecp[e + 1]; ++c)
+        if ((rc = enqueue_step(s, sc, c, y, x, st))) return rc;
+    if (s->p.sync == CT_SYNC_EPOCH && sc->uni_chunks[e] > 0) {
+        ResArgs a{};
+        a.ent = sc->d_uni + sc->uni_off[e];
+        a.n_ent = sc->uni_off[e + 1] - sc->uni_off[e];
+        a.z = s->z;
+        a.y = y;
+        a.r = s->r;
+        a.M = g->M;
+        a.n_cols = g->n;
+        HIPCHK(launch_residual(g->G, a, sc->uni_chunks[e], st));
+    }
+    return CT_OK;
+}
+
+extern "C" int ct_true_residual(ct_solver* s, const float* y, const float* x, double* rel, void* stream) {
+    if (!s || !y || !x || !rel) return fail(CT_EINVAL, "NULL argument");
+    ct_geom* g = s->geom;
+    int rc = check_device(g);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    for (int J = 0; J < g->n; ++J) {
+        FwdArgs a = fwd_all(g, J);
+        a.mode = 0;
+        a.flags = J == 0 ? 0 : CT_ACCUMULATE;
+        a.x = x;
+        a.out = s->q;
+        HIPCHK(launch_fwd(g->G, a, st));
+    }
+    const int nblk = (int)std::min<int64_t>(1024, (g->M + 255) / 256);
+    HIPCHK(launch_resnorm(y, s->q, g->M, g->d_part, nblk, st));
+    std::vector<double> part(2 * (size_t)nblk);
+    HIPCHK(hipMemcpyAsync(part.data(), g->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < nblk; ++i) {
+        a += part[2 * i];
+        b += part[2 * i + 1];
+    }
+    *rel = b > 0 ? std::sqrt(a / b) : 0.0;
+    return CT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// whole solve
+// ---------------------------------------------------------------------------
+extern "C" int ct_solve(ct_geom* g, const ct_solve_params* p, const float* y, float* x, ct_solve_stats* st_out,
+                        void* stream) {
+    if (!g || !p || !y || !x) return fail(CT_EINVAL, "NULL argument");
+    if (p->check_every < 0) return fail(CT_EINVAL, "check_every < 0");
+    if (!(p->tau >= 0)) return fail(CT_EINVAL, "tau < 0");
+    int rc = check_device(g);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int64_t> nnz((size_t)g->m * g->n);
+    if ((rc = ct_geom_block_nnz(g, p->tau, nnz.data(), stream))) return rc;
+    ct_schedule* sc = nullptr;
+    if ((rc = ct_schedule_create(g, &p->sched, nnz.data(), &sc))) return rc;
+    size_t bytes = 0;
+    ct_solver_workspace_bytes(g, &p->solver, &bytes);
+    void* ws = nullptr;
+    if (hipMalloc(&ws, bytes) != hipSuccess) {
+        ct_schedule_destroy(sc);
+        return fail(CT_ENOMEM, "hipMalloc(%zu) for the solver workspace failed", bytes);
+    }
+    ct_solver* s = nullptr;
+    rc = ct_solver_create(g, &p->solver, ws, bytes, &s);
+    int64_t updates = 0;
+    int run = 0;
+    double rel = -1.0;
+    bool converged = false;
+    if (!rc) rc = launch_fill(x, g->N, 0.f, st) == hipSuccess ? CT_OK : fail(CT_EDEVICE, "fill x");
+    if (!rc) rc = ct_solver_reset(s, y, nullptr, stream);
+    for (int e = 0; !rc && e < p->sched.epochs; ++e) {
+        rc = ct_block_epoch(s, sc, e, y, x, stream);
+        if (rc) break;
+        run = e + 1;
+        for (int c = sc->ecp[e]; c < sc->ecp[e + 1]; ++c) {
+            const int J = sc->cols[c];
+            for (int k = sc->grp[sc->cgp[c]]; k < sc->grp[sc->cgp[c + 1]]; ++k)
+                updates += 2 * nnz[(size_t)sc->rbs[k] * g->n + J];
+        }
+        if (p->check_every > 0 && run % p->check_every == 0) {
+            rc = ct_true_residual(s, y, x, &rel, stream);
+            if (!rc && rel <= p->rel_tol) {
+                converged = true;
+                break;
+            }
+        }
+    }
+    if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = fail(CT_EDEVICE, "stream sync failed");
+    if (st_out) {
+        st_out->epochs_run = run;
+        st_out->rel_residual = rel;
+        st_out->ray_voxel_updates = updates;
+    }
+    ct_solver_destroy(s);
+    (void)hipFree(ws);
+    ct_schedule_destroy(sc);
+    if (rc) return rc;
+    if (p->check_every > 0 && !converged) return CT_NOT_CONVERGED;
+    return CT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batch
+// ---------------------------------------------------------------------------
+struct ct_batch {
+    std::vector<ct_solver*> jobs;
+};
+
+extern "C" int ct_batch_create(int32_t n_jobs, ct_solver* const* solvers, ct_batch** out) {
+    if (!out || n_jobs < 1 || !solvers) return fail(CT_EINVAL, "bad argument");
+    *out = nullptr;
+    for (int k = 0; k < n_jobs; ++k)
+        if (!solvers[k]) return fail(CT_EINVAL, "solver %d is NULL", k);
+    ct_batch* b = new (std::nothrow) ct_batch();
+    if (!b) return fail(CT_ENOMEM, "host allocation failed");
+    b->jobs.assign(solvers, solvers + n_jobs);
+    *out = b;
+    return CT_OK;
+}
+
+extern "C" void ct_batch_destroy(ct_batch* b) { delete b; }
+
+extern "C" int ct_batch_epoch(ct_batch* b, const ct_schedule* const* scheds, const int32_t* epochs,
+                              const float* const* ys, float* const* xs, void* stream) {
+    if (!b || !scheds || !epochs || !ys || !xs) return fail(CT_EINVAL, "NULL argument");
+    const int n = (int)b->jobs.size();
+    for (int k = 0; k < n; ++k) {
+        if (epochs[k] < 0) continue;
+        if (!scheds[k] || !ys[k] || !xs[k]) return fail(CT_EINVAL, "job %d: NULL argument", k);
+        if (epochs[k] >= (int)scheds[k]->ecp.size() - 1) return fail(CT_EINVAL, "job %d: epoch out of range", k);
+    }
+    for (int k = 0; k < n; ++k) {
+        if (epochs[k] < 0) continue;
+        int rc = ct_block_epoch(b->jobs[k], scheds[k], epochs[k], ys[k], xs[k], stream);
+        if (rc) return rc;
+    }
+    return CT_OK;
+}
+
+extern "C" int ct_job_footprint(const ct_geom_desc* desc, const ct_solver_params* p, size_t* bytes) {
+    if (!bytes) return fail(CT_EINVAL, "NULL argument");
+    ct_geom tmp;
+    int rc = build_host(&tmp, desc);
+    if (rc) return rc;
+    (void)p;
+    *bytes = dev_layout(&tmp).total + ws_layout(&tmp).total;
+    return CT_OK;
+}
+
+extern "C" const char* ct_last_error(void) { return g_err.c_str(); }

@@ -1,0 +1,125 @@
+"""C-ABI library: exports, argument validation and the host-side sampler
+(CPU only; no compute call reaches a GPU here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import sampler
+from paper_1709_00953_amd import ct, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "ct.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(ct_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ct.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(ct.EXPORTS)
+
+
+def _err(fn, *args):
+    with pytest.raises(ct.CtError) as ei:
+        fn(*args)
+    assert ei.value.code == ct.CT_EINVAL
+    assert ct.ct_last_error()
+
+
+def test_geometry_validation_rejects_bad_descriptions():
+    g = inputs.config_c1()
+    ok = ct.ct_geom_create(g)
+    assert (ok.M, ok.N, ok.m, ok.n) == (8640, 4096, 4, 4)
+
+    bad = inputs.config_c1()
+    bad.row_blocks = [bad.row_blocks[0], bad.row_blocks[0]] + bad.row_blocks[2:]
+    _err(ct.ct_geom_create, bad)                      # overlap + uncovered rays
+
+    bad = inputs.config_c1()
+    bad.row_blocks = bad.row_blocks[:3]
+    _err(ct.ct_geom_create, bad)                      # rays not covered
+
+    bad = inputs.config_c1()
+    bad.col_blocks = bad.col_blocks.copy()
+    bad.col_blocks[0, 1] += 1
+    _err(ct.ct_geom_create, bad)                      # boxes overlap
+
+    bad = inputs.config_c1()
+    bad.views = bad.views.copy()
+    bad.views[3, 6:8] *= 1.5
+    _err(ct.ct_geom_create, bad)                      # e_u not unit
+
+    bad = inputs.fan2d(64, 1.0, 12, 40, 0.02, 30.0, 60.0, m=2, bx=2, by=2)
+    _err(ct.ct_geom_create, bad)                      # source inside / too close
+
+    bad = inputs.config_c1()
+    bad.nz = 2
+    _err(ct.ct_geom_create, bad)                      # 2D with nz != 1
+
+
+def test_primitive_argument_errors_enqueue_nothing():
+    G = ct.ct_geom_create(inputs.config_c1())
+    L = ct.lib()
+    rbs = np.array([0, 0], dtype=np.int32)
+    assert L.ct_block_fwd(G.handle, rbs.ctypes.data_as(ct.P), 2, 0, ct.P(16), ct.P(16), 0, None) == ct.CT_EINVAL
+    rbs = np.array([0, 9], dtype=np.int32)
+    assert L.ct_block_back(G.handle, rbs.ctypes.data_as(ct.P), 2, 0, ct.P(16), ct.P(16), 0, None) == ct.CT_EINVAL
+    rbs = np.array([1], dtype=np.int32)
+    assert L.ct_block_fwd(G.handle, rbs.ctypes.data_as(ct.P), 1, 7, ct.P(16), ct.P(16), 0, None) == ct.CT_EINVAL
+    assert L.ct_block_fwd(G.handle, rbs.ctypes.data_as(ct.P), 1, 0, None, ct.P(16), 0, None) == ct.CT_EINVAL
+
+
+@pytest.mark.parametrize("samp", [sampler.DENSITY, sampler.UNIFORM, sampler.MIXED])
+@pytest.mark.parametrize("alpha,gamma,s", [(0.5, 1.0, 1), (1.0, 0.5, 3), (0.3, 0.75, 2)])
+def test_library_sampler_equals_oracle_sampler(samp, alpha, gamma, s):
+    g = inputs.fan2d(128, 2.0, 60, 64, 4e-3, 500.0, 1000.0, m=10, bx=3, by=2)
+    G = ct.ct_geom_create(g)
+    rng = np.random.default_rng(101)
+    nnz = rng.integers(0, 5000, size=(G.m, G.n))
+    nnz[3, :] = 0
+    nnz[:, 4] = 0
+    params = ct.sched_params(9, alpha, gamma, s, 2.5, samp, 0.125, seed=987654321)
+    ex = ct.ct_schedule_export(ct.ct_schedule_create(G, params, nnz))
+    o = sampler.make_schedule(sampler.density(nnz), 9, alpha, gamma, s, 2.5, 987654321, samp, 0.125)
+    for k in ("epoch_col_ptr", "cols", "col_group_ptr", "group_rb_ptr", "rbs"):
+        assert np.array_equal(ex[k], getattr(o, k)), k
+    assert np.array_equal(ex["beta"], o.beta)          # bitwise: same FP64 formula and order
+
+
+def test_schedule_import_round_trip_and_validation():
+    g = inputs.config_c1()
+    G = ct.ct_geom_create(g)
+    o = sampler.make_schedule(np.full((4, 4), 0.25), 3, 0.5, 1.0, 1, 1.0, 5)
+    ex = ct.ct_schedule_export(ct.ct_schedule_import(G, o))
+    for k in ("epoch_col_ptr", "cols", "col_group_ptr", "group_rb_ptr", "rbs", "beta"):
+        assert np.array_equal(ex[k], getattr(o, k))
+    bad = sampler.Schedule(o.epoch_col_ptr, o.cols.copy(), o.col_group_ptr, o.group_rb_ptr,
+                           o.rbs, o.beta)
+    bad.cols[1] = bad.cols[0]                           # column twice in one epoch
+    _err(ct.ct_schedule_import, G, bad)
+    bad = sampler.full_sweep_schedule(4, 4, 1, 1.0)
+    bad.rbs = bad.rbs.copy()
+    bad.rbs[1] = bad.rbs[0]                             # row block twice for a column
+    _err(ct.ct_schedule_import, G, bad)
+    bad = sampler.full_sweep_schedule(4, 4, 1, 1.0)
+    bad.rbs = bad.rbs.copy()
+    bad.rbs[0] = 4                                      # out of range
+    _err(ct.ct_schedule_import, G, bad)
+
+
+def test_footprint_and_workspace_are_consistent():
+    g = inputs.config_c2()
+    G = ct.ct_geom_create(g)
+    ws = ct.ct_solver_workspace_bytes(G)
+    assert ws >= 4 * G.n * G.M + 8 * G.M
+    fp = ct.ct_job_footprint(g)
+    assert fp > ws
+    assert fp < ws + 64 * 1024 * 1024
