@@ -98,11 +98,13 @@ typedef struct ct_geom_info {
     int32_t max_cb_vox;         /* largest column block (voxels)         */
 } ct_geom_info;
 
-/* Validates the description and builds the device tables (FP64 per-view
- * frames, per-bin direction coefficients, tile and ray-chunk lists) on the
- * current device.  Host arrays are copied; they may be freed on return.
- * CT_EINVAL on inconsistent sizes, non-partitions, non-unit axes or a source
- * inside the volume.  Synchronous. */
+/* Validates the description and copies it (host arrays may be freed on
+ * return).  The device tables (float64 per-view frames, per-ray 2D constants,
+ * tile and ray-chunk lists) are built on the first call that needs them, on
+ * the device current at that time; every later call on the geometry must run
+ * with that device current.  CT_EINVAL on inconsistent sizes, non-partitions,
+ * non-unit or non-perpendicular axes, or a volume not entirely in front of a
+ * source.  Host-only. */
 int ct_geom_create(const ct_geom_desc* desc, ct_geom** out);
 void ct_geom_destroy(ct_geom* geom);
 int ct_geom_get_info(const ct_geom* geom, ct_geom_info* out);
@@ -211,6 +213,19 @@ int ct_solver_state(const ct_solver* solver, float** z, float** r);
  * synchronous on `stream`. */
 int ct_true_residual(ct_solver* solver, const float* y, const float* x, double* rel,
                      void* stream);
+
+/* Kernel timing: while enabled, every kernel a solver enqueues is bracketed
+ * by HIP events on its stream (a small per-launch cost).  Reading syncs those
+ * events and returns, per kernel class, the summed device time (ms) and the
+ * launch count since the last read; reading resets the counters. */
+enum { CT_K_BACK = 0, CT_K_FWD = 1, CT_K_STEP = 2, CT_K_FINALIZE = 3, CT_K_RESIDUAL = 4,
+       CT_K_COUNT = 5 };
+typedef struct ct_kernel_times {
+    double ms[8];
+    int64_t launches[8];
+} ct_kernel_times;
+int ct_solver_profile(ct_solver* solver, int32_t enable);
+int ct_solver_profile_read(ct_solver* solver, ct_kernel_times* out);
 
 /* ---- whole solve ----------------------------------------------------------- */
 typedef struct ct_solve_params {

@@ -921,7 +921,15 @@ static WsLayout ws_layout(const ct_geom* g) {
     return L;
 }
 
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+};
+
 struct ct_solver {
+    bool prof = false;
+    std::vector<ProfRec> recs;          // recorded (kernel class, start, end)
+    std::vector<hipEvent_t> pool;       // idle events
     ct_geom* geom = nullptr;
     ct_solver_params p{};
     char* ws = nullptr;
@@ -969,7 +977,64 @@ extern "C" int ct_solver_create(ct_geom* g, const ct_solver_params* p, void* ws,
     return CT_OK;
 }
 
-extern "C" void ct_solver_destroy(ct_solver* s) { delete s; }
+static void prof_release(ct_solver* s) {
+    for (auto& r : s->recs) {
+        s->pool.push_back(r.a);
+        s->pool.push_back(r.b);
+    }
+    s->recs.clear();
+}
+
+extern "C" void ct_solver_destroy(ct_solver* s) {
+    if (!s) return;
+    prof_release(s);
+    for (hipEvent_t e : s->pool) (void)hipEventDestroy(e);
+    delete s;
+}
+
+static hipEvent_t prof_event(ct_solver* s) {
+    if (!s->pool.empty()) {
+        hipEvent_t e = s->pool.back();
+        s->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Enqueue `launch` on `st`, bracketed by events when profiling is on.
+template <class F>
+static hipError_t timed(ct_solver* s, int kind, hipStream_t st, F&& launch) {
+    if (!s->prof) return launch();
+    hipEvent_t a = prof_event(s), b = prof_event(s);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, st);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    s->recs.push_back(ProfRec{kind, a, b});
+    return e;
+}
+
+extern "C" int ct_solver_profile(ct_solver* s, int32_t enable) {
+    if (!s) return fail(CT_EINVAL, "NULL solver");
+    s->prof = enable != 0;
+    return CT_OK;
+}
+
+extern "C" int ct_solver_profile_read(ct_solver* s, ct_kernel_times* out) {
+    if (!s || !out) return fail(CT_EINVAL, "NULL argument");
+    std::memset(out, 0, sizeof *out);
+    for (auto& r : s->recs) {
+        HIPCHK(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+        out->ms[r.kind] += ms;
+        out->launches[r.kind] += 1;
+    }
+    prof_release(s);
+    return CT_OK;
+}
 
 extern "C" int ct_solver_state(const ct_solver* s, float** z, float** r) {
     if (!s) return fail(CT_EINVAL, "NULL solver");
@@ -1036,7 +1101,7 @@ static int enqueue_step(ct_solver* s, const ct_schedule* sc, int c, const float*
     b.xg = s->xg;
     b.vox_J = vox_J;
     b.partial = s->pg;
-    HIPCHK(launch_back(g->G, b, nG, st));
+    HIPCHK(timed(s, CT_K_BACK, st, [&] { return launch_back(g->G, b, nG, st); }));
 
     FwdArgs f{};
     f.box = box;
@@ -1049,7 +1114,7 @@ static int enqueue_step(ct_solver* s, const ct_schedule* sc, int c, const float*
     f.out = s->z + (size_t)J * g->M;
     f.q = s->q;
     f.partial = s->pq;
-    HIPCHK(launch_fwd(g->G, f, st));
+    HIPCHK(timed(s, CT_K_FWD, st, [&] { return launch_fwd(g->G, f, st); }));
 
     StepArgs sa{};
     sa.ent = ent;
@@ -1060,7 +1125,7 @@ static int enqueue_step(ct_solver* s, const ct_schedule* sc, int c, const float*
     sa.pq = s->pq;
     sa.beta = sc->d_beta + sc->cgp[c];
     sa.mu = s->mu;
-    HIPCHK(launch_step(sa, nG, st));
+    HIPCHK(timed(s, CT_K_STEP, st, [&] { return launch_step(sa, nG, st); }));
 
     FinArgs fa{};
     fa.ent = ent;
@@ -1082,7 +1147,7 @@ static int enqueue_step(ct_solver* s, const ct_schedule* sc, int c, const float*
     fa.x = x;
     fa.nx = g->d.nx;
     fa.ny = g->d.ny;
-    HIPCHK(launch_finalize(g->G, fa, (vox_J + 255) / 256, st));
+    HIPCHK(timed(s, CT_K_FINALIZE, st, [&] { return launch_finalize(g->G, fa, (vox_J + 255) / 256, st); }));
     return CT_OK;
 }
 
@@ -1107,7 +1172,8 @@ extern "C" int ct_block_epoch(ct_solver* s, const ct_schedule* sc, int32_t e, co
         a.r = s->r;
         a.M = g->M;
         a.n_cols = g->n;
-        HIPCHK(launch_residual(g->G, a, sc->uni_chunks[e], st));
+        const int nch = sc->uni_chunks[e];
+        HIPCHK(timed(s, CT_K_RESIDUAL, st, [&] { return launch_residual(g->G, a, nch, st); }));
     }
     return CT_OK;
 }

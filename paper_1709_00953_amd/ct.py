@@ -29,6 +29,7 @@ EXPORTS = (
     "ct_schedule_create", "ct_schedule_import", "ct_schedule_export", "ct_schedule_destroy",
     "ct_solver_workspace_bytes", "ct_solver_create", "ct_solver_destroy", "ct_solver_reset",
     "ct_block_epoch", "ct_solver_state", "ct_true_residual", "ct_solve",
+    "ct_solver_profile", "ct_solver_profile_read",
     "ct_batch_create", "ct_batch_destroy", "ct_batch_epoch", "ct_job_footprint",
     "ct_last_error",
 )
@@ -66,6 +67,13 @@ class ct_sched_view(ctypes.Structure):
     _fields_ = [("n_epochs", i32), ("n_cols", i32), ("n_groups", i32), ("n_rbs", i32),
                 ("epoch_col_ptr", P), ("cols", P), ("col_group_ptr", P),
                 ("group_rb_ptr", P), ("rbs", P), ("beta", P)]
+
+
+class ct_kernel_times(ctypes.Structure):
+    _fields_ = [("ms", f64 * 8), ("launches", i64 * 8)]
+
+
+KERNEL_NAMES = ("back", "fwd", "step", "finalize", "residual")
 
 
 class ct_solver_params(ctypes.Structure):
@@ -112,6 +120,8 @@ def lib():
             "ct_solver_state": [P, ctypes.POINTER(P), ctypes.POINTER(P)],
             "ct_true_residual": [P, P, P, ctypes.POINTER(f64), P],
             "ct_solve": [P, ctypes.POINTER(ct_solve_params), P, P, ctypes.POINTER(ct_solve_stats), P],
+            "ct_solver_profile": [P, i32],
+            "ct_solver_profile_read": [P, ctypes.POINTER(ct_kernel_times)],
             "ct_batch_create": [i32, P, ctypes.POINTER(P)],
             "ct_batch_destroy": [P],
             "ct_batch_epoch": [P, P, P, P, P, P],
@@ -366,6 +376,17 @@ def ct_true_residual(solver: Solver, y, x, stream=None) -> float:
     _check(lib().ct_true_residual(solver.handle, _dev(y, g.M, "y"), _dev(x, g.N, "x"),
                                   ctypes.byref(rel), _stream(stream)))
     return float(rel.value)
+
+
+def ct_solver_profile(solver: Solver, enable: bool = True):
+    _check(lib().ct_solver_profile(solver.handle, 1 if enable else 0))
+
+
+def ct_solver_profile_read(solver: Solver) -> dict:
+    """{kernel: (ms, launches)} since the last read (synchronises)."""
+    t = ct_kernel_times()
+    _check(lib().ct_solver_profile_read(solver.handle, ctypes.byref(t)))
+    return {name: (float(t.ms[k]), int(t.launches[k])) for k, name in enumerate(KERNEL_NAMES)}
 
 
 def ct_solve(geom: Geom, params: ct_sched_params, y, x, sync=CT_SYNC_COLUMN, tau=0.0,

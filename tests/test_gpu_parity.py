@@ -161,9 +161,9 @@ def _run_pair(ct, name, epochs, alpha, gamma, s, b, seed, sync="column",
 
 @pytest.mark.parametrize("case", [
     # name, epochs, alpha, gamma, s, b, seed, sync, sampling
-    ("c1_par2d", 50, 0.5, 1.0, 1, 4.0, 1000, "column", sampler.DENSITY),
+    ("c1_par2d", 50, 0.5, 1.0, 1, 0.5, 1000, "column", sampler.DENSITY),
     ("c1_par2d", 20, 1.0, 0.5, 2, 2.0, 1001, "column", sampler.DENSITY),
-    ("c1_par2d", 20, 0.75, 1.0, 1, 4.0, 1002, "epoch", sampler.UNIFORM),
+    ("c1_par2d", 20, 0.75, 1.0, 1, 1.0, 1002, "epoch", sampler.UNIFORM),
     ("fan_curved", 20, 0.5, 1.0, 1, 3.0, 2000, "column", sampler.DENSITY),
     ("fan_curved", 10, 1.0, 1.0, 3, 1.0, 2001, "column", sampler.MIXED),
     ("fan_flat", 12, 0.6, 1.0, 2, 2.0, 2100, "epoch", sampler.DENSITY),

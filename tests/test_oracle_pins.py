@@ -304,3 +304,18 @@ def test_mixed_sampling_reaches_uniform_and_uniform_mode():
     assert cu[3] > 0
     _, p = scipy.stats.chisquare(cu)
     assert p > 1e-3
+
+
+def test_large_relaxation_diverges_small_converges():
+    """Sec. III-A: beyond a range of b the iteration diverges, inside it the
+    residual falls (qualitative; the paper's own curves are not available)."""
+    g = inputs.config_c1()
+    S = csgd.BlockSystem(siddon.system_matrix(g), g)
+    x = inputs.phantom_for(g, 1000, n_ell=10)
+    y = inputs.gaussian_noise(S.A @ x, 0.01, 1000).astype(np.float64)
+    P = sampler.density(S.nnz_table(1e-5))
+    r0 = csgd.true_rel_residual(S, y, np.zeros(g.n_vox))
+    small = csgd.run(S, y, sampler.make_schedule(P, 20, 0.5, 1.0, 1, 0.5, 1000))
+    large = csgd.run(S, y, sampler.make_schedule(P, 20, 0.5, 1.0, 1, 8.0, 1000))
+    assert csgd.true_rel_residual(S, y, small.x) < 0.2 * r0
+    assert csgd.true_rel_residual(S, y, large.x) > 10 * r0
