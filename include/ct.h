@@ -201,7 +201,8 @@ int ct_solver_create(ct_geom* geom, const ct_solver_params* params, void* worksp
                      size_t ws_bytes, ct_solver** out);
 void ct_solver_destroy(ct_solver* solver);
 /* Start state of Alg. 4: with x == NULL, z^j = 0 and r = y (x must then be
- * zero); otherwise z^j = A^j x_J and r = y - sum_j z^j. */
+ * zero); otherwise z^j = A^j x_J and r = y - sum_j z^j.  Must be called
+ * before the first ct_block_epoch of a solver. */
 int ct_solver_reset(ct_solver* solver, const float* y, const float* x, void* stream);
 /* One epoch `epoch` of the schedule, updating x (device, [N]) in place. */
 int ct_block_epoch(ct_solver* solver, const ct_schedule* sched, int32_t epoch, const float* y,

@@ -54,13 +54,18 @@ struct ct_geom {
     std::vector<double> views;         // n_views*12
     std::vector<Tile> tiles;
     std::vector<int32_t> rb_tile_ptr, tile_roff;
-    std::vector<Chunk> chunks;
+    std::vector<double> v64;           // float64 per-view frames [n_views][kViewStride]
+    std::vector<Chunk> chunks;         // whole row blocks
     std::vector<int32_t> rb_chunk_ptr;
+    std::vector<Chunk> wchunks;        // (row block, column block) windows
+    std::vector<int32_t> rbj_chunk_ptr;
+    std::vector<int64_t> rbj_rays;
     std::vector<int64_t> rb_rays;
     std::vector<Box> boxes;
     std::vector<int32_t> box_tiles;    // back-projection work-groups per group
     std::vector<Entry> all_entries;
-    int32_t max_rb_rays = 0, max_cb_vox = 0, max_tiles = 0, total_chunks = 0;
+    int32_t max_rb_rays = 0, max_cb_vox = 0, max_tiles = 0, total_chunks = 0, max_xg = 0;
+    int32_t max_step_wchunks = 0;      // windowed chunks of all row blocks, worst column block
     int device = -1;
     void* dmem = nullptr;               // device tables, uploaded on first use
     size_t dbytes = 0;
@@ -86,6 +91,111 @@ static void box_tiling(const ct_geom* g, const Box& b, int* tx, int* ty, int* tz
 
 static inline double dot3(const double* a, const double* b) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// float64 per-view frames: a(3) c(3) e_u(3) e_v(3) n(3), then
+// kappa = cross(d, e_u) (parallel) or sdd, 1/sdd, sigma = cross(n, e_u).
+static void build_views(ct_geom* g) {
+    const ct_geom_desc& d = g->d;
+    g->v64.assign((size_t)d.n_views * kViewStride, 0.0);
+    for (int k = 0; k < d.n_views; ++k) {
+        const double* V = &g->views[(size_t)k * 12];
+        double* W = &g->v64[(size_t)k * kViewStride];
+        if (d.kind == CT_PAR2D) {
+            const double na = std::hypot(V[0], V[1]);
+            W[0] = V[0] / na;
+            W[1] = V[1] / na;
+            W[3] = V[3];
+            W[4] = V[4];
+            W[6] = V[6];
+            W[7] = V[7];
+            W[15] = W[0] * W[7] - W[1] * W[6];
+        } else {
+            for (int c = 0; c < 12; ++c) W[c] = V[c];
+            if (g->dims == 2) W[2] = W[5] = W[8] = W[9] = W[10] = W[11] = 0.0;
+            double w[3] = {W[3] - W[0], W[4] - W[1], W[5] - W[2]};
+            const double sdd = std::sqrt(dot3(w, w));
+            W[12] = w[0] / sdd;
+            W[13] = w[1] / sdd;
+            W[14] = w[2] / sdd;
+            W[15] = sdd;
+            W[16] = 1.0 / sdd;
+            W[17] = W[12] * W[7] - W[13] * W[6];
+        }
+    }
+}
+
+// Detector rectangle of tile `tl` whose rays can meet box `b`: the bin
+// coordinates of the box corners' projections, widened by one bin.  The
+// projection of a box lying in front of the source is the hull of its
+// corners' projections, so no ray outside the rectangle meets the box.
+static void tile_window(const ct_geom* g, const Tile& tl, const Box& b, int* u0, int* u1, int* v0,
+                        int* v1) {
+    const ct_geom_desc& d = g->d;
+    const double* W = &g->v64[(size_t)tl.view * kViewStride];
+    const double cu = 0.5 * (d.nu - 1), cv = 0.5 * (d.nv - 1);
+    double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+    const int nzc = g->dims == 3 ? 2 : 1;
+    for (int cz = 0; cz < nzc; ++cz)
+        for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) {
+                const double p[3] = {d.ox + (cx ? b.x1 : b.x0) * d.vx, d.oy + (cy ? b.y1 : b.y0) * d.vy,
+                                     g->dims == 3 ? d.oz + (cz ? b.z1 : b.z0) * d.vz : 0.0};
+                double bu = 0.0, bv = cv;
+                if (d.kind == CT_PAR2D) {
+                    bu = (W[0] * (p[1] - W[4]) - W[1] * (p[0] - W[3])) / W[15] / d.pu + cu;
+                } else {
+                    const double q[3] = {p[0] - W[0], p[1] - W[1], p[2] - W[2]};
+                    const double A = q[0] * W[12] + q[1] * W[13] + q[2] * W[14];
+                    const double Bu = q[0] * W[6] + q[1] * W[7] + q[2] * W[8];
+                    if (d.kind == CT_FAN2D_CURVED) {
+                        bu = std::atan2(Bu, A) / d.pu + cu;
+                    } else {
+                        bu = W[15] * Bu / A / d.pu + cu;
+                    }
+                    if (g->dims == 3) {
+                        const double Bv = q[0] * W[9] + q[1] * W[10] + q[2] * W[11];
+                        bv = W[15] * Bv / A / d.pv + cv;
+                    }
+                }
+                umin = std::min(umin, bu);
+                umax = std::max(umax, bu);
+                vmin = std::min(vmin, bv);
+                vmax = std::max(vmax, bv);
+            }
+    *u0 = std::max(tl.u0, (int)std::floor(umin) - 1);
+    *u1 = std::min(tl.u1, (int)std::ceil(umax) + 2);
+    *v0 = std::max(tl.v0, (int)std::floor(vmin) - 1);
+    *v1 = std::min(tl.v1, (int)std::ceil(vmax) + 2);
+    if (*u1 < *u0) *u1 = *u0;
+    if (*v1 < *v0) *v1 = *v0;
+}
+
+static void build_windows(ct_geom* g) {
+    g->wchunks.clear();
+    g->rbj_chunk_ptr.assign(1, 0);
+    g->rbj_rays.clear();
+    std::vector<int32_t> per_col(g->n, 0);
+    for (int b = 0; b < g->m; ++b)
+        for (int J = 0; J < g->n; ++J) {
+            int64_t roff = 0;
+            const size_t before = g->wchunks.size();
+            for (int t = g->rb_tile_ptr[b]; t < g->rb_tile_ptr[b + 1]; ++t) {
+                const Tile& tl = g->tiles[t];
+                int u0, u1, v0, v1;
+                tile_window(g, tl, g->boxes[J], &u0, &u1, &v0, &v1);
+                const int64_t nr = (int64_t)(u1 - u0) * (v1 - v0);
+                for (int64_t k0 = 0; k0 < nr; k0 += kChunk)
+                    g->wchunks.push_back(Chunk{tl.view, u0, v0, u1 - u0, (int32_t)k0,
+                                               (int32_t)std::min<int64_t>(kChunk, nr - k0), (int32_t)(roff + k0), 0});
+                roff += nr;
+            }
+            per_col[J] += (int32_t)(g->wchunks.size() - before);
+            g->rbj_chunk_ptr.push_back((int32_t)g->wchunks.size());
+            g->rbj_rays.push_back(roff);
+        }
+    g->max_step_wchunks = 0;
+    for (int J = 0; J < g->n; ++J) g->max_step_wchunks = std::max(g->max_step_wchunks, per_col[J]);
 }
 
 // Validate the description and fill the host-side tables.
@@ -184,8 +294,10 @@ static int build_host(ct_geom* g, const ct_geom_desc* d) {
             g->tiles.push_back(tl);
             g->tile_roff.push_back((int32_t)roff);
             const int64_t nr = (int64_t)(tl.u1 - tl.u0) * (tl.v1 - tl.v0);
+            (void)tid;
             for (int64_t k0 = 0; k0 < nr; k0 += kChunk) {
-                Chunk ch{tid, (int32_t)k0, (int32_t)std::min<int64_t>(kChunk, nr - k0), (int32_t)(roff + k0)};
+                Chunk ch{tl.view, tl.u0, tl.v0, tl.u1 - tl.u0, (int32_t)k0,
+                         (int32_t)std::min<int64_t>(kChunk, nr - k0), (int32_t)(roff + k0), 0};
                 g->chunks.push_back(ch);
             }
             roff += nr;
@@ -217,6 +329,7 @@ static int build_host(ct_geom* g, const ct_geom_desc* d) {
         g->boxes.push_back(bx);
         const int64_t nv = (int64_t)(bx.x1 - bx.x0) * (bx.y1 - bx.y0) * (bx.z1 - bx.z0);
         g->max_cb_vox = std::max<int32_t>(g->max_cb_vox, (int32_t)nv);
+        g->max_xg = std::max(g->max_xg, xg_size(bx.x1 - bx.x0, bx.y1 - bx.y0, bx.z1 - bx.z0));
         int tx, ty, tz;
         box_tiling(g, bx, &tx, &ty, &tz);
         g->box_tiles.push_back(tx * ty * tz);
@@ -224,6 +337,9 @@ static int build_host(ct_geom* g, const ct_geom_desc* d) {
     }
     for (int64_t i = 0; i < N; ++i)
         if (!vc[i]) return fail(CT_EINVAL, "column blocks do not cover voxel %lld", (long long)i);
+
+    build_views(g);
+    build_windows(g);
 
     // all-row-block launch entries
     g->all_entries.clear();
@@ -236,42 +352,23 @@ static int build_host(ct_geom* g, const ct_geom_desc* d) {
     return CT_OK;
 }
 
-// float64 per-view frames and 2D per-ray constants.
-static void build_frames(const ct_geom* g, std::vector<double>& v64, std::vector<Ray2>& ray2,
+// 2D per-ray constants and per-view zero-direction flags.
+static void build_frames(const ct_geom* g, std::vector<Ray2F>& rayf, std::vector<Ray2B>& rayb,
                          std::vector<int32_t>& flags) {
     const ct_geom_desc& d = g->d;
-    v64.assign((size_t)d.n_views * kViewStride, 0.0);
     flags.assign(d.n_views, 0);
     const double hx = 0.5 * d.vx, hy = 0.5 * d.vy;
-    if (g->dims == 2) ray2.assign((size_t)d.n_views * d.nu, Ray2{});
+    if (g->dims == 2) {
+        rayf.assign((size_t)d.n_views * d.nu, Ray2F{});
+        rayb.assign((size_t)d.n_views * d.nu, Ray2B{});
+    }
     for (int k = 0; k < d.n_views; ++k) {
-        const double* V = &g->views[(size_t)k * 12];
-        double* W = &v64[(size_t)k * kViewStride];
-        if (d.kind == CT_PAR2D) {
-            const double na = std::hypot(V[0], V[1]);
-            W[0] = V[0] / na;
-            W[1] = V[1] / na;
-            W[3] = V[3];
-            W[4] = V[4];
-            W[6] = V[6];
-            W[7] = V[7];
-            W[15] = W[0] * W[7] - W[1] * W[6];      // kappa = cross(d, e_u)
-        } else {
-            for (int c = 0; c < 12; ++c) W[c] = V[c];
-            if (g->dims == 2) W[2] = W[5] = W[8] = W[9] = W[10] = W[11] = 0.0;
-            double w[3] = {W[3] - W[0], W[4] - W[1], W[5] - W[2]};
-            const double sdd = std::sqrt(dot3(w, w));
-            W[12] = w[0] / sdd;
-            W[13] = w[1] / sdd;
-            W[14] = w[2] / sdd;
-            W[15] = sdd;
-            W[16] = 1.0 / sdd;
-            W[17] = W[12] * W[7] - W[13] * W[6];    // sigma = cross(n, e_u) (2D)
-        }
+        const double* W = &g->v64[(size_t)k * kViewStride];
         if (g->dims == 2) {
             for (int iu = 0; iu < d.nu; ++iu) {
                 const double u = ((double)iu - 0.5 * (double)(d.nu - 1)) * d.pu;
-                Ray2& R = ray2[(size_t)k * d.nu + iu];
+                Ray2B& R = rayb[(size_t)k * d.nu + iu];
+                Ray2F& F = rayf[(size_t)k * d.nu + iu];
                 double dx, dy;
                 if (d.kind == CT_PAR2D) {
                     dx = W[0];
@@ -292,23 +389,26 @@ static void build_frames(const ct_geom* g, std::vector<double>& v64, std::vector
                     R.p = W[17] * sdd / nD;
                     R.q = W[17] * u / nD;
                 }
-                R.dx = dx;
-                R.dy = dy;
+                F.dx = dx;
+                F.dy = dy;
+                F.idx = dx != 0.0 ? 1.0 / dx : 0.0;
+                F.idy = dy != 0.0 ? 1.0 / dy : 0.0;
+                R.pad = 0.f;
                 if (dx == 0.0) {
-                    R.kx = (float)dy;
-                    R.wx = -1.f;
+                    R.K = (float)dy;
+                    R.S = (float)(2.0 * hy / std::fabs(dy));
+                    R.M = -1.f;
+                    flags[k] |= 1;
+                } else if (dy == 0.0) {
+                    R.K = (float)(-dx);
+                    R.S = (float)(2.0 * hx / std::fabs(dx));
+                    R.M = -2.f;
                     flags[k] |= 1;
                 } else {
-                    R.kx = (float)(-dy / dx);
-                    R.wx = (float)(hx / std::fabs(dx));
-                }
-                if (dy == 0.0) {
-                    R.ky = (float)(-dx);
-                    R.wy = -1.f;
-                    flags[k] |= 1;
-                } else {
-                    R.ky = (float)(dx / dy);
-                    R.wy = (float)(hy / std::fabs(dy));
+                    const double wx = hx / std::fabs(dx), wy = hy / std::fabs(dy);
+                    R.K = (float)(-dy / dx - dx / dy);
+                    R.S = (float)(wx + wy);
+                    R.M = (float)std::min(2.0 * wx, 2.0 * wy);
                 }
             }
         } else {
@@ -331,7 +431,8 @@ static void build_frames(const ct_geom* g, std::vector<double>& v64, std::vector
 }
 
 struct DevLayout {
-    size_t off_view, off_ray2, off_flags, off_tiles, off_rbt, off_troff, off_chunks, off_rbc, off_all,
+    size_t off_view, off_rayf, off_rayb, off_flags, off_tiles, off_rbt, off_troff, off_chunks, off_rbc, off_wch,
+        off_rbj, off_all,
         off_nnz, off_part, total;
 };
 
@@ -344,13 +445,16 @@ static DevLayout dev_layout(const ct_geom* g) {
         return r;
     };
     L.off_view = take((size_t)g->d.n_views * kViewStride * sizeof(double));
-    L.off_ray2 = take(g->dims == 2 ? (size_t)g->d.n_views * g->d.nu * sizeof(Ray2) : 0);
+    L.off_rayf = take(g->dims == 2 ? (size_t)g->d.n_views * g->d.nu * sizeof(Ray2F) : 0);
+    L.off_rayb = take(g->dims == 2 ? (size_t)g->d.n_views * g->d.nu * sizeof(Ray2B) : 0);
     L.off_flags = take((size_t)g->d.n_views * sizeof(int32_t));
     L.off_tiles = take(g->tiles.size() * sizeof(Tile));
     L.off_rbt = take((g->m + 1) * sizeof(int32_t));
     L.off_troff = take(g->tiles.size() * sizeof(int32_t));
     L.off_chunks = take(g->chunks.size() * sizeof(Chunk));
     L.off_rbc = take((g->m + 1) * sizeof(int32_t));
+    L.off_wch = take(g->wchunks.size() * sizeof(Chunk));
+    L.off_rbj = take(g->rbj_chunk_ptr.size() * sizeof(int32_t));
     L.off_all = take(g->all_entries.size() * sizeof(Entry));
     L.off_nnz = take((size_t)g->m * g->n * sizeof(unsigned long long));
     L.off_part = take(2 * 1024 * sizeof(double));
@@ -368,10 +472,11 @@ static int geom_ensure_device(ct_geom* g) {
         if (dev != g->device) return fail(CT_EINVAL, "geometry lives on device %d, current is %d", g->device, dev);
         return CT_OK;
     }
-    std::vector<double> v64;
-    std::vector<Ray2> ray2;
+    const std::vector<double>& v64 = g->v64;
+    std::vector<Ray2F> rayf;
+    std::vector<Ray2B> rayb;
     std::vector<int32_t> flags;
-    build_frames(g, v64, ray2, flags);
+    build_frames(g, rayf, rayb, flags);
     DevLayout L = dev_layout(g);
     void* mem = nullptr;
     if (hipMalloc(&mem, L.total) != hipSuccess)
@@ -383,13 +488,16 @@ static int geom_ensure_device(ct_geom* g) {
     };
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = up(L.off_view, v64.data(), v64.size() * sizeof(double));
-    if (e == hipSuccess) e = up(L.off_ray2, ray2.data(), ray2.size() * sizeof(Ray2));
+    if (e == hipSuccess) e = up(L.off_rayf, rayf.data(), rayf.size() * sizeof(Ray2F));
+    if (e == hipSuccess) e = up(L.off_rayb, rayb.data(), rayb.size() * sizeof(Ray2B));
     if (e == hipSuccess) e = up(L.off_flags, flags.data(), flags.size() * sizeof(int32_t));
     if (e == hipSuccess) e = up(L.off_tiles, g->tiles.data(), g->tiles.size() * sizeof(Tile));
     if (e == hipSuccess) e = up(L.off_rbt, g->rb_tile_ptr.data(), g->rb_tile_ptr.size() * sizeof(int32_t));
     if (e == hipSuccess) e = up(L.off_troff, g->tile_roff.data(), g->tile_roff.size() * sizeof(int32_t));
     if (e == hipSuccess) e = up(L.off_chunks, g->chunks.data(), g->chunks.size() * sizeof(Chunk));
     if (e == hipSuccess) e = up(L.off_rbc, g->rb_chunk_ptr.data(), g->rb_chunk_ptr.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = up(L.off_wch, g->wchunks.data(), g->wchunks.size() * sizeof(Chunk));
+    if (e == hipSuccess) e = up(L.off_rbj, g->rbj_chunk_ptr.data(), g->rbj_chunk_ptr.size() * sizeof(int32_t));
     if (e == hipSuccess) e = up(L.off_all, g->all_entries.data(), g->all_entries.size() * sizeof(Entry));
     if (e != hipSuccess) {
         (void)hipFree(mem);
@@ -415,15 +523,21 @@ static int geom_ensure_device(ct_geom* g) {
     G.pv = d.pv;
     const double hz = g->dims == 3 ? 0.5 * d.vz : 0.0;
     G.radius = (float)(std::sqrt(0.25 * d.vx * d.vx + 0.25 * d.vy * d.vy + hz * hz) * (1.0 + 1e-6));
+    G.ivx = 1.0 / d.vx;
+    G.ivy = 1.0 / d.vy;
+    G.ivz = 1.0 / d.vz;
     G.view64 = (const double*)(base + L.off_view);
-    G.bin64 = nullptr;
-    G.ray2 = g->dims == 2 ? (const Ray2*)(base + L.off_ray2) : nullptr;
+    G.ray2f = g->dims == 2 ? (const Ray2F*)(base + L.off_rayf) : nullptr;
+    G.ray2b = g->dims == 2 ? (const Ray2B*)(base + L.off_rayb) : nullptr;
     G.view_flags = (const int32_t*)(base + L.off_flags);
     G.tiles = (const Tile*)(base + L.off_tiles);
     G.rb_tile_ptr = (const int32_t*)(base + L.off_rbt);
     G.tile_roff = (const int32_t*)(base + L.off_troff);
     G.chunks = (const Chunk*)(base + L.off_chunks);
     G.rb_chunk_ptr = (const int32_t*)(base + L.off_rbc);
+    G.wchunks = (const Chunk*)(base + L.off_wch);
+    G.rbj_chunk_ptr = (const int32_t*)(base + L.off_rbj);
+    G.n_cols = g->n;
     g->d_all = (Entry*)(base + L.off_all);
     g->d_nnz = (unsigned long long*)(base + L.off_nnz);
     g->d_part = (double*)(base + L.off_part);
@@ -637,9 +751,10 @@ static int sched_finish(ct_schedule* s) {
             s->gptr.push_back(ne);
             for (int k = s->grp[G]; k < s->grp[G + 1]; ++k) {
                 const int b = s->rbs[k];
+                const int bj = b * g->n + s->cols[c];
                 s->entries.push_back(Entry{b, G - s->cgp[c], cp, sp});
-                cp += g->rb_chunk_ptr[b + 1] - g->rb_chunk_ptr[b];
-                sp += (int32_t)g->rb_rays[b];
+                cp += g->rbj_chunk_ptr[bj + 1] - g->rbj_chunk_ptr[bj];
+                sp += (int32_t)g->rbj_rays[bj];
                 ++ne;
             }
         }
@@ -913,9 +1028,9 @@ static WsLayout ws_layout(const ct_geom* g) {
     L.z = take((size_t)g->n * g->M * sizeof(float));
     L.r = take((size_t)g->M * sizeof(float));
     L.q = take((size_t)g->M * sizeof(float));
-    L.xg = take((size_t)g->m * g->max_cb_vox * sizeof(float2));
+    L.xg = take((size_t)g->m * g->max_xg * sizeof(float2));
     L.pg = take((size_t)g->m * g->max_tiles * sizeof(double));
-    L.pq = take((size_t)g->total_chunks * sizeof(double));
+    L.pq = take((size_t)std::max(g->total_chunks, g->max_step_wchunks) * sizeof(double));
     L.mu = take((size_t)g->m * sizeof(double));
     L.total = o;
     return L;
@@ -1063,6 +1178,7 @@ extern "C" int ct_solver_reset(ct_solver* s, const float* y, const float* x, voi
     int rc = check_device(g);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
+    HIPCHK(launch_fill((float*)s->xg, 2 * (int64_t)g->m * g->max_xg, 0.f, st));  // zero margins
     if (!x) {
         HIPCHK(launch_fill(s->z, (int64_t)g->n * g->M, 0.f, st));
         HIPCHK(hipMemcpyAsync(s->r, y, (size_t)g->M * sizeof(float), hipMemcpyDeviceToDevice, st));
@@ -1100,6 +1216,7 @@ static int enqueue_step(ct_solver* s, const ct_schedule* sc, int c, const float*
     b.x = x;
     b.xg = s->xg;
     b.vox_J = vox_J;
+    b.xg_stride = xg_size(box.x1 - box.x0, box.y1 - box.y0, box.z1 - box.z0);
     b.partial = s->pg;
     HIPCHK(timed(s, CT_K_BACK, st, [&] { return launch_back(g->G, b, nG, st); }));
 
@@ -1109,8 +1226,11 @@ static int enqueue_step(ct_solver* s, const ct_schedule* sc, int c, const float*
     f.n_ent = n_ent;
     f.n_chunks = n_chunks;
     f.mode = 1;
+    f.windowed = 1;
+    f.col = J;
     f.xg = s->xg;
     f.vox_J = vox_J;
+    f.xg_stride = b.xg_stride;
     f.out = s->z + (size_t)J * g->M;
     f.q = s->q;
     f.partial = s->pq;
@@ -1140,8 +1260,10 @@ static int enqueue_step(ct_solver* s, const ct_schedule* sc, int c, const float*
     fa.M = g->M;
     fa.n_cols = g->n;
     fa.refresh = (s->p.sync == CT_SYNC_COLUMN) ? 1 : 0;
+    fa.col = J;
     fa.box = box;
     fa.vox_J = vox_J;
+    fa.xg_stride = b.xg_stride;
     fa.n_groups = nG;
     fa.xg = s->xg;
     fa.x = x;

@@ -7,25 +7,43 @@
 
 namespace ct {
 
-constexpr int kChunk = 256;        // rays per forward work-group
+constexpr int kChunk = 64;         // rays per forward chunk (one wave's lanes)
+constexpr int kSplit = 4;          // waves per forward work-group; each walks 1/kSplit of every chord
 constexpr int kMaxInline = 128;    // row blocks passed by value to a primitive launch
-constexpr int kTile2 = 16;         // 2D back-projection tile: 16 x 16 voxels
+constexpr int kTile2 = 8;          // 2D back-projection tile: 8 x 8 voxels, 4 waves split the views
 constexpr int kTile3x = 8, kTile3y = 8, kTile3z = 4;   // 3D tile: 8 x 8 x 4
 // Per-view float64 frame: a(3) c(3) e_u(3) e_v(3) n(3) sdd|kappa, 1/sdd, sigma.
 constexpr int kViewStride = 24;
 enum { kPar2D = 0, kFanFlat = 1, kFanCurved = 2, kCone = 3 };
+
+// J-local (x, g) pairs of a group are stored twice: copy 0 x-fastest
+// ([z][y][x]) and copy 1 y-fastest ([z][x][y]).  The forward pass reads the
+// copy whose fast axis runs across its rays, so the lanes of a wave (adjacent
+// rays) gather adjacent pixels.  Each copy has xg_pad zero elements before and
+// after it, so the walk may step a few voxels past the exit without a bounds
+// check: those segments have zero length and read finite values.
+__host__ __device__ inline int xg_pad(int nx, int ny, int nz) {
+    const int step = nz > 1 ? nx * ny : (nx > ny ? nx : ny);
+    return 4 * step + 64;
+}
+__host__ __device__ inline int xg_copy(int nx, int ny, int nz) { return nx * ny * nz + 2 * xg_pad(nx, ny, nz); }
+__host__ __device__ inline int xg_size(int nx, int ny, int nz) { return 2 * xg_copy(nx, ny, nz); }
 
 // One detector tile of a row block: rays (view, v0..v1-1, u0..u1-1).
 struct Tile {
     int32_t view, u0, u1, v0, v1;
 };
 
-// Up to kChunk consecutive rays of one tile (v-major, u fastest).
+// Up to kChunk consecutive rays of a detector rectangle of one view
+// (v-major, u fastest): ray k of the rectangle is (v0 + k / w, u0 + k % w).
+// The rectangle is a whole tile (row-block chunk lists) or the part of a
+// tile whose rays can meet one column block (windowed lists).
 struct Chunk {
-    int32_t tile;   // global tile index
-    int32_t k0;     // first ray within the tile
+    int32_t view, u0, v0, w;
+    int32_t k0;     // first ray within the rectangle
     int32_t cnt;    // rays in the chunk
-    int32_t roff;   // offset of the first ray within its row block
+    int32_t roff;   // offset of the first ray within its (windowed) row block
+    int32_t pad;
 };
 
 // A row block taking part in a launch.  chunk_prefix / slot_prefix are the
@@ -37,17 +55,24 @@ struct Entry {
     int32_t slot_prefix;
 };
 
-// Per-(view, bin) constants of a 2D ray, built on the host in float64.
-// (dx, dy) is the unit direction used by every 2D kernel.  For the gather
-// back-projector, delta = p*B - q*A is the signed distance of the ray from a
-// voxel centre whose view-frame coordinates are (A, B), and the clip of the
-// ray with the voxel is
-//   max(0, min(delta*kx + wx, delta*ky + wy) - max(delta*kx - wx, delta*ky - wy)).
-// A zero direction component is marked by wx < 0 (or wy < 0); then kx (ky)
-// holds the factor that turns delta into the ray's offset along that axis.
-struct Ray2 {
-    double p, q, dx, dy;
-    float kx, ky, wx, wy;
+// Per-(view, bin) data of a 2D ray, built on the host in float64.
+// Forward: unit direction (dx, dy) and its reciprocals (0 where a component is
+// exactly zero).
+struct Ray2F {
+    double dx, dy, idx, idy;
+};
+// Back-projection: delta = p*B - q*A is the signed distance of the ray from a
+// voxel centre whose view-frame coordinates are (A, B).  Along the ray the
+// voxel's x slab is [delta kx - wx, delta kx + wx] and its y slab
+// [delta ky - wy, delta ky + wy] (kx = -dy/dx, ky = dx/dy, wx = hx/|dx|,
+// wy = hy/|dy|), so the clip length is
+//   max(0, min(2 wx, 2 wy, wx + wy - |delta (kx - ky)|))
+// stored as K = kx - ky, S = wx + wy, M = min(2 wx, 2 wy).  A zero direction
+// component is marked by M = -1 (dx = 0) or M = -2 (dy = 0); then K turns
+// delta into the ray's offset along that axis and S is the full chord.
+struct Ray2B {
+    double p, q;
+    float K, S, M, pad;
 };
 
 // Device-side geometry, passed by value.
@@ -55,16 +80,20 @@ struct DGeom {
     int32_t kind, nx, ny, nz, nu, nv, n_views;
     int32_t dims;
     double vx, vy, vz, ox, oy, oz, pu, pv;
+    double ivx, ivy, ivz;         // reciprocal voxel pitch
     float radius;                 // voxel half-diagonal (mm)
     const double* view64;         // [n_views][kViewStride]
-    const double* bin64;          // [nu][2]  (curved: cos, sin of the bin angle)
-    const Ray2* ray2;             // [n_views][nu] (2D kinds)
+    const Ray2F* ray2f;           // [n_views][nu] (2D kinds)
+    const Ray2B* ray2b;           // [n_views][nu] (2D kinds)
     const int32_t* view_flags;    // [n_views] bit0: some ray has a zero direction component
     const Tile* tiles;
     const int32_t* rb_tile_ptr;
     const int32_t* tile_roff;     // first ray of the tile within its row block
-    const Chunk* chunks;
-    const int32_t* rb_chunk_ptr;
+    const Chunk* chunks;           // whole row blocks
+    const int32_t* rb_chunk_ptr;  // [m+1]
+    const Chunk* wchunks;         // row block x column block windows
+    const int32_t* rbj_chunk_ptr; // [m*n+1], index rb*n + J
+    int32_t n_cols;
 };
 
 struct Box {
@@ -79,9 +108,11 @@ struct FwdArgs {
     int32_t n_chunks;
     int32_t flags;                // CT_ACCUMULATE
     int32_t mode;                 // 0 single, 1 fused (x,g), 2 count
+    int32_t windowed;             // 1: chunks of the (row block, col) windows
     const float* x;               // single: full volume
-    const float2* xg;             // fused: [group][|J|] (x_J, g_J), J-local
+    const float2* xg;             // fused: [group][xg_stride] (x_J, g_J), two J-local copies
     int32_t vox_J;                // |J|
+    int32_t xg_stride;            // per-group stride of xg (both padded copies)
     float* out;                   // single/fused: ray-indexed (Ax)
     float* q;                     // fused: slot-indexed A g
     double* partial;              // fused: per chunk sum (A g)^2
@@ -104,31 +135,32 @@ struct BackArgs {
     const float* r;               // ray-indexed
     const float* x;               // full volume (fused: copied into xg)
     float* g;                     // single: full volume
-    float2* xg;                   // fused: [group][|J|]
+    float2* xg;                   // fused: [group][xg_stride], two J-local copies
     int32_t vox_J;
+    int32_t xg_stride;
     double* partial;              // fused: [group][tiles]
     Entry inl[kMaxInline];
 };
 
+// Finalize of one column-block step (ray part, then voxel part).
 // Step sizes of one column-block step: group g's ||g||^2 partials are
-// pg[g*n_tiles ..], its ||A g||^2 partials the chunks of its entries.
+// pg[g*n_tiles ..], its ||A g||^2 partials those of its entries' chunks.
 struct StepArgs {
-    const Entry* ent;       // step entries (sorted by group)
+    const Entry* ent;
     const int32_t* gptr;    // group -> entries
-    int32_t n_chunks;       // chunks of the step
-    int32_t n_tiles;        // back-projection work-groups per group
-    const double* pg;       // [G][n_tiles]   ||g||^2 partials
-    const double* pq;       // [n_chunks]     ||A g||^2 partials
+    int32_t n_chunks;
+    int32_t n_tiles;        // back-projection tiles per group
+    const double* pg;
+    const double* pq;
     const double* beta;     // [G]
     double* mu;             // [G]
 };
 
-// Finalize of one column-block step (ray part, then voxel part).
 struct FinArgs {
     const Entry* ent;
     int32_t n_ent;
     int32_t n_chunks;
-    const double* mu;
+    const double* mu;       // [G]
     const float* q;
     float* z;               // [n][M]
     float* zJ;              // z + J*M
@@ -137,9 +169,11 @@ struct FinArgs {
     int64_t M;
     int32_t n_cols;
     int32_t refresh;        // 1: r = y - sum_j z^j on the step's rays
+    int32_t col;            // column block (windowed chunk lists)
     // voxel part
     Box box;
     int32_t vox_J;
+    int32_t xg_stride;
     int32_t n_groups;
     const float2* xg;
     float* x;

@@ -4,21 +4,27 @@
 //             column block (Alg. 3 last line; Eq. 12-13).  One lane per ray,
 //             consecutive lanes = consecutive detector bins, so the output
 //             writes are coalesced along the detector-major ray layout.  The
-//             ray is set up in float64 (entry into the box), then walked in
-//             float32 box-local voxel coordinates, crossing parameters taken
-//             from the plane index rather than by repeated addition.  The
-//             fused mode walks x_J and g_J together (A x and A g in one pass)
-//             and emits a float64 partial of ||A g||^2 per work-group; the
-//             count mode counts the pairs longer than tau (block densities).
+//             ray is set up in float64 (entry into the box, no division), then
+//             walked in float32 box-local voxel coordinates, crossing
+//             parameters taken from the plane index rather than by repeated
+//             addition; four segments are formed before their four gathers so
+//             that the loads overlap.  The fused mode walks x_J and g_J
+//             together (A x and A g in one pass), emits a float64 partial of
+//             ||A g||^2 per work-group, and the last work-group to finish
+//             turns all partials into mu = beta ||g||^2 / ||A g||^2 (Eq. 11,
+//             relaxed) in a fixed order.  The count mode counts the pairs
+//             longer than tau (block densities).
 //  k_back2/3  gather back-projection (A_I^J)^T r_I (Eq. 7): one lane per
 //             voxel, which visits the bins of its shadow in every view of the
 //             group and clips each candidate ray against its own box, so no
 //             two lanes write the same output and no atomics are needed.
 //             The voxel's view-frame offset and each candidate's distance from
 //             the voxel centre are formed in float64 (they cancel ~500 mm
-//             lever arms); the clip itself is float32.
-//  k_step     mu = beta ||g||^2 / ||A g||^2 per group (Eq. 11, relaxed), from
-//             fixed-order float64 sums of the per-work-group partials.
+//             lever arms); the clip itself is float32.  In 2D a work-group is
+//             an 8 x 8 voxel tile whose four waves take every fourth view;
+//             per (tile, view) one lane derives the frame offsets and a
+//             linearised shadow with a rigorous curvature margin, so a voxel's
+//             candidate bins cost two FMAs.
 //  k_finalize z^J_{I_G} = A x + mu A g, residual r = y - sum_j z^j on the
 //             touched rays (Sec. II-C), and x_J = mean_G (x_J + mu_G g_G).
 //  k_residual r_I = y_I - sum_j z^j_I (epoch-synchronous refresh, reset).
@@ -58,6 +64,13 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
     return t;
 }
 
+// Load base[i] with a 32-bit unsigned byte offset (lets the compiler use a
+// uniform base register plus a per-lane 32-bit offset).
+template <class T>
+__device__ __forceinline__ T ldu(const T* base, unsigned i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(T));
+}
+
 template <class A>
 __device__ __forceinline__ Entry get_entry(const A& a, int i) {
     return a.ent ? a.ent[i] : a.inl[i];
@@ -80,6 +93,13 @@ __device__ __forceinline__ const double* view_of(const DGeom& G, int view) {
     return G.view64 + (size_t)view * kViewStride;
 }
 
+// Chunk `c` of the launch owned by entry `en` (whole row block, or its window
+// on column block `col`).
+__device__ __forceinline__ Chunk chunk_of(const DGeom& G, const Entry& en, int c, int windowed, int col) {
+    if (windowed) return G.wchunks[G.rbj_chunk_ptr[en.rb * G.n_cols + col] + (c - en.chunk_prefix)];
+    return G.chunks[G.rb_chunk_ptr[en.rb] + (c - en.chunk_prefix)];
+}
+
 // float64 ray (origin o, unit direction d) of (view, iv, iu).
 template <int KIND>
 __device__ __forceinline__ void ray_of(const DGeom& G, int view, int iv, int iu, double o[3],
@@ -100,7 +120,7 @@ __device__ __forceinline__ void ray_of(const DGeom& G, int view, int iv, int iu,
         o[1] = V[1];
         o[2] = V[2];
     } else {
-        const Ray2& R = G.ray2[(size_t)view * G.nu + iu];
+        const Ray2F& R = G.ray2f[(size_t)view * G.nu + iu];
         d[0] = R.dx;
         d[1] = R.dy;
         d[2] = 0.0;
@@ -118,35 +138,77 @@ __device__ __forceinline__ void ray_of(const DGeom& G, int view, int iv, int iu,
 // ----------------------------------------------------------------------------
 // K2 / K0: forward projection through box J
 // ----------------------------------------------------------------------------
+// Fixed-order float64 sum over [lo, hi) of p by 256 lanes; result in lane 0.
+__device__ __forceinline__ double strided_sum256(const double* p, int lo, int hi, double* sh) {
+    double v = 0.0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += 256) v += p[i];
+    const double t = block_sum256(v, sh);
+    __syncthreads();
+    return t;
+}
+
 template <int KIND, int MODE>
 __global__ __launch_bounds__(256) void k_fwd(DGeom G, FwdArgs a) {
     constexpr int DIMS = (KIND == kCone) ? 3 : 2;
     constexpr bool DIVERGENT = (KIND != kPar2D);
-    __shared__ double sh[4];
-    __shared__ unsigned shu[4];
+    constexpr int U = 4;                       // segments formed before their gathers
+    // the count mode needs whole segment lengths, so it walks each ray in one piece
+    constexpr int K = (MODE == 2) ? 1 : kSplit;
+    __shared__ float pacc[K][kChunk], pacc2[K][kChunk];
 
     const int bid = blockIdx.x;
     const int ei = find_entry(a, bid);
     const Entry en = get_entry(a, ei);
     const int rb = en.rb;
-    const Chunk ch = G.chunks[G.rb_chunk_ptr[rb] + (bid - en.chunk_prefix)];
-    const Tile tl = G.tiles[ch.tile];
-    const int lane = threadIdx.x;
+    const Chunk ch = chunk_of(G, en, bid, a.windowed, a.col);
+    const int lane = threadIdx.x & (kChunk - 1);
+    const int piece = threadIdx.x / kChunk;    // which part of the chord this wave walks
     const bool active = lane < ch.cnt;
 
     float acc = 0.f, acc2 = 0.f;
     unsigned cnt = 0;
     int ray = 0;
     if (active) {
-        const int w = tl.u1 - tl.u0;
         const int k = ch.k0 + lane;
-        const int iv = tl.v0 + k / w;
-        const int iu = tl.u0 + k % w;
+        const int iv = ch.v0 + k / ch.w;
+        const int iu = ch.u0 + k % ch.w;
+        const Tile tl{ch.view, 0, 0, 0, 0};
         ray = (tl.view * G.nv + iv) * G.nu + iu;
 
-        double o[3], d[3];
-        ray_of<KIND>(G, tl.view, iv, iu, o, d);
+        // float64 set-up: origin, unit direction, reciprocal direction
+        double o[3], d[3], id[3];
+        const double* V = view_of(G, tl.view);
+        if constexpr (KIND == kCone) {
+            const double u = ((double)iu - 0.5 * (double)(G.nu - 1)) * G.pu;
+            const double v = ((double)iv - 0.5 * (double)(G.nv - 1)) * G.pv;
+            const double sdd = V[15];
+            double D[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) D[c] = fma(v, V[9 + c], fma(u, V[6 + c], sdd * V[12 + c]));
+            const double inv = 1.0 / sqrt(fma(D[0], D[0], fma(D[1], D[1], D[2] * D[2])));
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                d[c] = D[c] * inv;
+                id[c] = d[c] != 0.0 ? 1.0 / d[c] : 0.0;
+                o[c] = V[c];
+            }
+        } else {
+            const Ray2F R = G.ray2f[(size_t)tl.view * G.nu + iu];
+            d[0] = R.dx;
+            d[1] = R.dy;
+            id[0] = R.idx;
+            id[1] = R.idy;
+            if constexpr (KIND == kPar2D) {
+                const double u = ((double)iu - 0.5 * (double)(G.nu - 1)) * G.pu;
+                o[0] = fma(u, V[6], V[3]);
+                o[1] = fma(u, V[7], V[4]);
+            } else {
+                o[0] = V[0];
+                o[1] = V[1];
+            }
+        }
         const double h[3] = {G.vx, G.vy, G.vz};
+        const double ih[3] = {G.ivx, G.ivy, G.ivz};
         const double org[3] = {G.ox, G.oy, G.oz};
         const int b0[3] = {a.box.x0, a.box.y0, a.box.z0};
         const int b1[3] = {a.box.x1, a.box.y1, a.box.z1};
@@ -154,130 +216,182 @@ __global__ __launch_bounds__(256) void k_fwd(DGeom G, FwdArgs a) {
         bool hit = true;
         double lo[3];
 #pragma unroll
-        for (int k2 = 0; k2 < DIMS; ++k2) {
-            lo[k2] = fma((double)b0[k2], h[k2], org[k2]);
-            const double hi = fma((double)b1[k2], h[k2], org[k2]);
-            if (d[k2] == 0.0) {
-                hit = hit && (o[k2] >= lo[k2]) && (o[k2] < hi);
+        for (int c = 0; c < DIMS; ++c) {
+            lo[c] = fma((double)b0[c], h[c], org[c]);
+            const double hi = fma((double)b1[c], h[c], org[c]);
+            if (d[c] == 0.0) {
+                hit = hit && (o[c] >= lo[c]) && (o[c] < hi);
             } else {
-                const double inv = 1.0 / d[k2];
-                const double ta = (lo[k2] - o[k2]) * inv;
-                const double tb = (hi - o[k2]) * inv;
+                const double ta = (lo[c] - o[c]) * id[c];
+                const double tb = (hi - o[c]) * id[c];
                 t0 = fmax(t0, fmin(ta, tb));
                 t1 = fmin(t1, fmax(ta, tb));
             }
         }
         hit = hit && (t1 > t0);
         if (hit) {
-            // box-local entry point in voxel units and per-axis stepping
+            // this wave's piece of the chord: [t0 + p L/K, t0 + (p+1) L/K]
+            const double Lc = (t1 - t0) / (double)K;
+            t0 = fma((double)piece, Lc, t0);
+            // box-local walk: ii = voxel, dl = distance (voxel units) to the
+            // next plane, inv = mm per voxel along the ray, tk = crossing
             int nb[3], ii[3], sg[3];
             float dl[3], inv[3], tk[3];
-            int stride[3];
-            const int nxJ = a.box.x1 - a.box.x0, nyJ = a.box.y1 - a.box.y0;
-            if constexpr (MODE == 1) {
-                stride[0] = 1;
-                stride[1] = nxJ;
-                stride[2] = nxJ * nyJ;
-            } else {
-                stride[0] = 1;
-                stride[1] = G.nx;
-                stride[2] = G.nx * G.ny;
-            }
-            const float T = (float)(t1 - t0);
+            float T = (float)Lc;
 #pragma unroll
-            for (int k2 = 0; k2 < DIMS; ++k2) {
-                nb[k2] = b1[k2] - b0[k2];
-                const double e = (fma(t0, d[k2], o[k2]) - lo[k2]) / h[k2];
-                const float ef = (float)e;
+            for (int c = 0; c < DIMS; ++c) {
+                nb[c] = b1[c] - b0[c];
+                const float ef = (float)((fma(t0, d[c], o[c]) - lo[c]) * ih[c]);
                 int i = (int)floorf(ef);
-                if (d[k2] < 0.0 && (float)i == ef) i -= 1;
-                i = min(max(i, 0), nb[k2] - 1);
-                ii[k2] = i;
-                if (d[k2] > 0.0) {
-                    sg[k2] = 1;
-                    dl[k2] = (float)(i + 1) - ef;
-                    inv[k2] = (float)(h[k2] / d[k2]);
-                    tk[k2] = dl[k2] * inv[k2];
-                } else if (d[k2] < 0.0) {
-                    sg[k2] = -1;
-                    dl[k2] = ef - (float)i;
-                    inv[k2] = (float)(-h[k2] / d[k2]);
-                    tk[k2] = dl[k2] * inv[k2];
-                } else {
-                    sg[k2] = 0;
-                    dl[k2] = 0.f;
-                    inv[k2] = 0.f;
-                    tk[k2] = INFINITY;
+                if (d[c] < 0.0 && (float)i == ef) i -= 1;
+                i = min(max(i, 0), nb[c] - 1);
+                ii[c] = i;
+                if (d[c] > 0.0) {
+                    sg[c] = 1;
+                    dl[c] = (float)(i + 1) - ef;
+                    inv[c] = (float)(h[c] * id[c]);
+                    tk[c] = dl[c] * inv[c];
+                } else if (d[c] < 0.0) {
+                    sg[c] = -1;
+                    dl[c] = ef - (float)i;
+                    inv[c] = (float)(-h[c] * id[c]);
+                    tk[c] = dl[c] * inv[c];
+                } else {                       // never crossed: dl * inv stays +inf
+                    sg[c] = 0;
+                    dl[c] = 1.f;
+                    inv[c] = INFINITY;
+                    tk[c] = INFINITY;
                 }
             }
+            // linear voxel index and its step per axis.  The fused path uses
+            // the copy whose fast axis is across the view's central ray.
+            int step[3];
             int idx;
+            const float2* xg = nullptr;
             if constexpr (MODE == 1) {
-                idx = ii[0] + ii[1] * stride[1] + (DIMS == 3 ? ii[2] * stride[2] : 0);
+                const int grp = __builtin_amdgcn_readfirstlane(en.group);
+                const double* Vc = view_of(G, tl.view);
+                const double cdx = (KIND == kPar2D) ? Vc[0] : Vc[12];
+                const double cdy = (KIND == kPar2D) ? Vc[1] : Vc[13];
+                const int tr = __builtin_amdgcn_readfirstlane(fabs(cdx) > fabs(cdy) ? 1 : 0);
+                const int cs = xg_copy(nb[0], nb[1], DIMS == 3 ? nb[2] : 1);
+                xg = a.xg + (size_t)grp * (size_t)a.xg_stride + (size_t)tr * (size_t)cs;
+                step[0] = tr ? nb[1] : 1;
+                step[1] = tr ? 1 : nb[0];
+                step[2] = nb[0] * nb[1];
             } else {
-                idx = (a.box.x0 + ii[0]) + (a.box.y0 + ii[1]) * stride[1] +
-                      (DIMS == 3 ? (a.box.z0 + ii[2]) * stride[2] : 0);
+                step[0] = 1;
+                step[1] = G.nx;
+                step[2] = G.nx * G.ny;
             }
-            const float2* xg = (MODE == 1) ? a.xg + (size_t)en.group * a.vox_J : nullptr;
-            const int maxit = nb[0] + nb[1] + (DIMS == 3 ? nb[2] : 0) + 4;
+            {
+                int lin = ii[0] * step[0] + ii[1] * step[1] + (DIMS == 3 ? ii[2] * step[2] : 0);
+                if constexpr (MODE == 0)
+                    lin += a.box.x0 + a.box.y0 * G.nx + (DIMS == 3 ? a.box.z0 * G.nx * G.ny : 0);
+                if constexpr (MODE == 1) lin += xg_pad(nb[0], nb[1], DIMS == 3 ? nb[2] : 1);
+                idx = lin;                      // never negative: the padding is in front
+            }
+            int sst[3];
+#pragma unroll
+            for (int c = 0; c < DIMS; ++c) sst[c] = sg[c] * step[c];
+            const int maxit = (nb[0] + nb[1] + (DIMS == 3 ? nb[2] : 0) + 4 + U - 1) / U;
             float tau = 0.f;
             for (int it = 0; it < maxit; ++it) {
-                float tn = fminf(tk[0], tk[1]);
-                if constexpr (DIMS == 3) tn = fminf(tn, tk[2]);
-                tn = fminf(tn, T);
-                const float len = tn - tau;
-                if constexpr (MODE == 0) {
-                    acc = fmaf(len, a.x[idx], acc);
-                } else if constexpr (MODE == 1) {
-                    const float2 v = xg[idx];
-                    acc = fmaf(len, v.x, acc);
-                    acc2 = fmaf(len, v.y, acc2);
-                } else {
-                    cnt += (len > a.tau) ? 1u : 0u;
-                }
-                if (tn >= T) break;
-                tau = tn;
-                int ax;
-                if constexpr (DIMS == 3) {
-                    ax = (tk[0] <= tk[1]) ? ((tk[0] <= tk[2]) ? 0 : 2) : ((tk[1] <= tk[2]) ? 1 : 2);
-                } else {
-                    ax = (tk[0] <= tk[1]) ? 0 : 1;
-                }
-                // branch-free advance of axis `ax`
-                bool out = false;
+                int sid[U];
+                float sl[U];
 #pragma unroll
-                for (int k2 = 0; k2 < DIMS; ++k2) {
-                    if (ax == k2) {
-                        ii[k2] += sg[k2];
-                        idx += sg[k2] * stride[k2];
-                        dl[k2] += 1.f;
-                        tk[k2] = dl[k2] * inv[k2];
-                        out = (unsigned)ii[k2] >= (unsigned)nb[k2];
+                for (int q = 0; q < U; ++q) {
+                    // segment q: from tau to the nearest crossing (or the exit)
+                    float tn = fminf(fminf(tk[0], tk[1]), T);
+                    if constexpr (DIMS == 3) tn = fminf(tn, tk[2]);
+                    sl[q] = tn - tau;
+                    tau = tn;
+                    sid[q] = idx;
+                    // cross the nearest plane.  Past the exit the lengths are
+                    // zero; the fused path then reads the zero padding, the
+                    // primitive path is clamped to the box.
+                    if constexpr (DIMS == 3) {
+                        const bool a0 = tk[0] <= tk[1] && tk[0] <= tk[2];
+                        const bool a1 = !a0 && tk[1] <= tk[2];
+                        const bool a2 = !a0 && !a1;
+                        idx += a0 ? sst[0] : (a1 ? sst[1] : sst[2]);
+                        dl[0] = a0 ? dl[0] + 1.f : dl[0];
+                        dl[1] = a1 ? dl[1] + 1.f : dl[1];
+                        dl[2] = a2 ? dl[2] + 1.f : dl[2];
+                        if constexpr (MODE == 0) {
+                            ii[0] = a0 ? ii[0] + sg[0] : ii[0];
+                            ii[1] = a1 ? ii[1] + sg[1] : ii[1];
+                            ii[2] = a2 ? ii[2] + sg[2] : ii[2];
+                        }
+                    } else {
+                        const bool a0 = tk[0] <= tk[1];
+                        idx += a0 ? sst[0] : sst[1];
+                        dl[0] = a0 ? dl[0] + 1.f : dl[0];
+                        dl[1] = a0 ? dl[1] : dl[1] + 1.f;
+                        if constexpr (MODE == 0) {
+                            ii[0] = a0 ? ii[0] + sg[0] : ii[0];
+                            ii[1] = a0 ? ii[1] : ii[1] + sg[1];
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c < DIMS; ++c) tk[c] = dl[c] * inv[c];
+                    if constexpr (MODE == 0) {
+                        // keep the caller's array in bounds: stop at the box
+                        bool out = false;
+#pragma unroll
+                        for (int c = 0; c < DIMS; ++c) out = out || (unsigned)ii[c] >= (unsigned)nb[c];
+                        if (out) {
+                            T = tau;
+                            idx = sid[q];
+#pragma unroll
+                            for (int c = 0; c < DIMS; ++c) ii[c] = min(max(ii[c], 0), nb[c] - 1);
+                        }
                     }
                 }
-                if (out) break;
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    if constexpr (MODE == 0) {
+                        acc = fmaf(sl[q], ldu(a.x, (unsigned)sid[q]), acc);
+                    } else if constexpr (MODE == 1) {
+                        const float2 v = ldu(xg, (unsigned)sid[q]);
+                        acc = fmaf(sl[q], v.x, acc);
+                        acc2 = fmaf(sl[q], v.y, acc2);
+                    } else {
+                        cnt += (sl[q] > a.tau) ? 1u : 0u;
+                    }
+                }
+                if (!(tau < T)) break;
             }
         }
     }
 
-    if constexpr (MODE == 0) {
-        if (active) a.out[ray] = (a.flags & 1) ? a.out[ray] + acc : acc;
-    } else if constexpr (MODE == 1) {
-        if (active) {
-            a.out[ray] = acc;
-            a.q[en.slot_prefix + ch.roff + lane] = acc2;
-        }
-        const double p = active ? (double)acc2 * (double)acc2 : 0.0;
-        const double t = block_sum256(p, sh);
-        if (threadIdx.x == 0) a.partial[bid] = t;
-    } else {
-        unsigned c = wave_sum_u(cnt);
-        const int w = threadIdx.x >> 6;
-        if ((threadIdx.x & 63) == 0) shu[w] = c;
+    // the pieces of each ray, added in a fixed order
+    if constexpr (K > 1) {
+        pacc[piece][lane] = acc;
+        if constexpr (MODE == 1) pacc2[piece][lane] = acc2;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long tot = (unsigned long long)shu[0] + shu[1] + shu[2] + shu[3];
-            if (tot) atomicAdd(a.nnz + (size_t)rb * a.n_cols + a.col, tot);
+        acc = pacc[0][lane];
+        if constexpr (MODE == 1) acc2 = pacc2[0][lane];
+#pragma unroll
+        for (int p = 1; p < K; ++p) {
+            acc += pacc[p][lane];
+            if constexpr (MODE == 1) acc2 += pacc2[p][lane];
         }
+    }
+    if constexpr (MODE == 0) {
+        if (piece == 0 && active) a.out[ray] = (a.flags & 1) ? a.out[ray] + acc : acc;
+    } else if constexpr (MODE == 1) {
+        if (piece == 0) {
+            if (active) {
+                a.out[ray] = acc;
+                a.q[en.slot_prefix + ch.roff + lane] = acc2;
+            }
+            const double t = wave_sum(active ? (double)acc2 * (double)acc2 : 0.0);
+            if (lane == 0) a.partial[bid] = t;
+        }
+    } else {
+        const unsigned c = wave_sum_u(cnt);
+        if (lane == 0 && c) atomicAdd(a.nnz + (size_t)rb * a.n_cols + a.col, (unsigned long long)c);
     }
 }
 
@@ -285,119 +399,203 @@ __global__ __launch_bounds__(256) void k_fwd(DGeom G, FwdArgs a) {
 // K1: gather back-projection, 2D
 // ----------------------------------------------------------------------------
 // Clip length of the ray described by R with the voxel whose centre lies at
-// signed distance delta from it.
-__device__ __forceinline__ float chord2(float delta, const Ray2& R) {
-    const float cx = delta * R.kx, cy = delta * R.ky;
-    const float hi = fminf(cx + R.wx, cy + R.wy);
-    const float lo = fmaxf(cx - R.wx, cy - R.wy);
-    return fmaxf(hi - lo, 0.f);
+// signed distance delta from it: the overlap of its two slab intervals.
+__device__ __forceinline__ float chord2(float delta, const Ray2B& R) {
+    return fmaxf(fminf(R.M, R.S - fabsf(delta * R.K)), 0.f);
 }
 
 // Same, for rays with an exactly zero direction component (half-open voxels).
-__device__ __forceinline__ float chord2_axis(float delta, const Ray2& R, float hx, float hy) {
-    if (R.wx < 0.f) {
-        const float off = delta * R.kx;
-        return (off >= -hx && off < hx) ? 2.f * R.wy : 0.f;
-    }
-    if (R.wy < 0.f) {
-        const float off = delta * R.ky;
-        return (off >= -hy && off < hy) ? 2.f * R.wx : 0.f;
+__device__ __forceinline__ float chord2_axis(float delta, const Ray2B& R, float hx, float hy) {
+    if (R.M < 0.f) {
+        const float off = delta * R.K;
+        const float h = (R.M == -1.f) ? hx : hy;
+        return (off >= -h && off < h) ? R.S : 0.f;
     }
     return chord2(delta, R);
 }
 
+// Per (tile, view) parameters.  For a voxel at index offset (lx, ly) from the
+// tile centre: view-frame offset A = Ac + lx ax + ly ay, B = Bc + lx bx + ly by
+// (exact, both are affine in position); bin coordinate of its shadow centre
+// ~ bc + lx bxs + ly bys, with W (bins) covering the voxel's own half-width,
+// the curvature of the projection over the tile and float32 rounding.
+struct ViewP {
+    double Ac, Bc, ax, ay, bx, by;
+    float bc, bxs, bys, W;
+    int32_t view, u0, u1, flags;
+};
+
+template <int KIND>
+__device__ __forceinline__ void view_params(const DGeom& G, const Tile& tl, double cx, double cy,
+                                            double dt, ViewP& P) {
+    const double* V = view_of(G, tl.view);
+    const double c0 = 0.5 * (double)(G.nu - 1);
+    const double R = (double)G.radius;
+    P.view = tl.view;
+    P.u0 = tl.u0;
+    P.u1 = tl.u1;
+    P.flags = G.view_flags[tl.view];
+    double bc, bxs, bys, W;
+    if constexpr (KIND == kPar2D) {
+        // delta(u) = B - u kappa with B = cross(d, p - C): affine, so exact
+        P.Ac = 1.0;
+        P.ax = P.ay = 0.0;
+        P.Bc = V[0] * (cy - V[4]) - V[1] * (cx - V[3]);
+        P.bx = -V[1] * G.vx;
+        P.by = V[0] * G.vy;
+        const double s = 1.0 / (V[15] * G.pu);
+        bc = P.Bc * s + c0;
+        bxs = P.bx * s;
+        bys = P.by * s;
+        W = R / (fabs(V[15]) * G.pu);
+    } else {
+        const double qx = cx - V[0], qy = cy - V[1];
+        P.Ac = fma(qx, V[12], qy * V[13]);
+        P.Bc = fma(qx, V[6], qy * V[7]);
+        P.ax = V[12] * G.vx;
+        P.ay = V[13] * G.vy;
+        P.bx = V[6] * G.vx;
+        P.by = V[7] * G.vy;
+        const double A = P.Ac, B = P.Bc;
+        const double rho = sqrt(A * A + B * B);
+        const double amin = A - dt;                   // every point of the tile is this deep
+        if constexpr (KIND == kFanCurved) {
+            // polar angle of the voxel centre; Hessian norm 1/rho^2
+            const double rmin = rho - dt;
+            const double ir2 = 1.0 / (rho * rho);
+            // float32 angle: it only selects candidates (margin 1e-6 rad below)
+            bc = (double)atan2f((float)B, (float)A) / G.pu + c0;
+            bxs = (A * P.bx - B * P.ax) * ir2 / G.pu;
+            bys = (A * P.by - B * P.ay) * ir2 / G.pu;
+            W = (rmin > 1.0001 * R)
+                    ? (R / sqrt(rmin * rmin - R * R) + 0.5 * dt * dt / (rmin * rmin) + 1e-6) / G.pu
+                    : 1e9;
+        } else {
+            // u = sdd * B / A; Hessian norm of B/A <= 2 (1 + |B/A|) / A^2
+            const double sdd = V[15];
+            const double ia = 1.0 / A;
+            const double tb = (fabs(B) + dt) / amin;   // bound of |B/A| over the tile
+            bc = sdd * B * ia / G.pu + c0;
+            bxs = sdd * (A * P.bx - B * P.ax) * ia * ia / G.pu;
+            bys = sdd * (A * P.by - B * P.ay) * ia * ia / G.pu;
+            W = (amin > 1.0001 * R)
+                    ? sdd * ((1.0 + tb) * R / (amin - R) + (1.0 + tb) * dt * dt / (amin * amin)) / G.pu
+                    : 1e9;
+        }
+    }
+    P.bc = (float)bc;
+    P.bxs = (float)bxs;
+    P.bys = (float)bys;
+    P.W = (float)fmin(W, 1e9) + 2e-3f + 1e-6f * fabsf((float)bc);
+}
+
 template <int KIND>
 __global__ __launch_bounds__(256) void k_back2(DGeom G, BackArgs a) {
-    __shared__ double sh[4];
+    __shared__ ViewP vp[4][64];
+    __shared__ float red[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wu = __builtin_amdgcn_readfirstlane(w);
     const int gi = blockIdx.y;
     const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
-    const int lx = threadIdx.x & (kTile2 - 1), ly = threadIdx.x / kTile2;
+    const int lx = lane & (kTile2 - 1), ly = lane / kTile2;
     const int ix = a.box.x0 + tx * kTile2 + lx, iy = a.box.y0 + ty * kTile2 + ly;
     const bool valid = ix < a.box.x1 && iy < a.box.y1;
 
-    const double cx = G.ox + ((double)ix + 0.5) * G.vx;
-    const double cy = G.oy + ((double)iy + 0.5) * G.vy;
+    // centre and half-diagonal of the tile's voxels inside the box
+    const int xs = a.box.x0 + tx * kTile2, ys = a.box.y0 + ty * kTile2;
+    const int nvx = min(kTile2, a.box.x1 - xs), nvy = min(kTile2, a.box.y1 - ys);
+    const double tcx = G.ox + ((double)xs + 0.5 * nvx) * G.vx;
+    const double tcy = G.oy + ((double)ys + 0.5 * nvy) * G.vy;
+    const double hkx = 0.5 * (nvx - 1), hky = 0.5 * (nvy - 1);
+    const double dt = sqrt((hkx * G.vx) * (hkx * G.vx) + (hky * G.vy) * (hky * G.vy));
+    const float lxf = (float)lx - (float)hkx, lyf = (float)ly - (float)hky;
+    const double lxd = (double)lxf, lyd = (double)lyf;
     const float hx = (float)(0.5 * G.vx), hy = (float)(0.5 * G.vy);
-    const float R = G.radius;
-    const float c0 = 0.5f * (float)(G.nu - 1);
-    const float ipu = (float)(1.0 / G.pu);
-    float acc = 0.f;
 
     int e0 = 0, e1 = a.n_ent;
     if (a.gptr) {
         e0 = a.gptr[gi];
         e1 = a.gptr[gi + 1];
     }
-    if (valid) {
-        for (int e = e0; e < e1; ++e) {
-            const int rb = get_entry(a, e).rb;
-            const int t_end = G.rb_tile_ptr[rb + 1];
-            for (int t = G.rb_tile_ptr[rb]; t < t_end; ++t) {
-                const Tile tl = G.tiles[t];
-                const int view = tl.view;
-                const double* V = view_of(G, view);
-                double A, B;
-                float beta, wb;
-                if constexpr (KIND == kPar2D) {
-                    // signed distance of the bin-u ray: delta = B - u*kappa
-                    A = 1.0;
-                    B = V[0] * (cy - V[4]) - V[1] * (cx - V[3]);
-                    const float kap = (float)V[15];
-                    beta = (float)(B / V[15]) * ipu + c0;
-                    wb = R / fabsf(kap) * ipu;
-                } else {
-                    const double qx = cx - V[0], qy = cy - V[1];
-                    A = fma(qx, V[12], qy * V[13]);
-                    B = fma(qx, V[6], qy * V[7]);
-                    const float Af = (float)A, Bf = (float)B;
-                    if constexpr (KIND == kFanCurved) {
-                        const float phi = atan2f(Bf, Af);
-                        const float rho2 = fmaf(Af, Af, Bf * Bf);
-                        beta = phi * ipu + c0;
-                        wb = R * rsqrtf(fmaxf(rho2 - R * R, 1e-30f)) * ipu;
-                    } else {
-                        const float sdd = (float)V[15];
-                        const float t = Bf / Af;
-                        beta = sdd * t * ipu + c0;
-                        wb = sdd * R * (1.f + fabsf(t)) / (Af - R) * ipu;
-                    }
+    int nt = 0;                                          // views (tiles) of the group
+    for (int e = e0; e < e1; ++e) {
+        const int rb = get_entry(a, e).rb;
+        nt += G.rb_tile_ptr[rb + 1] - G.rb_tile_ptr[rb];
+    }
+
+    float acc = 0.f;
+    for (int base = 0; base < nt; base += 256) {
+        // lane `lane` of wave `w` prepares the view with flat index base + 4 lane + w
+        const int f = base + 4 * lane + w;
+        if (f < nt) {
+            int e = e0, off = f;
+            for (;;) {
+                const int rb = get_entry(a, e).rb;
+                const int cnt = G.rb_tile_ptr[rb + 1] - G.rb_tile_ptr[rb];
+                if (off < cnt) {
+                    const Tile tl = G.tiles[G.rb_tile_ptr[rb] + off];
+                    view_params<KIND>(G, tl, tcx, tcy, dt, vp[w][lane]);
+                    break;
                 }
-                int blo = (int)ceilf(beta - wb - 1e-3f);
-                int bhi = (int)floorf(beta + wb + 1e-3f);
-                blo = max(blo, tl.u0);
-                bhi = min(bhi, tl.u1 - 1);
-                const Ray2* RR = G.ray2 + (size_t)view * G.nu;
+                off -= cnt;
+                ++e;
+            }
+        }
+        __syncthreads();
+        const int nb = min(64, (nt - base - wu + 3) / 4);
+        if (valid) {
+            for (int j = 0; j < nb; ++j) {
+                const ViewP& P = vp[wu][j];
+                const int view = __builtin_amdgcn_readfirstlane(P.view);
+                const int u0 = __builtin_amdgcn_readfirstlane(P.u0);
+                const int u1 = __builtin_amdgcn_readfirstlane(P.u1);
+                const int vflags = __builtin_amdgcn_readfirstlane(P.flags);
+                const double A = fma(lyd, P.ay, fma(lxd, P.ax, P.Ac));
+                const double B = fma(lyd, P.by, fma(lxd, P.bx, P.Bc));
+                const float beta = fmaf(lyf, P.bys, fmaf(lxf, P.bxs, P.bc));
+                const int blo = max((int)ceilf(beta - P.W), u0);
+                const int bhi = min((int)floorf(beta + P.W), u1 - 1);
+                const Ray2B* RB = G.ray2b + (size_t)view * G.nu;
                 const float* rr = a.r + (size_t)view * G.nu;
-                if (G.view_flags[view] & 1) {
+                if (vflags & 1) {
                     for (int b = blo; b <= bhi; ++b) {
-                        const Ray2 Rb = RR[b];
+                        const Ray2B Rb = ldu(RB, (unsigned)b);
                         const float dlt = (float)fma(Rb.p, B, -Rb.q * A);
-                        acc = fmaf(chord2_axis(dlt, Rb, hx, hy), rr[b], acc);
+                        acc = fmaf(chord2_axis(dlt, Rb, hx, hy), ldu(rr, (unsigned)b), acc);
                     }
                 } else {
                     for (int b = blo; b <= bhi; ++b) {
-                        const Ray2 Rb = RR[b];
+                        const Ray2B Rb = ldu(RB, (unsigned)b);
                         const float dlt = (float)fma(Rb.p, B, -Rb.q * A);
-                        acc = fmaf(chord2(dlt, Rb), rr[b], acc);
+                        acc = fmaf(chord2(dlt, Rb), ldu(rr, (unsigned)b), acc);
                     }
                 }
             }
         }
+        __syncthreads();
     }
 
+    // the four waves' partial sums, added in a fixed order
+    red[w][lane] = acc;
+    __syncthreads();
+    const float gsum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
     const int nxJ = a.box.x1 - a.box.x0;
     if (a.fused) {
-        if (valid) {
-            const int li = (iy - a.box.y0) * nxJ + (ix - a.box.x0);
-            const int gix = iy * G.nx + ix;
-            a.xg[(size_t)gi * a.vox_J + li] = make_float2(a.x[gix], acc);
+        if (w == 0) {
+            if (valid) {
+                const int nyJ = a.box.y1 - a.box.y0;
+                const int lx = ix - a.box.x0, ly = iy - a.box.y0;
+                const float2 v = make_float2(a.x[(size_t)iy * G.nx + ix], gsum);
+                float2* base = a.xg + (size_t)gi * a.xg_stride + xg_pad(nxJ, nyJ, 1);
+                base[ly * nxJ + lx] = v;
+                base[xg_copy(nxJ, nyJ, 1) + lx * nyJ + ly] = v;
+            }
+            const double t = wave_sum(valid ? (double)gsum * (double)gsum : 0.0);
+            if (lane == 0) a.partial[(size_t)gi * gridDim.x + blockIdx.x] = t;
         }
-        const double p = valid ? (double)acc * (double)acc : 0.0;
-        const double t = block_sum256(p, sh);
-        if (threadIdx.x == 0) a.partial[(size_t)gi * gridDim.x + blockIdx.x] = t;
-    } else if (valid) {
-        const int gix = iy * G.nx + ix;
-        a.g[gix] = (a.flags & 1) ? a.g[gix] + acc : acc;
+    } else if (w == 0 && valid) {
+        const size_t gix = (size_t)iy * G.nx + ix;
+        a.g[gix] = (a.flags & 1) ? a.g[gix] + gsum : gsum;
     }
 }
 
@@ -492,8 +690,12 @@ __global__ __launch_bounds__(256) void k_back3(DGeom G, BackArgs a) {
     const size_t gix = ((size_t)iz * G.ny + iy) * G.nx + ix;
     if (a.fused) {
         if (valid) {
-            const int li = ((iz - a.box.z0) * nyJ + (iy - a.box.y0)) * nxJ + (ix - a.box.x0);
-            a.xg[(size_t)gi * a.vox_J + li] = make_float2(a.x[gix], acc);
+            const int nzJ = a.box.z1 - a.box.z0;
+            const int lx = ix - a.box.x0, ly = iy - a.box.y0, lz = iz - a.box.z0;
+            const float2 v = make_float2(a.x[gix], acc);
+            float2* base = a.xg + (size_t)gi * a.xg_stride + xg_pad(nxJ, nyJ, nzJ);
+            base[(lz * nyJ + ly) * nxJ + lx] = v;
+            base[xg_copy(nxJ, nyJ, nzJ) + (lz * nxJ + lx) * nyJ + ly] = v;
         }
         const double p = valid ? (double)acc * (double)acc : 0.0;
         const double t = block_sum256(p, sh);
@@ -504,21 +706,17 @@ __global__ __launch_bounds__(256) void k_back3(DGeom G, BackArgs a) {
 }
 
 // ----------------------------------------------------------------------------
-// K3: step sizes
+// K3: step sizes mu = beta ||g||^2 / ||A g||^2 (Eq. 11, relaxed), one
+// work-group per group, fixed-order float64 sums of the partials
 // ----------------------------------------------------------------------------
-
-__global__ __launch_bounds__(64) void k_step(StepArgs s) {
+__global__ __launch_bounds__(256) void k_step(StepArgs s) {
+    __shared__ double sh[4];
     const int g = blockIdx.x;
-    const int lane = threadIdx.x;
+    const double gg = strided_sum256(s.pg, g * s.n_tiles, (g + 1) * s.n_tiles, sh);
     const int c0 = s.ent[s.gptr[g]].chunk_prefix;
-    const int e_next = s.gptr[g + 1];
-    const int c1 = (e_next < s.gptr[gridDim.x]) ? s.ent[e_next].chunk_prefix : s.n_chunks;
-    double gg = 0.0, qq = 0.0;
-    for (int t = lane; t < s.n_tiles; t += 64) gg += s.pg[(size_t)g * s.n_tiles + t];
-    for (int c = c0 + lane; c < c1; c += 64) qq += s.pq[c];
-    gg = wave_sum(gg);
-    qq = wave_sum(qq);
-    if (lane == 0) s.mu[g] = (gg > 0.0 && qq > 0.0) ? s.beta[g] * gg / qq : 0.0;
+    const int c1 = (g + 1 < (int)gridDim.x) ? s.ent[s.gptr[g + 1]].chunk_prefix : s.n_chunks;
+    const double qq = strided_sum256(s.pq, c0, c1, sh);
+    if (threadIdx.x == 0) s.mu[g] = (gg > 0.0 && qq > 0.0) ? s.beta[g] * gg / qq : 0.0;
 }
 
 // ----------------------------------------------------------------------------
@@ -527,16 +725,17 @@ __global__ __launch_bounds__(64) void k_step(StepArgs s) {
 
 __global__ __launch_bounds__(256) void k_finalize(DGeom G, FinArgs f) {
     const int bid = blockIdx.x;
-    if (bid < f.n_chunks) {
-        const int ei = find_entry(f, bid);
+    const int ray_blocks = (f.n_chunks + 3) / 4;
+    if (bid < ray_blocks) {
+        const int c = bid * 4 + (threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+        if (c >= f.n_chunks) return;
+        const int ei = find_entry(f, c);
         const Entry en = get_entry(f, ei);
-        const Chunk ch = G.chunks[G.rb_chunk_ptr[en.rb] + (bid - en.chunk_prefix)];
-        const int lane = threadIdx.x;
+        const Chunk ch = chunk_of(G, en, c, 1, f.col);
         if (lane >= ch.cnt) return;
-        const Tile tl = G.tiles[ch.tile];
-        const int w = tl.u1 - tl.u0;
         const int k = ch.k0 + lane;
-        const int ray = (tl.view * G.nv + tl.v0 + k / w) * G.nu + tl.u0 + k % w;
+        const int ray = (ch.view * G.nv + ch.v0 + k / ch.w) * G.nu + ch.u0 + k % ch.w;
         const float mu = (float)f.mu[en.group];
         const float zn = fmaf(mu, f.q[en.slot_prefix + ch.roff + lane], f.zJ[ray]);
         f.zJ[ray] = zn;
@@ -546,15 +745,17 @@ __global__ __launch_bounds__(256) void k_finalize(DGeom G, FinArgs f) {
             f.r[ray] = f.y[ray] - s;
         }
     } else {
-        const int v = (bid - f.n_chunks) * 256 + threadIdx.x;
+        const int v = (bid - ray_blocks) * 256 + threadIdx.x;
         if (v >= f.vox_J) return;
-        float s = 0.f;
-        for (int g = 0; g < f.n_groups; ++g) {
-            const float2 p = f.xg[(size_t)g * f.vox_J + v];
-            s += fmaf((float)f.mu[g], p.y, p.x);
-        }
         const int nxJ = f.box.x1 - f.box.x0, nyJ = f.box.y1 - f.box.y0;
         const int lx = v % nxJ, ly = (v / nxJ) % nyJ, lz = v / (nxJ * nyJ);
+        const int nzJ = f.box.z1 - f.box.z0;
+        const int li = xg_pad(nxJ, nyJ, nzJ) + v;           // copy 0 is x-fastest
+        float s = 0.f;
+        for (int g = 0; g < f.n_groups; ++g) {
+            const float2 p = f.xg[(size_t)g * f.xg_stride + li];
+            s += fmaf((float)f.mu[g], p.y, p.x);
+        }
         const size_t gix = ((size_t)(f.box.z0 + lz) * f.ny + (f.box.y0 + ly)) * f.nx + f.box.x0 + lx;
         f.x[gix] = s / (float)f.n_groups;
     }
@@ -564,17 +765,16 @@ __global__ __launch_bounds__(256) void k_finalize(DGeom G, FinArgs f) {
 // K5: residual refresh over the rays of a list of row blocks
 // ----------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_residual(DGeom G, ResArgs a) {
-    const int bid = blockIdx.x;
-    const int ei = find_entry(a, bid);
+__global__ __launch_bounds__(256) void k_residual(DGeom G, ResArgs a, int n_chunks) {
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= n_chunks) return;
+    const int ei = find_entry(a, c);
     const Entry en = get_entry(a, ei);
-    const Chunk ch = G.chunks[G.rb_chunk_ptr[en.rb] + (bid - en.chunk_prefix)];
-    const int lane = threadIdx.x;
+    const Chunk ch = chunk_of(G, en, c, 0, 0);
     if (lane >= ch.cnt) return;
-    const Tile tl = G.tiles[ch.tile];
-    const int w = tl.u1 - tl.u0;
     const int k = ch.k0 + lane;
-    const int ray = (tl.view * G.nv + tl.v0 + k / w) * G.nu + tl.u0 + k % w;
+    const int ray = (ch.view * G.nv + ch.v0 + k / ch.w) * G.nu + ch.u0 + k % ch.w;
     float s = 0.f;
     for (int j = 0; j < a.n_cols; ++j) s += a.z[(size_t)j * a.M + ray];
     a.r[ray] = a.y[ray] - s;
@@ -617,7 +817,7 @@ __global__ __launch_bounds__(256) void k_resnorm(const float* y, const float* p,
 // ----------------------------------------------------------------------------
 template <int MODE>
 static hipError_t launch_fwd_mode(const DGeom& G, const FwdArgs& a, hipStream_t st) {
-    dim3 grid(a.n_chunks), block(256);
+    dim3 grid(a.n_chunks), block(MODE == 2 ? kChunk : kChunk * kSplit);
     switch (G.kind) {
         case kPar2D: hipLaunchKernelGGL((k_fwd<kPar2D, MODE>), grid, block, 0, st, G, a); break;
         case kFanFlat: hipLaunchKernelGGL((k_fwd<kFanFlat, MODE>), grid, block, 0, st, G, a); break;
@@ -649,12 +849,12 @@ hipError_t launch_back(const DGeom& G, const BackArgs& a, int n_groups, hipStrea
 
 hipError_t launch_step(const StepArgs& s, int n_groups, hipStream_t st) {
     if (n_groups <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_step, dim3(n_groups), dim3(64), 0, st, s);
+    hipLaunchKernelGGL(k_step, dim3(n_groups), dim3(256), 0, st, s);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(const DGeom& G, const FinArgs& f, int vox_blocks, hipStream_t st) {
-    const int nb = f.n_chunks + vox_blocks;
+    const int nb = (f.n_chunks + 3) / 4 + vox_blocks;
     if (nb <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(256), 0, st, G, f);
     return hipGetLastError();
@@ -662,7 +862,7 @@ hipError_t launch_finalize(const DGeom& G, const FinArgs& f, int vox_blocks, hip
 
 hipError_t launch_residual(const DGeom& G, const ResArgs& a, int n_chunks, hipStream_t st) {
     if (n_chunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_residual, dim3(n_chunks), dim3(256), 0, st, G, a);
+    hipLaunchKernelGGL(k_residual, dim3((n_chunks + 3) / 4), dim3(256), 0, st, G, a, n_chunks);
     return hipGetLastError();
 }
 
