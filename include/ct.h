@@ -250,16 +250,44 @@ int ct_solve(ct_geom* geom, const ct_solve_params* params, const float* y, float
              ct_solve_stats* stats, void* stream);
 
 /* ---- batched epochs --------------------------------------------------------
- * Several independent solvers (each its own geometry, schedule and state)
- * advanced together: the kernels of one phase of every job go out as a single
- * launch, so many small jobs fill the GPU.  ct_batch_epoch runs, for every job
- * k, epoch epochs[k] of schedule scheds[k] (a negative entry skips the job).
- * Results equal those of ct_block_epoch job by job. */
+ * Many independent jobs (each its own geometry, solver, schedule, y and x)
+ * advanced together, for workloads of many small reconstructions.  One batch
+ * epoch runs the next epoch of Alg. 6 of every job that has one left: for
+ * each step index c, ONE launch per projector kind does the back-projection
+ * of step c of every job, then one launch the forward projections, one the
+ * step sizes and one the finalize; epoch-synchronous jobs then get their
+ * residual refresh, and a last tiny launch moves every job's epoch counter
+ * on.  Each work-group finds its job in a device job table, so a job's
+ * results are bit for bit those of ct_block_epoch run alone.
+ *
+ * Jobs are added and removed between batch epochs (continuous batching); the
+ * batch only refers to the caller's solvers, schedules and buffers, which must
+ * outlive the job's membership.  A job's solver must have been reset
+ * (ct_solver_reset) and belongs to one batch job at a time; no two jobs may
+ * share a solver or an x.  All calls on one batch must use the same stream
+ * (or be ordered by the caller): the job table is updated on that stream. */
 typedef struct ct_batch ct_batch;
-int ct_batch_create(int32_t n_jobs, ct_solver* const* solvers, ct_batch** out);
+typedef struct ct_batch_job {
+    ct_solver* solver;
+    const ct_schedule* sched;   /* built for the solver's geometry          */
+    const float* y;             /* device [M]                               */
+    float* x;                   /* device [N], updated in place             */
+    int32_t epoch;              /* first epoch of sched to run              */
+} ct_batch_job;
+/* CT_BATCH_GRAPH: record the launches of one batch epoch into a HIP graph
+ * once (again after every add/remove) and replay it; the kernels read each
+ * job's epoch from the device, so one graph serves every epoch. */
+enum { CT_BATCH_GRAPH = 1 };
+/* capacity: most jobs the batch holds at once (1..256). */
+int ct_batch_create(int32_t capacity, ct_batch** out);
 void ct_batch_destroy(ct_batch* batch);
-int ct_batch_epoch(ct_batch* batch, const ct_schedule* const* scheds, const int32_t* epochs,
-                   const float* const* ys, float* const* xs, void* stream);
+/* Adds a job; *id identifies it until ct_batch_remove. */
+int ct_batch_add(ct_batch* batch, const ct_batch_job* job, int32_t* id);
+int ct_batch_remove(ct_batch* batch, int32_t id);
+/* One batch epoch; *ran (may be NULL) = jobs that had an epoch to run. */
+int ct_batch_epoch(ct_batch* batch, int32_t flags, int32_t* ran, void* stream);
+/* Next epoch the job will run (== its schedule's epoch count when done). */
+int ct_batch_job_epoch(const ct_batch* batch, int32_t id, int32_t* epoch);
 
 /* Device bytes one job needs (geometry tables + workspace): for admission
  * by memory budget. */

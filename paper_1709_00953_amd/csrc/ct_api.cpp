@@ -74,6 +74,7 @@ struct ct_geom {
     Entry* d_all = nullptr;
     unsigned long long* d_nnz = nullptr;
     double* d_part = nullptr;          // residual-norm partials
+    Box* d_boxes = nullptr;            // [n]
 };
 
 static void box_tiling(const ct_geom* g, const Box& b, int* tx, int* ty, int* tz) {
@@ -433,7 +434,7 @@ static void build_frames(const ct_geom* g, std::vector<Ray2F>& rayf, std::vector
 struct DevLayout {
     size_t off_view, off_rayf, off_rayb, off_flags, off_tiles, off_rbt, off_troff, off_chunks, off_rbc, off_wch,
         off_rbj, off_all,
-        off_nnz, off_part, total;
+        off_nnz, off_part, off_boxes, total;
 };
 
 static DevLayout dev_layout(const ct_geom* g) {
@@ -458,6 +459,7 @@ static DevLayout dev_layout(const ct_geom* g) {
     L.off_all = take(g->all_entries.size() * sizeof(Entry));
     L.off_nnz = take((size_t)g->m * g->n * sizeof(unsigned long long));
     L.off_part = take(2 * 1024 * sizeof(double));
+    L.off_boxes = take(g->boxes.size() * sizeof(Box));
     L.total = o;
     return L;
 }
@@ -499,6 +501,7 @@ static int geom_ensure_device(ct_geom* g) {
     if (e == hipSuccess) e = up(L.off_wch, g->wchunks.data(), g->wchunks.size() * sizeof(Chunk));
     if (e == hipSuccess) e = up(L.off_rbj, g->rbj_chunk_ptr.data(), g->rbj_chunk_ptr.size() * sizeof(int32_t));
     if (e == hipSuccess) e = up(L.off_all, g->all_entries.data(), g->all_entries.size() * sizeof(Entry));
+    if (e == hipSuccess) e = up(L.off_boxes, g->boxes.data(), g->boxes.size() * sizeof(Box));
     if (e != hipSuccess) {
         (void)hipFree(mem);
         return fail(CT_EDEVICE, "geometry upload: %s", hipGetErrorString(e));
@@ -541,6 +544,7 @@ static int geom_ensure_device(ct_geom* g) {
     g->d_all = (Entry*)(base + L.off_all);
     g->d_nnz = (unsigned long long*)(base + L.off_nnz);
     g->d_part = (double*)(base + L.off_part);
+    g->d_boxes = (Box*)(base + L.off_boxes);
     g->dbytes = L.total;
     g->device = dev;
     g->dmem = mem;
@@ -717,7 +721,39 @@ struct ct_schedule {
     int32_t* d_gptr = nullptr;
     double* d_beta = nullptr;
     Entry* d_uni = nullptr;
+    StepRec* d_steps = nullptr;         // per step (column entry), for batches
+    EpochRec* d_epochs = nullptr;       // per epoch, for batches
 };
+
+static std::vector<StepRec> sched_step_recs(const ct_schedule* s) {
+    std::vector<StepRec> v(s->cols.size());
+    for (size_t c = 0; c < v.size(); ++c) {
+        StepRec& r = v[c];
+        r.col = s->cols[c];
+        r.n_groups = s->cgp[c + 1] - s->cgp[c];
+        r.ent_off = s->step_ent_off[c];
+        r.n_ent = s->step_ent_off[c + 1] - s->step_ent_off[c];
+        r.gptr_off = s->step_gptr_off[c];
+        r.beta_off = s->cgp[c];
+        r.n_chunks = s->step_chunks[c];
+        r.pad = 0;
+    }
+    return v;
+}
+
+static std::vector<EpochRec> sched_epoch_recs(const ct_schedule* s) {
+    std::vector<EpochRec> v(s->ecp.size() - 1);
+    for (size_t e = 0; e < v.size(); ++e) {
+        EpochRec& r = v[e];
+        r.step0 = s->ecp[e];
+        r.n_steps = s->ecp[e + 1] - s->ecp[e];
+        r.uni_off = s->uni_off[e];
+        r.n_uni = s->uni_off[e + 1] - s->uni_off[e];
+        r.uni_chunks = s->uni_chunks[e];
+        r.pad = 0;
+    }
+    return v;
+}
 
 static uint64_t splitmix64(uint64_t seed, uint64_t ctr) {
     uint64_t z = seed + (ctr + 1) * 0x9E3779B97F4A7C15ull;
@@ -796,14 +832,20 @@ static int sched_ensure_device(ct_schedule* sc) {
     const size_t b_gptr = align256(std::max<size_t>(1, sc->gptr.size()) * sizeof(int32_t));
     const size_t b_beta = align256(std::max<size_t>(1, sc->beta.size()) * sizeof(double));
     const size_t b_uni = align256(std::max<size_t>(1, sc->uni.size()) * sizeof(Entry));
+    const std::vector<StepRec> steps = sched_step_recs(sc);
+    const std::vector<EpochRec> epochs = sched_epoch_recs(sc);
+    const size_t b_steps = align256(std::max<size_t>(1, steps.size()) * sizeof(StepRec));
+    const size_t b_epochs = align256(std::max<size_t>(1, epochs.size()) * sizeof(EpochRec));
     void* mem = nullptr;
-    if (hipMalloc(&mem, b_ent + b_gptr + b_beta + b_uni) != hipSuccess)
+    if (hipMalloc(&mem, b_ent + b_gptr + b_beta + b_uni + b_steps + b_epochs) != hipSuccess)
         return fail(CT_ENOMEM, "hipMalloc for schedule tables failed");
     char* base = (char*)mem;
     Entry* d_entries = (Entry*)base;
     int32_t* d_gptr = (int32_t*)(base + b_ent);
     double* d_beta = (double*)(base + b_ent + b_gptr);
     Entry* d_uni = (Entry*)(base + b_ent + b_gptr + b_beta);
+    StepRec* d_steps = (StepRec*)(base + b_ent + b_gptr + b_beta + b_uni);
+    EpochRec* d_epochs = (EpochRec*)(base + b_ent + b_gptr + b_beta + b_uni + b_steps);
     hipError_t e = hipSuccess;
     if (!sc->entries.empty())
         e = hipMemcpy(d_entries, sc->entries.data(), sc->entries.size() * sizeof(Entry), hipMemcpyHostToDevice);
@@ -813,6 +855,10 @@ static int sched_ensure_device(ct_schedule* sc) {
         e = hipMemcpy(d_beta, sc->beta.data(), sc->beta.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess && !sc->uni.empty())
         e = hipMemcpy(d_uni, sc->uni.data(), sc->uni.size() * sizeof(Entry), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !steps.empty())
+        e = hipMemcpy(d_steps, steps.data(), steps.size() * sizeof(StepRec), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !epochs.empty())
+        e = hipMemcpy(d_epochs, epochs.data(), epochs.size() * sizeof(EpochRec), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(mem);
         return fail(CT_EDEVICE, "schedule upload: %s", hipGetErrorString(e));
@@ -821,6 +867,8 @@ static int sched_ensure_device(ct_schedule* sc) {
     sc->d_gptr = d_gptr;
     sc->d_beta = d_beta;
     sc->d_uni = d_uni;
+    sc->d_steps = d_steps;
+    sc->d_epochs = d_epochs;
     sc->device = dev;
     sc->dmem = mem;
     return CT_OK;
@@ -1392,38 +1440,330 @@ extern "C" int ct_solve(ct_geom* g, const ct_solve_params* p, const float* y, fl
 // ---------------------------------------------------------------------------
 // batch
 // ---------------------------------------------------------------------------
-struct ct_batch {
-    std::vector<ct_solver*> jobs;
+// Device table (one allocation): BJob[cap], int32 ep[cap], then the prefix
+// arrays of every launch of a batch epoch.  The host keeps the authoritative
+// copy of each job's next epoch and uploads it with the table whenever the
+// job set changes; between changes only kb_advance moves the counters, in
+// step with the host's own count.
+struct BatchSlot {
+    int32_t id;
+    ct_batch_job job;
+    int32_t next;               // next epoch to run
+    int32_t n_epochs;
 };
 
-extern "C" int ct_batch_create(int32_t n_jobs, ct_solver* const* solvers, ct_batch** out) {
-    if (!out || n_jobs < 1 || !solvers) return fail(CT_EINVAL, "bad argument");
+struct BatchLaunch {
+    int phase, kind, c;
+    size_t prefix_off;          // int32 offset of the prefix array in the table
+    int blocks;
+};
+
+struct ct_batch {
+    int cap = 0;
+    int next_id = 0;
+    std::vector<BatchSlot> jobs;
+    bool dirty = true;
+    int device = -1;
+    // device table and its pinned staging copy
+    void* dmem = nullptr;
+    size_t dbytes = 0;
+    void* hmem = nullptr;
+    size_t hbytes = 0;
+    hipEvent_t staged = nullptr;    // the last upload from hmem has completed
+    bool staged_pending = false;
+    std::vector<BatchLaunch> launches;
+    // graph of one batch epoch
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool graph_valid = false;
+};
+
+static BJob make_bjob(const BatchSlot& b) {
+    const ct_solver* s = b.job.solver;
+    const ct_geom* g = s->geom;
+    const ct_schedule* sc = b.job.sched;
+    BJob J{};
+    J.G = g->G;
+    J.boxes = g->d_boxes;
+    J.z = s->z;
+    J.r = s->r;
+    J.q = s->q;
+    J.xg = s->xg;
+    J.pg = s->pg;
+    J.pq = s->pq;
+    J.mu = s->mu;
+    J.y = b.job.y;
+    J.x = b.job.x;
+    J.steps = sc->d_steps;
+    J.epochs = sc->d_epochs;
+    J.ent = sc->d_entries;
+    J.gptr = sc->d_gptr;
+    J.beta = sc->d_beta;
+    J.uni = sc->d_uni;
+    J.M = g->M;
+    J.n_epochs = (int32_t)sc->ecp.size() - 1;
+    J.sync = s->p.sync == CT_SYNC_EPOCH ? 1 : 0;
+    J.kind = g->d.kind;
+    return J;
+}
+
+// Work-groups job b needs in one phase of step index c: the most over all its
+// epochs, so that one set of launches (and one graph) serves every epoch.
+static int phase_work(const BatchSlot& b, int phase, int c) {
+    const ct_solver* s = b.job.solver;
+    const ct_geom* g = s->geom;
+    const ct_schedule* sc = b.job.sched;
+    const int E = (int)sc->ecp.size() - 1;
+    int w = 0;
+    for (int e = 0; e < E; ++e) {
+        if (phase == kPhRes) {
+            if (s->p.sync == CT_SYNC_EPOCH) w = std::max(w, (sc->uni_chunks[e] + 3) / 4);
+            continue;
+        }
+        if (c >= sc->ecp[e + 1] - sc->ecp[e]) continue;
+        const int k = sc->ecp[e] + c;
+        const int nG = sc->cgp[k + 1] - sc->cgp[k];
+        if (nG <= 0) continue;
+        const Box& box = g->boxes[sc->cols[k]];
+        int tx, ty, tz;
+        box_tiling(g, box, &tx, &ty, &tz);
+        const int vox = (box.x1 - box.x0) * (box.y1 - box.y0) * (box.z1 - box.z0);
+        const int nch = sc->step_chunks[k];
+        switch (phase) {
+            case kPhBack: w = std::max(w, nG * tx * ty * tz); break;
+            case kPhFwd: w = std::max(w, nch); break;
+            case kPhStep: w = std::max(w, nG); break;
+            default: w = std::max(w, (nch + 3) / 4 + (vox + 255) / 256); break;
+        }
+    }
+    return w;
+}
+
+static hipError_t batch_wait_staging(ct_batch* b) {
+    if (!b->staged_pending) return hipSuccess;
+    b->staged_pending = false;
+    return hipEventSynchronize(b->staged);
+}
+
+// Rebuild the job table and launch list after the job set changed, and
+// enqueue its upload on `st`.
+static int batch_rebuild(ct_batch* b, hipStream_t st) {
+    const int n = (int)b->jobs.size();
+    int cmax = 0;
+    bool any_epoch_sync = false;
+    std::vector<int> kinds;
+    for (const BatchSlot& j : b->jobs) {
+        const ct_schedule* sc = j.job.sched;
+        for (size_t e = 0; e + 1 < sc->ecp.size(); ++e) cmax = std::max(cmax, sc->ecp[e + 1] - sc->ecp[e]);
+        any_epoch_sync = any_epoch_sync || j.job.solver->p.sync == CT_SYNC_EPOCH;
+        const int k = j.job.solver->geom->d.kind;
+        if (std::find(kinds.begin(), kinds.end(), k) == kinds.end()) kinds.push_back(k);
+    }
+    std::sort(kinds.begin(), kinds.end());
+    // table: jobs, ep, prefix arrays
+    const size_t jobs_bytes = align256((size_t)std::max(n, 1) * sizeof(BJob));
+    const size_t ep_bytes = align256((size_t)std::max(n, 1) * sizeof(int32_t));
+    std::vector<int32_t> pre;
+    b->launches.clear();
+    auto add_launch = [&](int phase, int kind, int c) {
+        BatchLaunch L{phase, kind, c, pre.size(), 0};
+        int acc = 0;
+        pre.push_back(0);
+        for (const BatchSlot& j : b->jobs) {
+            const bool mine = (phase != kPhBack && phase != kPhFwd) || j.job.solver->geom->d.kind == kind;
+            acc += mine ? phase_work(j, phase, c) : 0;
+            pre.push_back(acc);
+        }
+        L.blocks = acc;
+        if (acc > 0) b->launches.push_back(L);
+        else pre.resize(L.prefix_off);
+    };
+    for (int c = 0; c < cmax; ++c) {
+        for (int k : kinds) add_launch(kPhBack, k, c);
+        for (int k : kinds) add_launch(kPhFwd, k, c);
+        add_launch(kPhStep, -1, c);
+        add_launch(kPhFin, -1, c);
+    }
+    if (any_epoch_sync) add_launch(kPhRes, -1, 0);
+    const size_t total = jobs_bytes + ep_bytes + align256(std::max<size_t>(1, pre.size()) * sizeof(int32_t));
+    HIPCHK(batch_wait_staging(b));
+    if (total > b->dbytes) {
+        // the old table may still be read by enqueued kernels
+        if (b->dmem) {
+            HIPCHK(hipStreamSynchronize(st));
+            (void)hipFree(b->dmem);
+            b->dmem = nullptr;
+            b->dbytes = 0;
+        }
+        if (hipMalloc(&b->dmem, total) != hipSuccess) return fail(CT_ENOMEM, "hipMalloc(%zu) for the batch table failed", total);
+        b->dbytes = total;
+    }
+    if (total > b->hbytes) {
+        if (b->hmem) (void)hipHostFree(b->hmem);
+        b->hmem = nullptr;
+        b->hbytes = 0;
+        if (hipHostMalloc(&b->hmem, total, hipHostMallocDefault) != hipSuccess)
+            return fail(CT_ENOMEM, "hipHostMalloc(%zu) for the batch table failed", total);
+        b->hbytes = total;
+    }
+    char* h = (char*)b->hmem;
+    std::memset(h, 0, total);
+    BJob* hj = (BJob*)h;
+    int32_t* hep = (int32_t*)(h + jobs_bytes);
+    int32_t* hpre = (int32_t*)(h + jobs_bytes + ep_bytes);
+    for (int k = 0; k < n; ++k) {
+        hj[k] = make_bjob(b->jobs[k]);
+        hep[k] = b->jobs[k].next;
+    }
+    if (!pre.empty()) std::memcpy(hpre, pre.data(), pre.size() * sizeof(int32_t));
+    HIPCHK(hipMemcpyAsync(b->dmem, b->hmem, total, hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(b->staged, st));
+    b->staged_pending = true;
+    b->dirty = false;
+    b->graph_valid = false;
+    return CT_OK;
+}
+
+static BatchArgs batch_args(const ct_batch* b, const BatchLaunch* L) {
+    const int n = (int)b->jobs.size();
+    const size_t jobs_bytes = align256((size_t)std::max(n, 1) * sizeof(BJob));
+    const size_t ep_bytes = align256((size_t)std::max(n, 1) * sizeof(int32_t));
+    char* d = (char*)b->dmem;
+    BatchArgs a{};
+    a.jobs = (const BJob*)d;
+    a.ep = (int32_t*)(d + jobs_bytes);
+    a.prefix = L ? (const int32_t*)(d + jobs_bytes + ep_bytes) + L->prefix_off : nullptr;
+    a.n_jobs = n;
+    a.c = L ? L->c : 0;
+    return a;
+}
+
+static int batch_enqueue(ct_batch* b, hipStream_t st) {
+    for (const BatchLaunch& L : b->launches)
+        HIPCHK(launch_batch(L.phase, L.kind, batch_args(b, &L), L.blocks, st));
+    HIPCHK(launch_batch_advance(batch_args(b, nullptr), st));
+    return CT_OK;
+}
+
+static void batch_drop_graph(ct_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    b->graph_valid = false;
+}
+
+extern "C" int ct_batch_create(int32_t capacity, ct_batch** out) {
+    if (!out) return fail(CT_EINVAL, "NULL argument");
     *out = nullptr;
-    for (int k = 0; k < n_jobs; ++k)
-        if (!solvers[k]) return fail(CT_EINVAL, "solver %d is NULL", k);
+    if (capacity < 1 || capacity > kMaxBatch) return fail(CT_EINVAL, "capacity must lie in [1, %d]", kMaxBatch);
     ct_batch* b = new (std::nothrow) ct_batch();
     if (!b) return fail(CT_ENOMEM, "host allocation failed");
-    b->jobs.assign(solvers, solvers + n_jobs);
+    b->cap = capacity;
+    if (hipGetDevice(&b->device) != hipSuccess || hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) {
+        delete b;
+        return fail(CT_EDEVICE, "no HIP device");
+    }
     *out = b;
     return CT_OK;
 }
 
-extern "C" void ct_batch_destroy(ct_batch* b) { delete b; }
+extern "C" void ct_batch_destroy(ct_batch* b) {
+    if (!b) return;
+    (void)batch_wait_staging(b);
+    batch_drop_graph(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->dmem) (void)hipFree(b->dmem);
+    if (b->hmem) (void)hipHostFree(b->hmem);
+    if (b->staged) (void)hipEventDestroy(b->staged);
+    delete b;
+}
 
-extern "C" int ct_batch_epoch(ct_batch* b, const ct_schedule* const* scheds, const int32_t* epochs,
-                              const float* const* ys, float* const* xs, void* stream) {
-    if (!b || !scheds || !epochs || !ys || !xs) return fail(CT_EINVAL, "NULL argument");
-    const int n = (int)b->jobs.size();
-    for (int k = 0; k < n; ++k) {
-        if (epochs[k] < 0) continue;
-        if (!scheds[k] || !ys[k] || !xs[k]) return fail(CT_EINVAL, "job %d: NULL argument", k);
-        if (epochs[k] >= (int)scheds[k]->ecp.size() - 1) return fail(CT_EINVAL, "job %d: epoch out of range", k);
+extern "C" int ct_batch_add(ct_batch* b, const ct_batch_job* job, int32_t* id) {
+    if (!b || !job || !id) return fail(CT_EINVAL, "NULL argument");
+    if (!job->solver || !job->sched || !job->y || !job->x) return fail(CT_EINVAL, "job has a NULL member");
+    if ((int)b->jobs.size() >= b->cap) return fail(CT_EINVAL, "batch is full (%d jobs)", b->cap);
+    ct_solver* s = job->solver;
+    if (job->sched->geom != s->geom) return fail(CT_EINVAL, "schedule was built for another geometry");
+    const int E = (int)job->sched->ecp.size() - 1;
+    if (job->epoch < 0 || job->epoch > E) return fail(CT_EINVAL, "first epoch %d out of range [0, %d]", job->epoch, E);
+    for (const BatchSlot& j : b->jobs) {
+        if (j.job.solver == s) return fail(CT_EINVAL, "solver already in the batch");
+        if (j.job.x == job->x) return fail(CT_EINVAL, "x already used by job %d", j.id);
     }
-    for (int k = 0; k < n; ++k) {
-        if (epochs[k] < 0) continue;
-        int rc = ct_block_epoch(b->jobs[k], scheds[k], epochs[k], ys[k], xs[k], stream);
-        if (rc) return rc;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
+        return fail(CT_EINVAL, "batch lives on device %d, current is %d", b->device, dev);
+    int rc = check_device(s->geom);
+    if (rc) return rc;
+    if ((rc = sched_ensure_device(const_cast<ct_schedule*>(job->sched)))) return rc;
+    BatchSlot sl{};
+    sl.id = b->next_id++;
+    sl.job = *job;
+    sl.next = job->epoch;
+    sl.n_epochs = E;
+    b->jobs.push_back(sl);
+    b->dirty = true;
+    *id = sl.id;
+    return CT_OK;
+}
+
+extern "C" int ct_batch_remove(ct_batch* b, int32_t id) {
+    if (!b) return fail(CT_EINVAL, "NULL batch");
+    for (size_t k = 0; k < b->jobs.size(); ++k)
+        if (b->jobs[k].id == id) {
+            b->jobs.erase(b->jobs.begin() + (long)k);
+            b->dirty = true;
+            return CT_OK;
+        }
+    return fail(CT_EINVAL, "no job %d in the batch", id);
+}
+
+extern "C" int ct_batch_job_epoch(const ct_batch* b, int32_t id, int32_t* epoch) {
+    if (!b || !epoch) return fail(CT_EINVAL, "NULL argument");
+    for (const BatchSlot& j : b->jobs)
+        if (j.id == id) {
+            *epoch = j.next;
+            return CT_OK;
+        }
+    return fail(CT_EINVAL, "no job %d in the batch", id);
+}
+
+extern "C" int ct_batch_epoch(ct_batch* b, int32_t flags, int32_t* ran, void* stream) {
+    if (!b) return fail(CT_EINVAL, "NULL batch");
+    if (flags & ~CT_BATCH_GRAPH) return fail(CT_EINVAL, "unknown flags 0x%x", flags);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
+        return fail(CT_EINVAL, "batch lives on device %d, current is %d", b->device, dev);
+    hipStream_t st = (hipStream_t)stream;
+    int active = 0;
+    for (const BatchSlot& j : b->jobs) active += j.next < j.n_epochs ? 1 : 0;
+    if (ran) *ran = active;
+    if (active == 0) return CT_OK;
+    int rc;
+    if (b->dirty && (rc = batch_rebuild(b, st))) return rc;
+    if (flags & CT_BATCH_GRAPH) {
+        if (!b->graph_valid) {
+            batch_drop_graph(b);
+            if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+            HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+            rc = batch_enqueue(b, b->cap_stream);
+            hipGraph_t graph = nullptr;
+            const hipError_t ec = hipStreamEndCapture(b->cap_stream, &graph);
+            if (rc) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (ec != hipSuccess) return fail(CT_EDEVICE, "graph capture: %s", hipGetErrorString(ec));
+            const hipError_t ei = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ei != hipSuccess) return fail(CT_EDEVICE, "graph instantiate: %s", hipGetErrorString(ei));
+            b->graph_valid = true;
+        }
+        HIPCHK(hipGraphLaunch(b->exec, st));
+    } else {
+        if ((rc = batch_enqueue(b, st))) return rc;
     }
+    for (BatchSlot& j : b->jobs)
+        if (j.next < j.n_epochs) ++j.next;
     return CT_OK;
 }
 

@@ -101,9 +101,10 @@ struct Box {
 };
 
 // Forward launch: rays of the entries' row blocks through box J.
-struct FwdArgs {
+struct FwdCore {
+    static constexpr bool kInl = false;
     Box box;
-    const Entry* ent;             // device array or nullptr (use inline)
+    const Entry* ent;             // entries (device); FwdArgs may pass them inline instead
     int32_t n_ent;
     int32_t n_chunks;
     int32_t flags;                // CT_ACCUMULATE
@@ -119,12 +120,15 @@ struct FwdArgs {
     unsigned long long* nnz;      // count: [m][n]
     int32_t n_cols, col;          // count: column count and this column
     float tau;                    // count threshold
-    Entry inl[kMaxInline];
+};
+struct FwdArgs : FwdCore {
+    static constexpr bool kInl = true;
+    Entry inl[kMaxInline];        // used when ent is nullptr
 };
 
-// Back-projection launch: blockIdx.y = group; a group's row blocks are
-// entries [gptr[g], gptr[g+1]).
-struct BackArgs {
+// Back-projection launch: group g's row blocks are entries [gptr[g], gptr[g+1]).
+struct BackCore {
+    static constexpr bool kInl = false;
     Box box;
     const Entry* ent;
     const int32_t* gptr;          // device or nullptr (single group of all entries)
@@ -139,6 +143,9 @@ struct BackArgs {
     int32_t vox_J;
     int32_t xg_stride;
     double* partial;              // fused: [group][tiles]
+};
+struct BackArgs : BackCore {
+    static constexpr bool kInl = true;
     Entry inl[kMaxInline];
 };
 
@@ -157,6 +164,7 @@ struct StepArgs {
 };
 
 struct FinArgs {
+    static constexpr bool kInl = false;
     const Entry* ent;
     int32_t n_ent;
     int32_t n_chunks;
@@ -178,11 +186,11 @@ struct FinArgs {
     const float2* xg;
     float* x;
     int32_t nx, ny;
-    Entry inl[1];
 };
 
 // Residual refresh over the rays of a list of row blocks.
 struct ResArgs {
+    static constexpr bool kInl = false;
     const Entry* ent;
     int32_t n_ent;
     const float* z;
@@ -190,8 +198,71 @@ struct ResArgs {
     float* r;
     int64_t M;
     int32_t n_cols;
-    Entry inl[1];
 };
+
+// ---------------------------------------------------------------------------
+// batches: several independent jobs advanced by the same launches
+// ---------------------------------------------------------------------------
+constexpr int kMaxBatch = 256;     // jobs in one batch
+
+// One column-block step of a schedule as the batched kernels read it.
+struct StepRec {
+    int32_t col;        // column block J
+    int32_t n_groups;
+    int32_t ent_off;    // the step's entries: ent[ent_off, ent_off + n_ent)
+    int32_t n_ent;
+    int32_t gptr_off;   // group -> entry offsets: gptr[gptr_off, gptr_off + n_groups]
+    int32_t beta_off;   // beta[beta_off, beta_off + n_groups)
+    int32_t n_chunks;   // windowed chunks of the step
+    int32_t pad;
+};
+
+struct EpochRec {
+    int32_t step0, n_steps;              // steps[step0, step0 + n_steps)
+    int32_t uni_off, n_uni, uni_chunks;  // row blocks touched in the epoch
+    int32_t pad;
+};
+
+// A job of a batch: geometry, solver buffers, data and schedule, all device
+// pointers.  The job's next epoch is the batch's counter ep[k].
+struct BJob {
+    DGeom G;
+    const Box* boxes;             // [n_cols]
+    float* z;
+    float* r;
+    float* q;
+    float2* xg;
+    double* pg;
+    double* pq;
+    double* mu;
+    const float* y;
+    float* x;
+    const StepRec* steps;
+    const EpochRec* epochs;
+    const Entry* ent;
+    const int32_t* gptr;
+    const double* beta;
+    const Entry* uni;
+    int64_t M;
+    int32_t n_epochs;
+    int32_t sync;                 // 0 column, 1 epoch
+    int32_t kind;
+    int32_t pad;
+};
+
+// One phase of one step index for every job of a batch.  Work-group b
+// belongs to the job k with prefix[k] <= b < prefix[k + 1] (local index
+// b - prefix[k]); jobs whose current epoch has no such step, or that have
+// run all their epochs, return at once.
+struct BatchArgs {
+    const BJob* jobs;
+    int32_t* ep;                  // per-job next epoch
+    const int32_t* prefix;        // [n_jobs + 1]
+    int32_t n_jobs;
+    int32_t c;                    // step index within the epoch
+};
+
+enum { kPhBack = 0, kPhFwd = 1, kPhStep = 2, kPhFin = 3, kPhRes = 4 };
 
 hipError_t launch_fwd(const DGeom& G, const FwdArgs& a, hipStream_t st);
 hipError_t launch_back(const DGeom& G, const BackArgs& a, int n_groups, hipStream_t st);
@@ -200,6 +271,10 @@ hipError_t launch_finalize(const DGeom& G, const FinArgs& f, int vox_blocks, hip
 hipError_t launch_residual(const DGeom& G, const ResArgs& a, int n_chunks, hipStream_t st);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
+// Batched phase launch: `kind` selects the projector instantiation (back and
+// forward phases); `blocks` is prefix[n_jobs].
+hipError_t launch_batch(int phase, int kind, const BatchArgs& b, int blocks, hipStream_t st);
+hipError_t launch_batch_advance(const BatchArgs& b, hipStream_t st);
 hipError_t launch_resnorm(const float* y, const float* p, int64_t n, double* part, int nblk,
                           hipStream_t st);
 

@@ -71,9 +71,13 @@ __device__ __forceinline__ T ldu(const T* base, unsigned i) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(T));
 }
 
+// Entry i of a launch: inline in the kernel arguments (primitives) or in
+// device memory.  The choice is a compile-time property of the argument type
+// so that no pointer select makes the compiler copy the arguments to scratch.
 template <class A>
 __device__ __forceinline__ Entry get_entry(const A& a, int i) {
-    return a.ent ? a.ent[i] : a.inl[i];
+    if constexpr (A::kInl) return a.inl[i];
+    else return a.ent[i];
 }
 
 // Entry that owns launch chunk `bid` (entries sorted by chunk_prefix):
@@ -147,8 +151,9 @@ __device__ __forceinline__ double strided_sum256(const double* p, int lo, int hi
     return t;
 }
 
-template <int KIND, int MODE>
-__global__ __launch_bounds__(256) void k_fwd(DGeom G, FwdArgs a) {
+// Forward work-group `bid` of a launch (chunk bid of the entries' rays).
+template <int KIND, int MODE, class FA>
+__device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int bid) {
     constexpr int DIMS = (KIND == kCone) ? 3 : 2;
     constexpr bool DIVERGENT = (KIND != kPar2D);
     constexpr int U = 4;                       // segments formed before their gathers
@@ -156,7 +161,6 @@ __global__ __launch_bounds__(256) void k_fwd(DGeom G, FwdArgs a) {
     constexpr int K = (MODE == 2) ? 1 : kSplit;
     __shared__ float pacc[K][kChunk], pacc2[K][kChunk];
 
-    const int bid = blockIdx.x;
     const int ei = find_entry(a, bid);
     const Entry en = get_entry(a, ei);
     const int rb = en.rb;
@@ -395,6 +399,16 @@ __global__ __launch_bounds__(256) void k_fwd(DGeom G, FwdArgs a) {
     }
 }
 
+template <int KIND, int MODE>
+__global__ __launch_bounds__(256) void k_fwd(DGeom G, FwdCore a) {
+    fwd_body<KIND, MODE>(G, a, blockIdx.x);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_fwd_inl(DGeom G, FwdArgs a) {
+    fwd_body<KIND, 0>(G, a, blockIdx.x);
+}
+
 // ----------------------------------------------------------------------------
 // K1: gather back-projection, 2D
 // ----------------------------------------------------------------------------
@@ -489,14 +503,15 @@ __device__ __forceinline__ void view_params(const DGeom& G, const Tile& tl, doub
     P.W = (float)fmin(W, 1e9) + 2e-3f + 1e-6f * fabsf((float)bc);
 }
 
-template <int KIND>
-__global__ __launch_bounds__(256) void k_back2(DGeom G, BackArgs a) {
+// Back-projection work-group for tile `tile` (of n_tiles) of group gi.
+template <int KIND, class BA>
+__device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const int gi, const int tile,
+                                           const int n_tiles) {
     __shared__ ViewP vp[4][64];
     __shared__ float red[4][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wu = __builtin_amdgcn_readfirstlane(w);
-    const int gi = blockIdx.y;
-    const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int lx = lane & (kTile2 - 1), ly = lane / kTile2;
     const int ix = a.box.x0 + tx * kTile2 + lx, iy = a.box.y0 + ty * kTile2 + ly;
     const bool valid = ix < a.box.x1 && iy < a.box.y1;
@@ -591,7 +606,7 @@ __global__ __launch_bounds__(256) void k_back2(DGeom G, BackArgs a) {
                 base[xg_copy(nxJ, nyJ, 1) + lx * nyJ + ly] = v;
             }
             const double t = wave_sum(valid ? (double)gsum * (double)gsum : 0.0);
-            if (lane == 0) a.partial[(size_t)gi * gridDim.x + blockIdx.x] = t;
+            if (lane == 0) a.partial[(size_t)gi * n_tiles + tile] = t;
         }
     } else if (w == 0 && valid) {
         const size_t gix = (size_t)iy * G.nx + ix;
@@ -599,13 +614,18 @@ __global__ __launch_bounds__(256) void k_back2(DGeom G, BackArgs a) {
     }
 }
 
+template <int KIND, class BA>
+__global__ __launch_bounds__(256) void k_back2(DGeom G, BA a) {
+    back2_body<KIND>(G, a, blockIdx.y, blockIdx.x, gridDim.x);
+}
+
 // ----------------------------------------------------------------------------
 // K1: gather back-projection, 3D cone
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_back3(DGeom G, BackArgs a) {
+template <class BA>
+__device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const int gi, const int bt,
+                                           const int n_tiles) {
     __shared__ double sh[4];
-    const int gi = blockIdx.y;
-    const int bt = blockIdx.x;
     const int tx = bt % a.tiles_x;
     const int ty = (bt / a.tiles_x) % a.tiles_y;
     const int tz = bt / (a.tiles_x * a.tiles_y);
@@ -699,32 +719,37 @@ __global__ __launch_bounds__(256) void k_back3(DGeom G, BackArgs a) {
         }
         const double p = valid ? (double)acc * (double)acc : 0.0;
         const double t = block_sum256(p, sh);
-        if (threadIdx.x == 0) a.partial[(size_t)gi * gridDim.x + blockIdx.x] = t;
+        if (threadIdx.x == 0) a.partial[(size_t)gi * n_tiles + bt] = t;
     } else if (valid) {
         a.g[gix] = (a.flags & 1) ? a.g[gix] + acc : acc;
     }
+}
+
+template <class BA>
+__global__ __launch_bounds__(256) void k_back3(DGeom G, BA a) {
+    back3_body(G, a, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // ----------------------------------------------------------------------------
 // K3: step sizes mu = beta ||g||^2 / ||A g||^2 (Eq. 11, relaxed), one
 // work-group per group, fixed-order float64 sums of the partials
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_step(StepArgs s) {
+__device__ __forceinline__ void step_body(const StepArgs& s, const int g, const int n_groups) {
     __shared__ double sh[4];
-    const int g = blockIdx.x;
     const double gg = strided_sum256(s.pg, g * s.n_tiles, (g + 1) * s.n_tiles, sh);
     const int c0 = s.ent[s.gptr[g]].chunk_prefix;
-    const int c1 = (g + 1 < (int)gridDim.x) ? s.ent[s.gptr[g + 1]].chunk_prefix : s.n_chunks;
+    const int c1 = (g + 1 < n_groups) ? s.ent[s.gptr[g + 1]].chunk_prefix : s.n_chunks;
     const double qq = strided_sum256(s.pq, c0, c1, sh);
     if (threadIdx.x == 0) s.mu[g] = (gg > 0.0 && qq > 0.0) ? s.beta[g] * gg / qq : 0.0;
 }
+
+__global__ __launch_bounds__(256) void k_step(StepArgs s) { step_body(s, blockIdx.x, gridDim.x); }
 
 // ----------------------------------------------------------------------------
 // K4: finalize a column-block step
 // ----------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_finalize(DGeom G, FinArgs f) {
-    const int bid = blockIdx.x;
+__device__ __forceinline__ void fin_body(const DGeom& G, const FinArgs& f, const int bid) {
     const int ray_blocks = (f.n_chunks + 3) / 4;
     if (bid < ray_blocks) {
         const int c = bid * 4 + (threadIdx.x >> 6);
@@ -761,12 +786,15 @@ __global__ __launch_bounds__(256) void k_finalize(DGeom G, FinArgs f) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_finalize(DGeom G, FinArgs f) { fin_body(G, f, blockIdx.x); }
+
 // ----------------------------------------------------------------------------
 // K5: residual refresh over the rays of a list of row blocks
 // ----------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_residual(DGeom G, ResArgs a, int n_chunks) {
-    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+__device__ __forceinline__ void res_body(const DGeom& G, const ResArgs& a, const int bid,
+                                         const int n_chunks) {
+    const int c = bid * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (c >= n_chunks) return;
     const int ei = find_entry(a, c);
@@ -778,6 +806,199 @@ __global__ __launch_bounds__(256) void k_residual(DGeom G, ResArgs a, int n_chun
     float s = 0.f;
     for (int j = 0; j < a.n_cols; ++j) s += a.z[(size_t)j * a.M + ray];
     a.r[ray] = a.y[ray] - s;
+}
+
+__global__ __launch_bounds__(256) void k_residual(DGeom G, ResArgs a, int n_chunks) {
+    res_body(G, a, blockIdx.x, n_chunks);
+}
+
+// ----------------------------------------------------------------------------
+// batched phases: one launch advances the same phase of every job of a batch.
+// Each work-group finds its job from the per-job work-group prefix, rebuilds
+// that job's launch arguments from the device job table and the job's own
+// epoch counter, and runs the same body as the single-job kernel, so a job's
+// results are the same bits in a batch as alone.
+// ----------------------------------------------------------------------------
+// Owner of work-group b: the last k with prefix[k] <= b (prefix is
+// non-decreasing, so jobs without work in this phase are skipped).  Every
+// lane of the wave must be active.
+__device__ __forceinline__ int batch_job(const BatchArgs& B, const int b) {
+    int cnt = 0;
+    for (int base = 0; base < B.n_jobs; base += 64) {
+        const int i = base + (int)(threadIdx.x & 63);
+        const bool le = i < B.n_jobs && B.prefix[i] <= b;
+        cnt += __popcll(__ballot(le));
+    }
+    return __builtin_amdgcn_readfirstlane(cnt - 1);
+}
+
+// Step c of job k's current epoch; false once the job has run all its epochs
+// or its epoch has fewer steps.
+__device__ __forceinline__ bool batch_step(const BatchArgs& B, const int k, const BJob& J, StepRec& sr) {
+    const int e = B.ep[k];
+    if (e < 0 || e >= J.n_epochs) return false;
+    const EpochRec er = J.epochs[e];
+    if (B.c >= er.n_steps) return false;
+    sr = J.steps[er.step0 + B.c];
+    return sr.n_groups > 0;            // a column without groups is skipped, as alone
+}
+
+__device__ __forceinline__ void box_tiles(const Box& b, const int dims, int& tx, int& ty, int& tz) {
+    if (dims == 2) {
+        tx = (b.x1 - b.x0 + kTile2 - 1) / kTile2;
+        ty = (b.y1 - b.y0 + kTile2 - 1) / kTile2;
+        tz = 1;
+    } else {
+        tx = (b.x1 - b.x0 + kTile3x - 1) / kTile3x;
+        ty = (b.y1 - b.y0 + kTile3y - 1) / kTile3y;
+        tz = (b.z1 - b.z0 + kTile3z - 1) / kTile3z;
+    }
+}
+
+__device__ __forceinline__ int box_vox(const Box& b) {
+    return (b.x1 - b.x0) * (b.y1 - b.y0) * (b.z1 - b.z0);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void kb_back(BatchArgs B) {
+    const int k = batch_job(B, blockIdx.x);
+    const int L = blockIdx.x - B.prefix[k];
+    const BJob& J = B.jobs[k];
+    StepRec sr;
+    if (!batch_step(B, k, J, sr)) return;
+    const DGeom G = J.G;
+    BackCore a{};
+    a.box = J.boxes[sr.col];
+    box_tiles(a.box, G.dims, a.tiles_x, a.tiles_y, a.tiles_z);
+    const int nt = a.tiles_x * a.tiles_y * a.tiles_z;
+    const int gi = L / nt, tile = L - gi * nt;
+    if (gi >= sr.n_groups) return;
+    a.ent = J.ent + sr.ent_off;
+    a.gptr = J.gptr + sr.gptr_off;
+    a.n_ent = sr.n_ent;
+    a.fused = 1;
+    a.r = J.r;
+    a.x = J.x;
+    a.xg = J.xg;
+    a.vox_J = box_vox(a.box);
+    a.xg_stride = xg_size(a.box.x1 - a.box.x0, a.box.y1 - a.box.y0, a.box.z1 - a.box.z0);
+    a.partial = J.pg;
+    if constexpr (KIND == kCone) back3_body(G, a, gi, tile, nt);
+    else back2_body<KIND>(G, a, gi, tile, nt);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void kb_fwd(BatchArgs B) {
+    const int k = batch_job(B, blockIdx.x);
+    const int L = blockIdx.x - B.prefix[k];
+    const BJob& J = B.jobs[k];
+    StepRec sr;
+    if (!batch_step(B, k, J, sr)) return;
+    if (L >= sr.n_chunks) return;
+    const DGeom G = J.G;
+    FwdCore a{};
+    a.box = J.boxes[sr.col];
+    a.ent = J.ent + sr.ent_off;
+    a.n_ent = sr.n_ent;
+    a.n_chunks = sr.n_chunks;
+    a.mode = 1;
+    a.windowed = 1;
+    a.col = sr.col;
+    a.xg = J.xg;
+    a.vox_J = box_vox(a.box);
+    a.xg_stride = xg_size(a.box.x1 - a.box.x0, a.box.y1 - a.box.y0, a.box.z1 - a.box.z0);
+    a.out = J.z + (size_t)sr.col * (size_t)J.M;
+    a.q = J.q;
+    a.partial = J.pq;
+    fwd_body<KIND, 1>(G, a, L);
+}
+
+__global__ __launch_bounds__(256) void kb_step(BatchArgs B) {
+    const int k = batch_job(B, blockIdx.x);
+    const int L = blockIdx.x - B.prefix[k];
+    const BJob& J = B.jobs[k];
+    StepRec sr;
+    if (!batch_step(B, k, J, sr)) return;
+    if (L >= sr.n_groups) return;
+    const Box box = J.boxes[sr.col];
+    int tx, ty, tz;
+    box_tiles(box, J.G.dims, tx, ty, tz);
+    StepArgs a{};
+    a.ent = J.ent + sr.ent_off;
+    a.gptr = J.gptr + sr.gptr_off;
+    a.n_chunks = sr.n_chunks;
+    a.n_tiles = tx * ty * tz;
+    a.pg = J.pg;
+    a.pq = J.pq;
+    a.beta = J.beta + sr.beta_off;
+    a.mu = J.mu;
+    step_body(a, L, sr.n_groups);
+}
+
+__global__ __launch_bounds__(256) void kb_finalize(BatchArgs B) {
+    const int k = batch_job(B, blockIdx.x);
+    const int L = blockIdx.x - B.prefix[k];
+    const BJob& J = B.jobs[k];
+    StepRec sr;
+    if (!batch_step(B, k, J, sr)) return;
+    const Box box = J.boxes[sr.col];
+    const int vox = box_vox(box);
+    if (L >= (sr.n_chunks + 3) / 4 + (vox + 255) / 256) return;
+    const DGeom G = J.G;
+    FinArgs f{};
+    f.ent = J.ent + sr.ent_off;
+    f.n_ent = sr.n_ent;
+    f.n_chunks = sr.n_chunks;
+    f.mu = J.mu;
+    f.q = J.q;
+    f.z = J.z;
+    f.zJ = J.z + (size_t)sr.col * (size_t)J.M;
+    f.y = J.y;
+    f.r = J.r;
+    f.M = J.M;
+    f.n_cols = G.n_cols;
+    f.refresh = J.sync == 0 ? 1 : 0;
+    f.col = sr.col;
+    f.box = box;
+    f.vox_J = vox;
+    f.xg_stride = xg_size(box.x1 - box.x0, box.y1 - box.y0, box.z1 - box.z0);
+    f.n_groups = sr.n_groups;
+    f.xg = J.xg;
+    f.x = J.x;
+    f.nx = G.nx;
+    f.ny = G.ny;
+    fin_body(G, f, L);
+}
+
+// Epoch-synchronous residual refresh over the epoch's touched row blocks
+// (launched once per epoch, with c = 0).
+__global__ __launch_bounds__(256) void kb_residual(BatchArgs B) {
+    const int k = batch_job(B, blockIdx.x);
+    const int L = blockIdx.x - B.prefix[k];
+    const BJob& J = B.jobs[k];
+    if (J.sync != 1) return;
+    const int e = B.ep[k];
+    if (e < 0 || e >= J.n_epochs) return;
+    const EpochRec er = J.epochs[e];
+    if (L * 4 >= er.uni_chunks) return;
+    const DGeom G = J.G;
+    ResArgs a{};
+    a.ent = J.uni + er.uni_off;
+    a.n_ent = er.n_uni;
+    a.z = J.z;
+    a.y = J.y;
+    a.r = J.r;
+    a.M = J.M;
+    a.n_cols = G.n_cols;
+    res_body(G, a, L, er.uni_chunks);
+}
+
+// End of a batch epoch: every job that had an epoch left moves to the next.
+__global__ void kb_advance(BatchArgs B) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= B.n_jobs) return;
+    const int e = B.ep[k];
+    if (e >= 0 && e < B.jobs[k].n_epochs) B.ep[k] = e + 1;
 }
 
 // ----------------------------------------------------------------------------
@@ -818,17 +1039,33 @@ __global__ __launch_bounds__(256) void k_resnorm(const float* y, const float* p,
 template <int MODE>
 static hipError_t launch_fwd_mode(const DGeom& G, const FwdArgs& a, hipStream_t st) {
     dim3 grid(a.n_chunks), block(MODE == 2 ? kChunk : kChunk * kSplit);
+    const FwdCore c = a;
     switch (G.kind) {
-        case kPar2D: hipLaunchKernelGGL((k_fwd<kPar2D, MODE>), grid, block, 0, st, G, a); break;
-        case kFanFlat: hipLaunchKernelGGL((k_fwd<kFanFlat, MODE>), grid, block, 0, st, G, a); break;
-        case kFanCurved: hipLaunchKernelGGL((k_fwd<kFanCurved, MODE>), grid, block, 0, st, G, a); break;
-        default: hipLaunchKernelGGL((k_fwd<kCone, MODE>), grid, block, 0, st, G, a); break;
+        case kPar2D: hipLaunchKernelGGL((k_fwd<kPar2D, MODE>), grid, block, 0, st, G, c); break;
+        case kFanFlat: hipLaunchKernelGGL((k_fwd<kFanFlat, MODE>), grid, block, 0, st, G, c); break;
+        case kFanCurved: hipLaunchKernelGGL((k_fwd<kFanCurved, MODE>), grid, block, 0, st, G, c); break;
+        default: hipLaunchKernelGGL((k_fwd<kCone, MODE>), grid, block, 0, st, G, c); break;
+    }
+    return hipGetLastError();
+}
+
+static hipError_t launch_fwd_inline(const DGeom& G, const FwdArgs& a, hipStream_t st) {
+    dim3 grid(a.n_chunks), block(kChunk * kSplit);
+    switch (G.kind) {
+        case kPar2D: hipLaunchKernelGGL(k_fwd_inl<kPar2D>, grid, block, 0, st, G, a); break;
+        case kFanFlat: hipLaunchKernelGGL(k_fwd_inl<kFanFlat>, grid, block, 0, st, G, a); break;
+        case kFanCurved: hipLaunchKernelGGL(k_fwd_inl<kFanCurved>, grid, block, 0, st, G, a); break;
+        default: hipLaunchKernelGGL(k_fwd_inl<kCone>, grid, block, 0, st, G, a); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_fwd(const DGeom& G, const FwdArgs& a, hipStream_t st) {
     if (a.n_chunks <= 0) return hipSuccess;
+    if (!a.ent) {
+        if (a.mode != 0) return hipErrorInvalidValue;     // inline entries: single mode only
+        return launch_fwd_inline(G, a, st);
+    }
     if (a.mode == 0) return launch_fwd_mode<0>(G, a, st);
     if (a.mode == 1) return launch_fwd_mode<1>(G, a, st);
     return launch_fwd_mode<2>(G, a, st);
@@ -838,11 +1075,21 @@ hipError_t launch_back(const DGeom& G, const BackArgs& a, int n_groups, hipStrea
     const int nt = a.tiles_x * a.tiles_y * a.tiles_z;
     if (nt <= 0 || n_groups <= 0) return hipSuccess;
     dim3 grid(nt, n_groups), block(256);
+    if (!a.ent) {
+        switch (G.kind) {
+            case kPar2D: hipLaunchKernelGGL((k_back2<kPar2D, BackArgs>), grid, block, 0, st, G, a); break;
+            case kFanFlat: hipLaunchKernelGGL((k_back2<kFanFlat, BackArgs>), grid, block, 0, st, G, a); break;
+            case kFanCurved: hipLaunchKernelGGL((k_back2<kFanCurved, BackArgs>), grid, block, 0, st, G, a); break;
+            default: hipLaunchKernelGGL(k_back3<BackArgs>, grid, block, 0, st, G, a); break;
+        }
+        return hipGetLastError();
+    }
+    const BackCore c = a;
     switch (G.kind) {
-        case kPar2D: hipLaunchKernelGGL(k_back2<kPar2D>, grid, block, 0, st, G, a); break;
-        case kFanFlat: hipLaunchKernelGGL(k_back2<kFanFlat>, grid, block, 0, st, G, a); break;
-        case kFanCurved: hipLaunchKernelGGL(k_back2<kFanCurved>, grid, block, 0, st, G, a); break;
-        default: hipLaunchKernelGGL(k_back3, grid, block, 0, st, G, a); break;
+        case kPar2D: hipLaunchKernelGGL((k_back2<kPar2D, BackCore>), grid, block, 0, st, G, c); break;
+        case kFanFlat: hipLaunchKernelGGL((k_back2<kFanFlat, BackCore>), grid, block, 0, st, G, c); break;
+        case kFanCurved: hipLaunchKernelGGL((k_back2<kFanCurved, BackCore>), grid, block, 0, st, G, c); break;
+        default: hipLaunchKernelGGL(k_back3<BackCore>, grid, block, 0, st, G, c); break;
     }
     return hipGetLastError();
 }
@@ -863,6 +1110,37 @@ hipError_t launch_finalize(const DGeom& G, const FinArgs& f, int vox_blocks, hip
 hipError_t launch_residual(const DGeom& G, const ResArgs& a, int n_chunks, hipStream_t st) {
     if (n_chunks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_residual, dim3((n_chunks + 3) / 4), dim3(256), 0, st, G, a, n_chunks);
+    return hipGetLastError();
+}
+
+template <int KIND>
+static hipError_t launch_batch_kind(int phase, const BatchArgs& b, int blocks, hipStream_t st) {
+    if (phase == kPhBack) hipLaunchKernelGGL(kb_back<KIND>, dim3(blocks), dim3(256), 0, st, b);
+    else hipLaunchKernelGGL(kb_fwd<KIND>, dim3(blocks), dim3(kChunk * kSplit), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(int phase, int kind, const BatchArgs& b, int blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    switch (phase) {
+        case kPhBack:
+        case kPhFwd:
+            switch (kind) {
+                case kPar2D: return launch_batch_kind<kPar2D>(phase, b, blocks, st);
+                case kFanFlat: return launch_batch_kind<kFanFlat>(phase, b, blocks, st);
+                case kFanCurved: return launch_batch_kind<kFanCurved>(phase, b, blocks, st);
+                default: return launch_batch_kind<kCone>(phase, b, blocks, st);
+            }
+        case kPhStep: hipLaunchKernelGGL(kb_step, dim3(blocks), dim3(256), 0, st, b); break;
+        case kPhFin: hipLaunchKernelGGL(kb_finalize, dim3(blocks), dim3(256), 0, st, b); break;
+        default: hipLaunchKernelGGL(kb_residual, dim3(blocks), dim3(256), 0, st, b); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(const BatchArgs& b, hipStream_t st) {
+    if (b.n_jobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_advance, dim3((b.n_jobs + 255) / 256), dim3(256), 0, st, b);
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ CT_EINVAL, CT_ENOMEM, CT_EDEVICE, CT_EUNSUPPORTED = -1, -2, -3, -4
 CT_ACCUMULATE = 1
 CT_SAMPLE_DENSITY, CT_SAMPLE_UNIFORM, CT_SAMPLE_MIXED = 0, 1, 2
 CT_SYNC_COLUMN, CT_SYNC_EPOCH = 0, 1
+CT_BATCH_GRAPH = 1
 
 EXPORTS = (
     "ct_geom_create", "ct_geom_destroy", "ct_geom_get_info", "ct_geom_block_nnz",
@@ -30,7 +31,8 @@ EXPORTS = (
     "ct_solver_workspace_bytes", "ct_solver_create", "ct_solver_destroy", "ct_solver_reset",
     "ct_block_epoch", "ct_solver_state", "ct_true_residual", "ct_solve",
     "ct_solver_profile", "ct_solver_profile_read",
-    "ct_batch_create", "ct_batch_destroy", "ct_batch_epoch", "ct_job_footprint",
+    "ct_batch_create", "ct_batch_destroy", "ct_batch_add", "ct_batch_remove", "ct_batch_epoch",
+    "ct_batch_job_epoch", "ct_job_footprint",
     "ct_last_error",
 )
 
@@ -74,6 +76,10 @@ class ct_kernel_times(ctypes.Structure):
 
 
 KERNEL_NAMES = ("back", "fwd", "step", "finalize", "residual")
+
+
+class ct_batch_job(ctypes.Structure):
+    _fields_ = [("solver", P), ("sched", P), ("y", P), ("x", P), ("epoch", i32)]
 
 
 class ct_solver_params(ctypes.Structure):
@@ -122,9 +128,12 @@ def lib():
             "ct_solve": [P, ctypes.POINTER(ct_solve_params), P, P, ctypes.POINTER(ct_solve_stats), P],
             "ct_solver_profile": [P, i32],
             "ct_solver_profile_read": [P, ctypes.POINTER(ct_kernel_times)],
-            "ct_batch_create": [i32, P, ctypes.POINTER(P)],
+            "ct_batch_create": [i32, ctypes.POINTER(P)],
             "ct_batch_destroy": [P],
-            "ct_batch_epoch": [P, P, P, P, P, P],
+            "ct_batch_add": [P, ctypes.POINTER(ct_batch_job), ctypes.POINTER(i32)],
+            "ct_batch_remove": [P, i32],
+            "ct_batch_epoch": [P, i32, ctypes.POINTER(i32), P],
+            "ct_batch_job_epoch": [P, i32, ctypes.POINTER(i32)],
             "ct_job_footprint": [ctypes.POINTER(ct_geom_desc), ctypes.POINTER(ct_solver_params),
                                  ctypes.POINTER(ctypes.c_size_t)],
             "ct_last_error": [],
@@ -404,9 +413,12 @@ def ct_solve(geom: Geom, params: ct_sched_params, y, x, sync=CT_SYNC_COLUMN, tau
 # batch
 # ----------------------------------------------------------------------------
 class Batch:
-    def __init__(self, handle, solvers):
+    """A batch handle; keeps the Python objects of its jobs alive while they
+    are members."""
+
+    def __init__(self, handle):
         self.handle = handle
-        self.solvers = list(solvers)
+        self.members = {}       # id -> (solver, sched, y, x)
 
     def __del__(self):
         h, self.handle = getattr(self, "handle", None), None
@@ -414,19 +426,35 @@ class Batch:
             _lib.ct_batch_destroy(h)
 
 
-def ct_batch_create(solvers: Sequence[Solver]) -> Batch:
-    arr = (P * len(solvers))(*[s.handle for s in solvers])
+def ct_batch_create(capacity: int) -> Batch:
     h = P()
-    _check(lib().ct_batch_create(len(solvers), arr, ctypes.byref(h)))
-    return Batch(h, solvers)
+    _check(lib().ct_batch_create(int(capacity), ctypes.byref(h)))
+    return Batch(h)
 
 
-def ct_batch_epoch(batch: Batch, scheds, epochs, ys, xs, stream=None):
-    n = len(batch.solvers)
-    sc = (P * n)(*[s.handle if s is not None else None for s in scheds])
-    ep = np.ascontiguousarray(epochs, dtype=np.int32)
-    yp = (P * n)(*[(_dev(y, s.geom.M, "y").value if e >= 0 else None)
-                   for y, s, e in zip(ys, batch.solvers, ep)])
-    xp = (P * n)(*[(_dev(x, s.geom.N, "x").value if e >= 0 else None)
-                   for x, s, e in zip(xs, batch.solvers, ep)])
-    _check(lib().ct_batch_epoch(batch.handle, sc, _np_ptr(ep), yp, xp, _stream(stream)))
+def ct_batch_add(batch: Batch, solver: Solver, sched: Schedule, y, x, epoch: int = 0) -> int:
+    g = solver.geom
+    job = ct_batch_job(solver.handle, sched.handle, _dev(y, g.M, "y"), _dev(x, g.N, "x"), int(epoch))
+    jid = i32()
+    _check(lib().ct_batch_add(batch.handle, ctypes.byref(job), ctypes.byref(jid)))
+    batch.members[int(jid.value)] = (solver, sched, y, x)
+    return int(jid.value)
+
+
+def ct_batch_remove(batch: Batch, jid: int):
+    _check(lib().ct_batch_remove(batch.handle, int(jid)))
+    batch.members.pop(int(jid), None)
+
+
+def ct_batch_epoch(batch: Batch, graph: bool = False, stream=None) -> int:
+    """One batch epoch; returns the number of jobs that had an epoch to run."""
+    ran = i32()
+    _check(lib().ct_batch_epoch(batch.handle, CT_BATCH_GRAPH if graph else 0, ctypes.byref(ran),
+                                _stream(stream)))
+    return int(ran.value)
+
+
+def ct_batch_job_epoch(batch: Batch, jid: int) -> int:
+    e = i32()
+    _check(lib().ct_batch_job_epoch(batch.handle, int(jid), ctypes.byref(e)))
+    return int(e.value)
