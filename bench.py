@@ -1,13 +1,20 @@
 #!/usr/bin/env python3
 """Throughput of the block-iterative CT solver on one MI355X.
 
-A step is one epoch of Alg. 6 on the 2D fan-beam workload: 512 x 512 image at
-0.5 mm, 720 views over 360 degrees, 768-bin curved detector (1e-3 rad), source
-500 mm / detector 1000 mm from the source, 12-ellipse seeded phantom, 1%
-Gaussian noise; 8 view groups x 8 image tiles, row blocks drawn with
-probability proportional to nnz(A_I^J), alpha = 0.5, group size 1.  Each epoch
-runs, per column block, the gather back-projection, the fused forward
-projection, the step, and the finalize/residual kernels.
+Default workload (fan2d_512): a step is one epoch of Alg. 6 on the 2D
+fan-beam case: 512 x 512 image at 0.5 mm, 720 views over 360 degrees,
+768-bin curved detector (1e-3 rad), source 500 mm / detector 1000 mm from
+the source, 12-ellipse seeded phantom, 1% Gaussian noise; 8 view groups x 8
+image tiles, row blocks drawn with probability proportional to nnz(A_I^J),
+alpha = 0.5, group size 1.  Each epoch runs, per column block, the gather
+back-projection, the fused forward projection, the step, and the
+finalize/residual kernels.
+
+Other workloads (--workload): par2d_64 (the small parallel-beam case),
+cone3d_256 (256^3 cone beam, 360 views of 384^2, 12 view groups x 8 z-slabs,
+4 groups of 3, Poisson noise at 1e5 photons), batch64 (64 fan slices of
+uneven sizes, all jobs advanced by shared launches, against the same jobs
+solved one at a time).
 
 Printed as one JSON line.  value = ray-voxel updates per second over the
 timed epochs (2 nnz(A_{I_G}^J) per group update, from the exact density
@@ -35,14 +42,22 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 78.6          # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
 FLOPS_PER_UPDATE = 5.0           # select next crossing, segment length, advance, multiply-add
 GATHER_BYTES_PER_UPDATE = 4.0    # what an explicit-A SpMV would stream per nonzero
+BATCH_SIZES = (128, 256, 384, 512, 768, 1024)
 
 
-def workload(name):
+def single_workload(name):
     from paper_1709_00953_amd import inputs
     if name == "fan2d_512":
-        return inputs.config_c2(), dict(alpha=0.5, gamma=1.0, s=1, b=1.0, seed=2000, noise=0.01)
+        return (inputs.config_c2(), dict(alpha=0.5, gamma=1.0, s=1, b=1.0, seed=2000, noise=0.01),
+                "fan2d_curved 512x512 0.5mm, 720 views/360deg, 768 bins 1e-3 rad, SID 500 SDD 1000, "
+                "8x8 blocks, P~nnz, alpha 0.5, s 1")
     if name == "par2d_64":
-        return inputs.config_c1(), dict(alpha=0.5, gamma=1.0, s=1, b=0.5, seed=1000, noise=0.01)
+        return (inputs.config_c1(), dict(alpha=0.5, gamma=1.0, s=1, b=0.5, seed=1000, noise=0.01),
+                "par2d 64x64 1mm, 90 views/180deg, 96 bins 1mm, 4x4 blocks, P~nnz, alpha 0.5, s 1")
+    if name == "cone3d_256":
+        return (inputs.config_c3(), dict(alpha=1.0, gamma=1.0, s=3, b=1.0, seed=3000, photons=1e5),
+                "cone3d 256^3 0.5mm, 360 views/360deg of 384x384 1mm, SID 500 SDD 1000, 12 view "
+                "groups x 8 z-slabs, alpha 1, s 3 (4 groups), Poisson 1e5 photons")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -59,7 +74,7 @@ def updates_per_epoch(ex, nnz):
     return out
 
 
-def cpu_baseline(g, y, ex, budget_s=15.0):
+def cpu_baseline(g, y, ex, budget_s=15.0, note=""):
     """The FP64 oracle, as it is, on a bounded sample of the same workload:
     whole epochs of the same schedule and y (wrapping around the schedule)
     until about ``budget_s`` seconds of oracle time, with the explicit A built
@@ -97,49 +112,83 @@ def cpu_baseline(g, y, ex, budget_s=15.0):
         epochs += 1
     return {"value": st.updates / t_run, "unit": "ray-voxel updates/s", "cores": 1,
             "kind": "oracle",
-            "sample": (f"{epochs} epochs (schedule wrapped every {E}) of the same workload, "
+            "sample": (f"{note}{epochs} epochs (schedule wrapped every {E}) of the same workload, "
                        f"schedule and y: {st.updates} updates in {t_run:.2f} s, scipy CSR "
                        f"matvecs on 1 thread; explicit FP64 A ({A.nnz} nnz) and its {g.m}x{g.n} "
                        f"sub-blocks built beforehand in {t_build:.1f} s, untimed"),
             "seconds": t_run}
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fan2d_512")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
-    args = ap.parse_args()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {max(args.gpus, world)}); "
-              "sharding the column blocks across GPUs is not built.",
-              file=sys.stderr)
-        sys.exit(2)
+def roofline_of(kt, prof_updates):
+    """Roofline object of the dominant kernel from per-class (ms, launches)."""
+    dom = max(kt, key=lambda k: kt[k][0])
+    dom_ms, dom_n = kt[dom]
+    avg_ms = dom_ms / max(dom_n, 1)
+    if dom in ("back", "fwd"):
+        units = prof_updates / 2                # ray-voxel pairs handled by one projector
+        per_launch = units / dom_n
+        achieved = per_launch * FLOPS_PER_UPDATE / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 5),
+                "traffic": None, "kernel": dom, "avg_launch_ms": round(avg_ms, 5),
+                "launches": dom_n, "units_per_launch": per_launch,
+                "flops_per_unit": FLOPS_PER_UPDATE}
+        gbytes = per_launch * GATHER_BYTES_PER_UPDATE / (avg_ms * 1e-3) / 1e9
+        gather = {"achieved": round(gbytes, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(gbytes / HBM_PEAK_GBS, 5)}
+    else:
+        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": None, "traffic": None, "kernel": dom}
+        gather = None
+    return roof, gather
 
+
+def make_y(ct, inputs, G, g, cfg, seed):
+    """y from the validated GPU projector: A x_true plus the workload's noise."""
+    import torch
+    xt = torch.as_tensor(inputs.phantom_for(g, seed).astype(np.float32), device="cuda")
+    p = torch.zeros(G.M, device="cuda")
+    for J in range(G.n):
+        ct.ct_block_fwd(G, list(range(G.m)), J, xt, p, flags=ct.CT_ACCUMULATE if J else 0)
+    pn = p.cpu().numpy().astype(np.float64)
+    del p, xt
+    if "photons" in cfg:
+        y_np = inputs.poisson_noise(pn, cfg["photons"], seed)
+    else:
+        y_np = inputs.gaussian_noise(pn, cfg["noise"], seed)
+    return y_np, torch.as_tensor(y_np, device="cuda")
+
+
+def base_record(args, metric_value, ms_total, steps, dtype="f32"):
+    return {
+        "metric": "ray-voxel updates/s (fwd+back)",
+        "value": metric_value,
+        "unit": "ray-voxel updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_total / max(steps, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+    }
+
+
+def run_single(args):
     import torch
     from paper_1709_00953_amd import ct, inputs
 
-    torch.cuda.set_device(0)
-    g, cfg = workload(args.workload)
+    g, cfg, desc = single_workload(args.workload)
     t_setup = time.perf_counter()
     G = ct.ct_geom_create(g)
     tau = 1e-5 * min(g.vx, g.vy)
-    x_true = inputs.phantom_for(g, cfg["seed"])
-    xt = torch.as_tensor(x_true.astype(np.float32), device="cuda")
-    p = torch.zeros(G.M, device="cuda")
-    for J in range(G.n):                       # y = A x_true with the validated projector
-        ct.ct_block_fwd(G, list(range(G.m)), J, xt, p, flags=ct.CT_ACCUMULATE if J else 0)
-    y_np = inputs.gaussian_noise(p.cpu().numpy().astype(np.float64), cfg["noise"], cfg["seed"])
-    y = torch.as_tensor(y_np, device="cuda")
+    y_np, y = make_y(ct, inputs, G, g, cfg, cfg["seed"])
     nnz = ct.ct_geom_block_nnz(G, tau)
     E = args.warmup + args.steps
     # epochs [0, W) warm up, [W, E) are timed, [E, E + K) are replayed with a
-    # HIP event pair around every kernel for the per-kernel durations (the
-    # events add gaps, so they stay out of the timed epochs)
+    # HIP event pair around every kernel for the per-kernel durations
     params = ct.sched_params(E + args.steps, cfg["alpha"], cfg["gamma"], cfg["s"], cfg["b"],
                              seed=cfg["seed"])
     sched = ct.ct_schedule_create(G, params, nnz)
@@ -173,56 +222,164 @@ def main():
     prof_updates = sum(upd[E:E + args.steps])
 
     timed_updates = sum(upd[args.warmup:E])
-    value = timed_updates / (ms * 1e-3)
-
-    # dominant kernel and its roofline
-    dom = max(kt, key=lambda k: kt[k][0])
-    dom_ms, dom_n = kt[dom]
-    avg_ms = dom_ms / max(dom_n, 1)
-    if dom in ("back", "fwd"):
-        units = prof_updates / 2                # ray-voxel pairs handled by one projector
-        per_launch = units / dom_n
-        achieved = per_launch * FLOPS_PER_UPDATE / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": VALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 5),
-                "traffic": None, "kernel": dom, "avg_launch_ms": round(avg_ms, 5),
-                "launches": dom_n, "units_per_launch": per_launch,
-                "flops_per_unit": FLOPS_PER_UPDATE}
-        gbytes = per_launch * GATHER_BYTES_PER_UPDATE / (avg_ms * 1e-3) / 1e9
-        gather = {"achieved": round(gbytes, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(gbytes / HBM_PEAK_GBS, 5)}
-    else:
-        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": None, "traffic": None, "kernel": dom}
-        gather = None
-
-    out = {
-        "metric": "ray-voxel updates/s (fwd+back)",
-        "value": value,
-        "unit": "ray-voxel updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": ("fan2d_curved 512x512 0.5mm, 720 views/360deg, 768 bins "
-                                "1e-3 rad, SID 500 SDD 1000, 8x8 blocks, P~nnz, alpha 0.5, s 1"
-                                if args.workload == "fan2d_512" else args.workload),
-                   "epoch_updates": upd[args.warmup], "b": cfg["b"],
-                   "rel_residual_after": rel, "setup_s": round(t_setup, 3)},
-        "roofline": roof,
-        "gather_equivalent_hbm": gather,
-        "kernels_ms": {k: round(v[0], 4) for k, v in kt.items()},
-        "kernels_note": "per-kernel HIP-event times from the same number of epochs run right after the timed ones",
-        "kernels_launches": {k: v[1] for k, v in kt.items()},
-        "cpu_baseline": None,
-    }
+    out = base_record(args, timed_updates / (ms * 1e-3), ms, args.steps)
+    roof, gather = roofline_of(kt, prof_updates)
+    out["config"] = {"workload": desc, "epoch_updates": upd[args.warmup], "b": cfg["b"],
+                     "rel_residual_after": rel, "setup_s": round(t_setup, 3)}
+    out["roofline"] = roof
+    out["gather_equivalent_hbm"] = gather
+    out["kernels_ms"] = {k: round(v[0], 4) for k, v in kt.items()}
+    out["kernels_note"] = "per-kernel HIP-event times from the same number of epochs run right after the timed ones"
+    out["kernels_launches"] = {k: v[1] for k, v in kt.items()}
+    out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, y_np, ex, args.cpu_budget)
+        if g.is3d:
+            # the explicit FP64 A of the full volume does not fit; time the
+            # oracle on the same geometry at parity scale instead
+            gs = inputs.config_p3()
+            Gs = ct.ct_geom_create(gs)
+            ys_np, _ = make_y(ct, inputs, Gs, gs, cfg, cfg["seed"])
+            nnzs = ct.ct_geom_block_nnz(Gs, 1e-5 * min(gs.vx, gs.vy))
+            exs = ct.ct_schedule_export(ct.ct_schedule_create(Gs, params, nnzs))
+            out["cpu_baseline"] = cpu_baseline(
+                gs, ys_np, exs, args.cpu_budget,
+                note="parity-scale version of the cone geometry (48^3, 360 views of 72^2): ")
+        else:
+            out["cpu_baseline"] = cpu_baseline(g, y_np, ex, args.cpu_budget)
+    return out
+
+
+def run_batch(args):
+    """64 uneven fan slices: every job solved one at a time with ct_block_epoch,
+    then all of them advanced together by the batched launches (HIP graph)."""
+    import torch
+    from paper_1709_00953_amd import ct, inputs
+
+    n_jobs, E, b = args.jobs, args.steps, 1.0
+    rng = np.random.default_rng(4000)
+    sizes = [int(v) for v in rng.choice(BATCH_SIZES, size=n_jobs)]
+    t_setup = time.perf_counter()
+    jobs = []
+    for k, N in enumerate(sizes):
+        g = inputs.slice_fan(N)
+        G = ct.ct_geom_create(g)
+        seed = inputs.seed_for(4, k)
+        y_np, y = make_y(ct, inputs, G, g, {"noise": 0.01}, seed)
+        nnz = ct.ct_geom_block_nnz(G, 1e-5 * g.vx)
+        sched = ct.ct_schedule_create(G, ct.sched_params(E, 1.0, 1.0, 2, b, seed=seed), nnz)
+        ex = ct.ct_schedule_export(sched)
+        sol = ct.ct_solver_create(G)
+        x = torch.zeros(G.N, device="cuda")
+        jobs.append(dict(N=N, g=g, G=G, y=y, y_np=y_np, sched=sched, ex=ex, sol=sol, x=x,
+                         upd=sum(updates_per_epoch(ex, nnz))))
+        if k == 0 or (k + 1) % 16 == 0:
+            print(f"[bench] job {k + 1}/{n_jobs} ready (N={N})", file=sys.stderr, flush=True)
+    total_updates = sum(j["upd"] for j in jobs)
+
+    def reset_all():
+        for j in jobs:
+            j["x"].zero_()
+            ct.ct_solver_reset(j["sol"], j["y"])
+
+    # warm-up: first use uploads each schedule's device tables
+    reset_all()
+    for j in jobs:
+        ct.ct_block_epoch(j["sol"], j["sched"], 0, j["y"], j["x"])
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+
+    # one job at a time
+    reset_all()
+    torch.cuda.synchronize()
+    start.record()
+    for j in jobs:
+        for e in range(E):
+            ct.ct_block_epoch(j["sol"], j["sched"], e, j["y"], j["x"])
+    stop.record()
+    torch.cuda.synchronize()
+    ms_plain = start.elapsed_time(stop)
+    x_plain = [j["x"].clone() for j in jobs]
+    res_plain = [ct.ct_true_residual(j["sol"], j["y"], j["x"]) for j in jobs]
+
+    # batched, replayed from a HIP graph (building the batch table and the
+    # graph is inside the timed region)
+    reset_all()
+    torch.cuda.synchronize()
+    start.record()
+    B = ct.ct_batch_create(n_jobs)
+    for j in jobs:
+        ct.ct_batch_add(B, j["sol"], j["sched"], j["y"], j["x"])
+    for e in range(E):
+        ct.ct_batch_epoch(B, graph=True)
+    stop.record()
+    torch.cuda.synchronize()
+    ms_batch = start.elapsed_time(stop)
+    same = all(torch.equal(a, j["x"]) for a, j in zip(x_plain, jobs))
+    res_batch = [ct.ct_true_residual(j["sol"], j["y"], j["x"]) for j in jobs]
+
+    # per-kernel replay of the batched epochs with events
+    reset_all()
+    B2 = ct.ct_batch_create(n_jobs)
+    for j in jobs:
+        ct.ct_batch_add(B2, j["sol"], j["sched"], j["y"], j["x"])
+    ct.ct_batch_profile(B2, True)
+    for e in range(E):
+        ct.ct_batch_epoch(B2)
+    kt = ct.ct_batch_profile_read(B2)
+    roof, gather = roofline_of(kt, total_updates)
+
+    out = base_record(args, total_updates / (ms_batch * 1e-3), ms_batch, E)
+    out["config"] = {
+        "workload": (f"{n_jobs} fan2d_curved slices, N drawn from {list(BATCH_SIZES)} (seed 4000), "
+                     "pixel 256/N mm, 1.5N views/360deg, 1.5N bins over 0.768 rad, 4 view groups x "
+                     "4 quadrants, alpha 1, s 2, b 1, 1% noise, epochs = steps"),
+        "sizes": sizes, "total_updates": total_updates, "setup_s": round(t_setup, 3)}
+    out["jobs_per_s"] = n_jobs / (ms_batch * 1e-3)
+    out["plain"] = {"value": total_updates / (ms_plain * 1e-3), "ms": ms_plain,
+                    "jobs_per_s": n_jobs / (ms_plain * 1e-3),
+                    "mean_rel_residual": float(np.mean(res_plain))}
+    out["batched_ms"] = ms_batch
+    out["speedup_vs_plain"] = ms_plain / ms_batch
+    out["mean_rel_residual"] = float(np.mean(res_batch))
+    out["identical_to_plain"] = bool(same)
+    out["roofline"] = roof
+    out["gather_equivalent_hbm"] = gather
+    out["kernels_ms"] = {k: round(v[0], 4) for k, v in kt.items()}
+    out["kernels_launches"] = {k: v[1] for k, v in kt.items()}
+    out["kernels_note"] = "batched launches timed with HIP events in a replay of the same epochs"
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        small = min(range(n_jobs), key=lambda k: sizes[k])
+        j = jobs[small]
+        out["cpu_baseline"] = cpu_baseline(j["g"], j["y_np"], j["ex"], args.cpu_budget,
+                                           note=f"smallest slice of the mix (N={j['N']}): ")
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="fan2d_512",
+                    choices=["fan2d_512", "par2d_64", "cone3d_256", "batch64"])
+    ap.add_argument("--jobs", type=int, default=64, help="batch64: number of slices")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {max(args.gpus, world)}); "
+              "sharding the column blocks across GPUs is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(0)
+    out = run_batch(args) if args.workload == "batch64" else run_single(args)
     print(json.dumps(out), flush=True)
 
 

@@ -288,6 +288,11 @@ int ct_batch_remove(ct_batch* batch, int32_t id);
 int ct_batch_epoch(ct_batch* batch, int32_t flags, int32_t* ran, void* stream);
 /* Next epoch the job will run (== its schedule's epoch count when done). */
 int ct_batch_job_epoch(const ct_batch* batch, int32_t id, int32_t* epoch);
+/* Kernel timing of the batched launches, as ct_solver_profile (the phase
+ * launches are timed per kernel class; while enabled, CT_BATCH_GRAPH is
+ * ignored and the launches go out one by one). */
+int ct_batch_profile(ct_batch* batch, int32_t enable);
+int ct_batch_profile_read(ct_batch* batch, ct_kernel_times* out);
 
 /* Device bytes one job needs (geometry tables + workspace): for admission
  * by memory budget. */

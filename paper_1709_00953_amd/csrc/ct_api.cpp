@@ -1089,10 +1089,61 @@ struct ProfRec {
     hipEvent_t a, b;
 };
 
-struct ct_solver {
-    bool prof = false;
+// Per-launch HIP-event timing of a solver or a batch.
+struct Prof {
+    bool on = false;
     std::vector<ProfRec> recs;          // recorded (kernel class, start, end)
     std::vector<hipEvent_t> pool;       // idle events
+
+    void release() {
+        for (auto& r : recs) {
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        recs.clear();
+    }
+    ~Prof() {
+        release();
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+    hipEvent_t event() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    // Enqueue `launch` on `st`, bracketed by events when profiling is on.
+    template <class F>
+    hipError_t timed(int kind, hipStream_t st, F&& launch) {
+        if (!on) return launch();
+        hipEvent_t a = event(), b = event();
+        if (!a || !b) return hipErrorOutOfMemory;
+        hipError_t e = hipEventRecord(a, st);
+        if (e == hipSuccess) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(b, st);
+        recs.push_back(ProfRec{kind, a, b});
+        return e;
+    }
+    int read(ct_kernel_times* out) {
+        std::memset(out, 0, sizeof *out);
+        for (auto& r : recs) {
+            HIPCHK(hipEventSynchronize(r.b));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+            out->ms[r.kind] += ms;
+            out->launches[r.kind] += 1;
+        }
+        release();
+        return CT_OK;
+    }
+};
+
+struct ct_solver {
+    Prof prof;
     ct_geom* geom = nullptr;
     ct_solver_params p{};
     char* ws = nullptr;
@@ -1140,63 +1191,22 @@ extern "C" int ct_solver_create(ct_geom* g, const ct_solver_params* p, void* ws,
     return CT_OK;
 }
 
-static void prof_release(ct_solver* s) {
-    for (auto& r : s->recs) {
-        s->pool.push_back(r.a);
-        s->pool.push_back(r.b);
-    }
-    s->recs.clear();
-}
+extern "C" void ct_solver_destroy(ct_solver* s) { delete s; }
 
-extern "C" void ct_solver_destroy(ct_solver* s) {
-    if (!s) return;
-    prof_release(s);
-    for (hipEvent_t e : s->pool) (void)hipEventDestroy(e);
-    delete s;
-}
-
-static hipEvent_t prof_event(ct_solver* s) {
-    if (!s->pool.empty()) {
-        hipEvent_t e = s->pool.back();
-        s->pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-}
-
-// Enqueue `launch` on `st`, bracketed by events when profiling is on.
 template <class F>
 static hipError_t timed(ct_solver* s, int kind, hipStream_t st, F&& launch) {
-    if (!s->prof) return launch();
-    hipEvent_t a = prof_event(s), b = prof_event(s);
-    if (!a || !b) return hipErrorOutOfMemory;
-    hipError_t e = hipEventRecord(a, st);
-    if (e == hipSuccess) e = launch();
-    if (e == hipSuccess) e = hipEventRecord(b, st);
-    s->recs.push_back(ProfRec{kind, a, b});
-    return e;
+    return s->prof.timed(kind, st, launch);
 }
 
 extern "C" int ct_solver_profile(ct_solver* s, int32_t enable) {
     if (!s) return fail(CT_EINVAL, "NULL solver");
-    s->prof = enable != 0;
+    s->prof.on = enable != 0;
     return CT_OK;
 }
 
 extern "C" int ct_solver_profile_read(ct_solver* s, ct_kernel_times* out) {
     if (!s || !out) return fail(CT_EINVAL, "NULL argument");
-    std::memset(out, 0, sizeof *out);
-    for (auto& r : s->recs) {
-        HIPCHK(hipEventSynchronize(r.b));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
-        out->ms[r.kind] += ms;
-        out->launches[r.kind] += 1;
-    }
-    prof_release(s);
-    return CT_OK;
+    return s->prof.read(out);
 }
 
 extern "C" int ct_solver_state(const ct_solver* s, float** z, float** r) {
@@ -1476,6 +1486,7 @@ struct ct_batch {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t exec = nullptr;
     bool graph_valid = false;
+    Prof prof;
 };
 
 static BJob make_bjob(const BatchSlot& b) {
@@ -1639,8 +1650,10 @@ static BatchArgs batch_args(const ct_batch* b, const BatchLaunch* L) {
 }
 
 static int batch_enqueue(ct_batch* b, hipStream_t st) {
+    static const int kind_of_phase[] = {CT_K_BACK, CT_K_FWD, CT_K_STEP, CT_K_FINALIZE, CT_K_RESIDUAL};
     for (const BatchLaunch& L : b->launches)
-        HIPCHK(launch_batch(L.phase, L.kind, batch_args(b, &L), L.blocks, st));
+        HIPCHK(b->prof.timed(kind_of_phase[L.phase], st,
+                             [&] { return launch_batch(L.phase, L.kind, batch_args(b, &L), L.blocks, st); }));
     HIPCHK(launch_batch_advance(batch_args(b, nullptr), st));
     return CT_OK;
 }
@@ -1717,6 +1730,17 @@ extern "C" int ct_batch_remove(ct_batch* b, int32_t id) {
     return fail(CT_EINVAL, "no job %d in the batch", id);
 }
 
+extern "C" int ct_batch_profile(ct_batch* b, int32_t enable) {
+    if (!b) return fail(CT_EINVAL, "NULL batch");
+    b->prof.on = enable != 0;
+    return CT_OK;
+}
+
+extern "C" int ct_batch_profile_read(ct_batch* b, ct_kernel_times* out) {
+    if (!b || !out) return fail(CT_EINVAL, "NULL argument");
+    return b->prof.read(out);
+}
+
 extern "C" int ct_batch_job_epoch(const ct_batch* b, int32_t id, int32_t* epoch) {
     if (!b || !epoch) return fail(CT_EINVAL, "NULL argument");
     for (const BatchSlot& j : b->jobs)
@@ -1740,7 +1764,7 @@ extern "C" int ct_batch_epoch(ct_batch* b, int32_t flags, int32_t* ran, void* st
     if (active == 0) return CT_OK;
     int rc;
     if (b->dirty && (rc = batch_rebuild(b, st))) return rc;
-    if (flags & CT_BATCH_GRAPH) {
+    if ((flags & CT_BATCH_GRAPH) && !b->prof.on) {
         if (!b->graph_valid) {
             batch_drop_graph(b);
             if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));

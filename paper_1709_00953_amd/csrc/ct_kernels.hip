@@ -65,15 +65,33 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
 }
 
 // Load base[i] with a 32-bit unsigned byte offset (lets the compiler use a
-// uniform base register plus a per-lane 32-bit offset).
+// uniform base register plus a per-lane 32-bit offset).  Every array read
+// this way lives in global memory; saying so keeps the load a global one even
+// when the base pointer was itself read from memory (batched launches).
 template <class T>
 __device__ __forceinline__ T ldu(const T* base, unsigned i) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(T));
+#if defined(__HIP_DEVICE_COMPILE__)
+    using GP = const __attribute__((address_space(1))) char*;
+    using GT = const __attribute__((address_space(1))) T*;
+    return *(GT)((GP)base + i * (unsigned)sizeof(T));
+#else
+    return base[i];     // host pass: never executed
+#endif
 }
 
 // Entry i of a launch: inline in the kernel arguments (primitives) or in
 // device memory.  The choice is a compile-time property of the argument type
 // so that no pointer select makes the compiler copy the arguments to scratch.
+// A pointer that is the same in every lane, moved to scalar registers so
+// that loads through it can use a scalar base.
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T*)(((uint64_t)hi << 32) | lo);
+}
+
 template <class A>
 __device__ __forceinline__ Entry get_entry(const A& a, int i) {
     if constexpr (A::kInl) return a.inl[i];
@@ -279,7 +297,7 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                 const double cdy = (KIND == kPar2D) ? Vc[1] : Vc[13];
                 const int tr = __builtin_amdgcn_readfirstlane(fabs(cdx) > fabs(cdy) ? 1 : 0);
                 const int cs = xg_copy(nb[0], nb[1], DIMS == 3 ? nb[2] : 1);
-                xg = a.xg + (size_t)grp * (size_t)a.xg_stride + (size_t)tr * (size_t)cs;
+                xg = uniform_ptr(a.xg + (size_t)grp * (size_t)a.xg_stride + (size_t)tr * (size_t)cs);
                 step[0] = tr ? nb[1] : 1;
                 step[1] = tr ? 1 : nb[0];
                 step[2] = nb[0] * nb[1];
@@ -622,88 +640,241 @@ __global__ __launch_bounds__(256) void k_back2(DGeom G, BA a) {
 // ----------------------------------------------------------------------------
 // K1: gather back-projection, 3D cone
 // ----------------------------------------------------------------------------
+// View frame of a cone view: source S, unit detector normal n, detector axes
+// e_u, e_v (orthonormal), source-detector distance sdd.  A voxel centre c has
+// frame coordinates A = (c-S).n, Bu = (c-S).e_u, Bv = (c-S).e_v.  The ray of
+// bin (u, v) is S + t D~ with D~ = n + (u/sdd) e_u + (v/sdd) e_v; at depth
+// A + s it lies at  s D~ - du e_u - dv e_v  from c, where du = Bu - A u/sdd and
+// dv = Bv - A v/sdd (float64: they cancel lever arms of the source distance).
+// Its x/y/z slabs of the voxel are then s-intervals centred on
+//   s_k = du a_k + dv b_k,  a_k = e_u,k / D~_k,  b_k = e_v,k / D~_k
+// with half-widths w_k = h_k / |D~_k|, and the clip length is
+//   |D~| max(0, min_k(s_k + w_k) - max_k(s_k - w_k)).
+// A work-group owns an 8 x 8 x 4 voxel tile (one voxel per lane) and walks the
+// views of the group; per (tile, view) it bounds the tile's shadow by the
+// projection of its bounding sphere, stages the per-ray constants of that
+// detector window (and r) in LDS, and every voxel then clips the candidate
+// rays of its own shadow window.
+struct ViewP3 {
+    double At, But, Bvt;          // frame coordinates of the tile centre
+    double ax, ay, az;            // A per voxel step in x, y, z
+    double bux, buy, buz, bvx, bvy, bvz;
+    double isdd;                  // 1 / sdd
+    float n[3], eu[3], ev[3];
+    float sdd;
+    int32_t view, fu0, fu1, fv0, fv1;     // detector window [fu0, fu1) x [fv0, fv1)
+    int32_t flags, pad;
+};
+
+constexpr int kRayC = 256;        // staged rays per pass
+
+__device__ __forceinline__ void view_params3(const DGeom& G, const Tile& tl, const double tc[3],
+                                             const double tr, ViewP3& P) {
+    const double* V = view_of(G, tl.view);
+    const double q[3] = {tc[0] - V[0], tc[1] - V[1], tc[2] - V[2]};
+    P.At = fma(q[0], V[12], fma(q[1], V[13], q[2] * V[14]));
+    P.But = fma(q[0], V[6], fma(q[1], V[7], q[2] * V[8]));
+    P.Bvt = fma(q[0], V[9], fma(q[1], V[10], q[2] * V[11]));
+    P.ax = V[12] * G.vx;
+    P.ay = V[13] * G.vy;
+    P.az = V[14] * G.vz;
+    P.bux = V[6] * G.vx;
+    P.buy = V[7] * G.vy;
+    P.buz = V[8] * G.vz;
+    P.bvx = V[9] * G.vx;
+    P.bvy = V[10] * G.vy;
+    P.bvz = V[11] * G.vz;
+    P.isdd = V[16];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        P.eu[k] = (float)V[6 + k];
+        P.ev[k] = (float)V[9 + k];
+        P.n[k] = (float)V[12 + k];
+    }
+    P.sdd = (float)V[15];
+    P.view = tl.view;
+    P.flags = G.view_flags[tl.view];
+    // shadow of the sphere of radius tr around the tile centre: a point
+    // c + r (|r| <= tr) moves the bin coordinate sdd B / A by at most
+    // sdd tr sqrt(1 + (B/A)^2) / (A - tr)
+    const double c0u = 0.5 * (double)(G.nu - 1), c0v = 0.5 * (double)(G.nv - 1);
+    int u0 = tl.u0, u1 = tl.u1, v0 = tl.v0, v1 = tl.v1;
+    if (P.At > 1.0001 * tr) {
+        const double tu = P.But / P.At, tv = P.Bvt / P.At;
+        const double den = V[15] * tr / (P.At - tr);
+        const double bu = V[15] * tu / G.pu + c0u, wu = den * sqrt(1.0 + tu * tu) / G.pu + 1e-3;
+        const double bv = V[15] * tv / G.pv + c0v, wv = den * sqrt(1.0 + tv * tv) / G.pv + 1e-3;
+        u0 = max(u0, (int)fmax(ceil(bu - wu), -1.0));
+        u1 = min(u1, (int)fmin(floor(bu + wu), 2e9) + 1);
+        v0 = max(v0, (int)fmax(ceil(bv - wv), -1.0));
+        v1 = min(v1, (int)fmin(floor(bv + wv), 2e9) + 1);
+    }
+    P.fu0 = u0;
+    P.fu1 = max(u0, u1);
+    P.fv0 = v0;
+    P.fv1 = max(v0, v1);
+}
+
 template <class BA>
 __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const int gi, const int bt,
                                            const int n_tiles) {
+    __shared__ ViewP3 vp[64];
+    __shared__ float4 rc0[kRayC], rc1[kRayC], rc2[kRayC];
     __shared__ double sh[4];
+    const int t = threadIdx.x;
     const int tx = bt % a.tiles_x;
     const int ty = (bt / a.tiles_x) % a.tiles_y;
     const int tz = bt / (a.tiles_x * a.tiles_y);
-    const int lx = threadIdx.x & 7, ly = (threadIdx.x >> 3) & 7, lz = threadIdx.x >> 6;
+    const int lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
     const int ix = a.box.x0 + tx * kTile3x + lx;
     const int iy = a.box.y0 + ty * kTile3y + ly;
     const int iz = a.box.z0 + tz * kTile3z + lz;
     const bool valid = ix < a.box.x1 && iy < a.box.y1 && iz < a.box.z1;
 
-    const double c[3] = {G.ox + ((double)ix + 0.5) * G.vx, G.oy + ((double)iy + 0.5) * G.vy,
-                         G.oz + ((double)iz + 0.5) * G.vz};
+    // tile centre, bounding-sphere radius, and this voxel's offset from the centre
+    const int xs = a.box.x0 + tx * kTile3x, ys = a.box.y0 + ty * kTile3y, zs = a.box.z0 + tz * kTile3z;
+    const int nvx = min(kTile3x, a.box.x1 - xs), nvy = min(kTile3y, a.box.y1 - ys);
+    const int nvz = min(kTile3z, a.box.z1 - zs);
+    const double tc[3] = {G.ox + ((double)xs + 0.5 * nvx) * G.vx, G.oy + ((double)ys + 0.5 * nvy) * G.vy,
+                          G.oz + ((double)zs + 0.5 * nvz) * G.vz};
+    const double trad = 0.5 * sqrt((nvx * G.vx) * (nvx * G.vx) + (nvy * G.vy) * (nvy * G.vy) +
+                                   (nvz * G.vz) * (nvz * G.vz)) * (1.0 + 1e-9);
+    const double ox = (double)lx - 0.5 * (nvx - 1), oy = (double)ly - 0.5 * (nvy - 1);
+    const double oz = (double)lz - 0.5 * (nvz - 1);
     const float hh[3] = {(float)(0.5 * G.vx), (float)(0.5 * G.vy), (float)(0.5 * G.vz)};
     const float R = G.radius;
-    const float c0u = 0.5f * (float)(G.nu - 1), c0v = 0.5f * (float)(G.nv - 1);
-    const float ipu = (float)(1.0 / G.pu), ipv = (float)(1.0 / G.pv);
-    float acc = 0.f;
+    const double pu = G.pu, pv = G.pv;
+    const double c0u = 0.5 * (double)(G.nu - 1), c0v = 0.5 * (double)(G.nv - 1);
+    const float ipu = (float)(1.0 / pu), ipv = (float)(1.0 / pv);
+    const float c0uf = (float)c0u, c0vf = (float)c0v;
 
     int e0 = 0, e1 = a.n_ent;
     if (a.gptr) {
         e0 = a.gptr[gi];
         e1 = a.gptr[gi + 1];
     }
-    if (valid) {
-        for (int e = e0; e < e1; ++e) {
-            const int rb = get_entry(a, e).rb;
-            const int t_end = G.rb_tile_ptr[rb + 1];
-            for (int t = G.rb_tile_ptr[rb]; t < t_end; ++t) {
-                const Tile tl = G.tiles[t];
-                const int view = tl.view;
-                const double* V = view_of(G, view);
-                const double q[3] = {c[0] - V[0], c[1] - V[1], c[2] - V[2]};
-                const double A = fma(q[0], V[12], fma(q[1], V[13], q[2] * V[14]));
-                const double Bu = fma(q[0], V[6], fma(q[1], V[7], q[2] * V[8]));
-                const double Bv = fma(q[0], V[9], fma(q[1], V[10], q[2] * V[11]));
-                const double sdd = V[15];
-                const double tc = A * V[16];            // ray parameter at the voxel's depth
-                const float Af = (float)A;
-                const float tu = (float)Bu / Af, tv = (float)Bv / Af;
-                const float sd = (float)sdd;
-                const float den = sd * R / (Af - R);
-                const float betu = sd * tu * ipu + c0u, betv = sd * tv * ipv + c0v;
-                const float wu = den * (1.f + fabsf(tu)) * ipu, wv = den * (1.f + fabsf(tv)) * ipv;
-                const int ulo = max((int)ceilf(betu - wu - 1e-3f), tl.u0);
-                const int uhi = min((int)floorf(betu + wu + 1e-3f), tl.u1 - 1);
-                const int vlo = max((int)ceilf(betv - wv - 1e-3f), tl.v0);
-                const int vhi = min((int)floorf(betv + wv + 1e-3f), tl.v1 - 1);
-                const bool careful = (G.view_flags[view] & 1) != 0;
-                for (int iv = vlo; iv <= vhi; ++iv) {
-                    const double v = ((double)iv - 0.5 * (double)(G.nv - 1)) * G.pv;
-                    const float* rr = a.r + ((size_t)view * G.nv + iv) * G.nu;
-                    for (int iu = ulo; iu <= uhi; ++iu) {
-                        const double u = ((double)iu - 0.5 * (double)(G.nu - 1)) * G.pu;
-                        const double D[3] = {fma(v, V[9], fma(u, V[6], sdd * V[12])),
-                                             fma(v, V[10], fma(u, V[7], sdd * V[13])),
-                                             fma(v, V[11], fma(u, V[8], sdd * V[14]))};
-                        float lo = -INFINITY, hi = INFINITY;
-                        bool member = true;
+    int nt = 0;                                          // views (tiles) of the group
+    for (int e = e0; e < e1; ++e) {
+        const int rb = get_entry(a, e).rb;
+        nt += G.rb_tile_ptr[rb + 1] - G.rb_tile_ptr[rb];
+    }
+
+    float acc = 0.f;
+    for (int base = 0; base < nt; base += 64) {
+        if (t < 64 && base + t < nt) {
+            int e = e0, off = base + t;
+            for (;;) {
+                const int rb = get_entry(a, e).rb;
+                const int cnt = G.rb_tile_ptr[rb + 1] - G.rb_tile_ptr[rb];
+                if (off < cnt) {
+                    view_params3(G, G.tiles[G.rb_tile_ptr[rb] + off], tc, trad, vp[t]);
+                    break;
+                }
+                off -= cnt;
+                ++e;
+            }
+        }
+        __syncthreads();
+        const int nb = min(64, nt - base);
+        for (int j = 0; j < nb; ++j) {
+            const ViewP3& P = vp[j];
+            const int view = P.view;
+            const int fu0 = P.fu0, fu1 = P.fu1, fv0 = P.fv0, fv1 = P.fv1;
+            const int fw = fu1 - fu0, fh = fv1 - fv0;
+            if (fw <= 0 || fh <= 0) continue;
+            // this voxel's frame coordinates and shadow window
+            const double A = fma(oz, P.az, fma(oy, P.ay, fma(ox, P.ax, P.At)));
+            const double Bu = fma(oz, P.buz, fma(oy, P.buy, fma(ox, P.bux, P.But)));
+            const double Bv = fma(oz, P.bvz, fma(oy, P.bvy, fma(ox, P.bvx, P.Bvt)));
+            const double Ai = A * P.isdd;
+            const float Af = (float)A;
+            const float tu = (float)Bu / Af, tv = (float)Bv / Af;
+            const float den = P.sdd * R / (Af - R);
+            const float betu = P.sdd * tu * ipu + c0uf, betv = P.sdd * tv * ipv + c0vf;
+            const float wu = den * (1.f + fabsf(tu)) * ipu + 1e-3f;
+            const float wv = den * (1.f + fabsf(tv)) * ipv + 1e-3f;
+            const int ulo = valid ? (int)ceilf(betu - wu) : 1, uhi = valid ? (int)floorf(betu + wu) : 0;
+            const int vlo = valid ? (int)ceilf(betv - wv) : 1, vhi = valid ? (int)floorf(betv + wv) : 0;
+            // the window in passes of at most kRayC rays
+            const int cw = min(fw, kRayC), chh = max(1, kRayC / cw);
+            for (int cv0 = fv0; cv0 < fv1; cv0 += chh) {
+                const int cv1 = min(fv1, cv0 + chh);
+                for (int cu0 = fu0; cu0 < fu1; cu0 += cw) {
+                    const int cu1 = min(fu1, cu0 + cw);
+                    const int pw = cu1 - cu0, np = pw * (cv1 - cv0);
+                    __syncthreads();                    // previous pass fully read
+                    if (t < np) {
+                        const int iu = cu0 + t % pw, iv = cv0 + t / pw;
+                        const double u = ((double)iu - c0u) * pu, v = ((double)iv - c0v) * pv;
+                        const double* V = view_of(G, view);
+                        float d[3];
+                        int zero = 0;
 #pragma unroll
                         for (int k = 0; k < 3; ++k) {
-                            const float w = (float)fma(-tc, D[k], q[k]);
-                            const float Dk = (float)D[k];
-                            if (careful && Dk == 0.f) {
-                                member = member && (w > -hh[k]) && (w <= hh[k]);
-                            } else {
-                                const float inv = 1.f / Dk;
-                                const float ta = (w - hh[k]) * inv, tb = (w + hh[k]) * inv;
-                                lo = fmaxf(lo, fminf(ta, tb));
-                                hi = fminf(hi, fmaxf(ta, tb));
-                            }
+                            const double Dk = fma(v, V[9 + k], fma(u, V[6 + k], V[15] * V[12 + k]));
+                            d[k] = (float)(Dk * P.isdd);
+                            zero |= (d[k] == 0.f) ? (1 << k) : 0;
                         }
-                        const float Df0 = (float)D[0], Df1 = (float)D[1], Df2 = (float)D[2];
-                        const float nrm = sqrtf(fmaf(Df0, Df0, fmaf(Df1, Df1, Df2 * Df2)));
-                        const float L = member ? fmaxf(hi - lo, 0.f) * nrm : 0.f;
-                        acc = fmaf(L, rr[iu], acc);
+                        float al[3], be[3], w[3];
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            const float inv = (zero >> k) & 1 ? 0.f : 1.f / d[k];
+                            al[k] = P.eu[k] * inv;
+                            be[k] = P.ev[k] * inv;
+                            w[k] = (zero >> k) & 1 ? INFINITY : hh[k] * fabsf(inv);
+                        }
+                        const float nrm = sqrtf(fmaf(d[0], d[0], fmaf(d[1], d[1], d[2] * d[2])));
+                        const float rv = a.r[((size_t)view * G.nv + iv) * G.nu + iu];
+                        rc0[t] = make_float4(al[0], al[1], al[2], w[0]);
+                        rc1[t] = make_float4(be[0], be[1], be[2], w[1]);
+                        rc2[t] = make_float4(w[2], nrm, rv, __int_as_float(zero));
+                    }
+                    __syncthreads();
+                    const int va = max(vlo, cv0), vb = min(vhi, cv1 - 1);
+                    const int ua = max(ulo, cu0), ub = min(uhi, cu1 - 1);
+                    if (ua > ub) continue;
+                    // du, dv at (ua, iv) in float64, stepped along u
+                    const double du0 = fma(-Ai, ((double)ua - c0u) * pu, Bu);
+                    const double ddu = -Ai * pu;
+                    for (int iv = va; iv <= vb; ++iv) {
+                        const float dv = (float)fma(-Ai, ((double)iv - c0v) * pv, Bv);
+                        double dud = du0;
+                        const int row = (iv - cv0) * pw - cu0;
+                        for (int iu = ua; iu <= ub; ++iu) {
+                            const float du = (float)dud;
+                            dud += ddu;
+                            const float4 q0 = rc0[row + iu], q1 = rc1[row + iu], q2 = rc2[row + iu];
+                            const float s0 = fmaf(du, q0.x, dv * q1.x);
+                            const float s1 = fmaf(du, q0.y, dv * q1.y);
+                            const float s2 = fmaf(du, q0.z, dv * q1.z);
+                            float lo = fmaxf(fmaxf(s0 - q0.w, s1 - q1.w), s2 - q2.x);
+                            float hi = fminf(fminf(s0 + q0.w, s1 + q1.w), s2 + q2.x);
+                            const int zero = __float_as_int(q2.w);
+                            if (zero) {
+                                // an axis the ray never crosses: it lies in one
+                                // half-open voxel slab or misses the voxel
+                                const float g[3] = {du * P.eu[0] + dv * P.ev[0], du * P.eu[1] + dv * P.ev[1],
+                                                    du * P.eu[2] + dv * P.ev[2]};
+                                const float ss[3] = {s0, s1, s2}, ww[3] = {q0.w, q1.w, q2.x};
+                                lo = -INFINITY;
+                                hi = INFINITY;
+#pragma unroll
+                                for (int k = 0; k < 3; ++k) {
+                                    if ((zero >> k) & 1) {
+                                        if (!(g[k] > -hh[k] && g[k] <= hh[k])) hi = -INFINITY;
+                                    } else {
+                                        lo = fmaxf(lo, ss[k] - ww[k]);
+                                        hi = fminf(hi, ss[k] + ww[k]);
+                                    }
+                                }
+                            }
+                            acc = fmaf(fmaxf(hi - lo, 0.f) * q2.y, q2.z, acc);
+                        }
                     }
                 }
             }
         }
+        __syncthreads();
     }
 
     const int nxJ = a.box.x1 - a.box.x0, nyJ = a.box.y1 - a.box.y0;
@@ -711,15 +882,15 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
     if (a.fused) {
         if (valid) {
             const int nzJ = a.box.z1 - a.box.z0;
-            const int lx = ix - a.box.x0, ly = iy - a.box.y0, lz = iz - a.box.z0;
+            const int jx = ix - a.box.x0, jy = iy - a.box.y0, jz = iz - a.box.z0;
             const float2 v = make_float2(a.x[gix], acc);
-            float2* base = a.xg + (size_t)gi * a.xg_stride + xg_pad(nxJ, nyJ, nzJ);
-            base[(lz * nyJ + ly) * nxJ + lx] = v;
-            base[xg_copy(nxJ, nyJ, nzJ) + (lz * nxJ + lx) * nyJ + ly] = v;
+            float2* basep = a.xg + (size_t)gi * a.xg_stride + xg_pad(nxJ, nyJ, nzJ);
+            basep[(jz * nyJ + jy) * nxJ + jx] = v;
+            basep[xg_copy(nxJ, nyJ, nzJ) + (jz * nxJ + jx) * nyJ + jy] = v;
         }
         const double p = valid ? (double)acc * (double)acc : 0.0;
-        const double t = block_sum256(p, sh);
-        if (threadIdx.x == 0) a.partial[(size_t)gi * n_tiles + bt] = t;
+        const double tsum = block_sum256(p, sh);
+        if (threadIdx.x == 0) a.partial[(size_t)gi * n_tiles + bt] = tsum;
     } else if (valid) {
         a.g[gix] = (a.flags & 1) ? a.g[gix] + acc : acc;
     }
@@ -819,6 +990,19 @@ __global__ __launch_bounds__(256) void k_residual(DGeom G, ResArgs a, int n_chun
 // epoch counter, and runs the same body as the single-job kernel, so a job's
 // results are the same bits in a batch as alone.
 // ----------------------------------------------------------------------------
+// Read a launch-constant table entry (job table, schedule records, boxes,
+// epoch counters outside kb_advance) through the constant address space, so
+// that wave-uniform reads become scalar loads into scalar registers.
+template <class T>
+__device__ __forceinline__ T cld(const T* p, int i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    using CT = const __attribute__((address_space(4))) T*;
+    return ((CT)p)[i];
+#else
+    return p[i];        // host pass: never executed
+#endif
+}
+
 // Owner of work-group b: the last k with prefix[k] <= b (prefix is
 // non-decreasing, so jobs without work in this phase are skipped).  Every
 // lane of the wave must be active.
@@ -826,7 +1010,7 @@ __device__ __forceinline__ int batch_job(const BatchArgs& B, const int b) {
     int cnt = 0;
     for (int base = 0; base < B.n_jobs; base += 64) {
         const int i = base + (int)(threadIdx.x & 63);
-        const bool le = i < B.n_jobs && B.prefix[i] <= b;
+        const bool le = i < B.n_jobs && ldu(B.prefix, (unsigned)i) <= b;
         cnt += __popcll(__ballot(le));
     }
     return __builtin_amdgcn_readfirstlane(cnt - 1);
@@ -835,11 +1019,11 @@ __device__ __forceinline__ int batch_job(const BatchArgs& B, const int b) {
 // Step c of job k's current epoch; false once the job has run all its epochs
 // or its epoch has fewer steps.
 __device__ __forceinline__ bool batch_step(const BatchArgs& B, const int k, const BJob& J, StepRec& sr) {
-    const int e = B.ep[k];
+    const int e = cld(B.ep, k);
     if (e < 0 || e >= J.n_epochs) return false;
-    const EpochRec er = J.epochs[e];
+    const EpochRec er = cld(J.epochs, e);
     if (B.c >= er.n_steps) return false;
-    sr = J.steps[er.step0 + B.c];
+    sr = cld(J.steps, er.step0 + B.c);
     return sr.n_groups > 0;            // a column without groups is skipped, as alone
 }
 
@@ -863,12 +1047,12 @@ template <int KIND>
 __global__ __launch_bounds__(256) void kb_back(BatchArgs B) {
     const int k = batch_job(B, blockIdx.x);
     const int L = blockIdx.x - B.prefix[k];
-    const BJob& J = B.jobs[k];
+    const BJob J = cld(B.jobs, k);
     StepRec sr;
     if (!batch_step(B, k, J, sr)) return;
     const DGeom G = J.G;
     BackCore a{};
-    a.box = J.boxes[sr.col];
+    a.box = cld(J.boxes, sr.col);
     box_tiles(a.box, G.dims, a.tiles_x, a.tiles_y, a.tiles_z);
     const int nt = a.tiles_x * a.tiles_y * a.tiles_z;
     const int gi = L / nt, tile = L - gi * nt;
@@ -891,13 +1075,13 @@ template <int KIND>
 __global__ __launch_bounds__(256) void kb_fwd(BatchArgs B) {
     const int k = batch_job(B, blockIdx.x);
     const int L = blockIdx.x - B.prefix[k];
-    const BJob& J = B.jobs[k];
+    const BJob J = cld(B.jobs, k);
     StepRec sr;
     if (!batch_step(B, k, J, sr)) return;
     if (L >= sr.n_chunks) return;
     const DGeom G = J.G;
     FwdCore a{};
-    a.box = J.boxes[sr.col];
+    a.box = cld(J.boxes, sr.col);
     a.ent = J.ent + sr.ent_off;
     a.n_ent = sr.n_ent;
     a.n_chunks = sr.n_chunks;
@@ -916,11 +1100,11 @@ __global__ __launch_bounds__(256) void kb_fwd(BatchArgs B) {
 __global__ __launch_bounds__(256) void kb_step(BatchArgs B) {
     const int k = batch_job(B, blockIdx.x);
     const int L = blockIdx.x - B.prefix[k];
-    const BJob& J = B.jobs[k];
+    const BJob J = cld(B.jobs, k);
     StepRec sr;
     if (!batch_step(B, k, J, sr)) return;
     if (L >= sr.n_groups) return;
-    const Box box = J.boxes[sr.col];
+    const Box box = cld(J.boxes, sr.col);
     int tx, ty, tz;
     box_tiles(box, J.G.dims, tx, ty, tz);
     StepArgs a{};
@@ -938,10 +1122,10 @@ __global__ __launch_bounds__(256) void kb_step(BatchArgs B) {
 __global__ __launch_bounds__(256) void kb_finalize(BatchArgs B) {
     const int k = batch_job(B, blockIdx.x);
     const int L = blockIdx.x - B.prefix[k];
-    const BJob& J = B.jobs[k];
+    const BJob J = cld(B.jobs, k);
     StepRec sr;
     if (!batch_step(B, k, J, sr)) return;
-    const Box box = J.boxes[sr.col];
+    const Box box = cld(J.boxes, sr.col);
     const int vox = box_vox(box);
     if (L >= (sr.n_chunks + 3) / 4 + (vox + 255) / 256) return;
     const DGeom G = J.G;
@@ -975,11 +1159,11 @@ __global__ __launch_bounds__(256) void kb_finalize(BatchArgs B) {
 __global__ __launch_bounds__(256) void kb_residual(BatchArgs B) {
     const int k = batch_job(B, blockIdx.x);
     const int L = blockIdx.x - B.prefix[k];
-    const BJob& J = B.jobs[k];
+    const BJob J = cld(B.jobs, k);
     if (J.sync != 1) return;
-    const int e = B.ep[k];
+    const int e = cld(B.ep, k);
     if (e < 0 || e >= J.n_epochs) return;
-    const EpochRec er = J.epochs[e];
+    const EpochRec er = cld(J.epochs, e);
     if (L * 4 >= er.uni_chunks) return;
     const DGeom G = J.G;
     ResArgs a{};

@@ -32,7 +32,7 @@ EXPORTS = (
     "ct_block_epoch", "ct_solver_state", "ct_true_residual", "ct_solve",
     "ct_solver_profile", "ct_solver_profile_read",
     "ct_batch_create", "ct_batch_destroy", "ct_batch_add", "ct_batch_remove", "ct_batch_epoch",
-    "ct_batch_job_epoch", "ct_job_footprint",
+    "ct_batch_job_epoch", "ct_batch_profile", "ct_batch_profile_read", "ct_job_footprint",
     "ct_last_error",
 )
 
@@ -134,6 +134,8 @@ def lib():
             "ct_batch_remove": [P, i32],
             "ct_batch_epoch": [P, i32, ctypes.POINTER(i32), P],
             "ct_batch_job_epoch": [P, i32, ctypes.POINTER(i32)],
+            "ct_batch_profile": [P, i32],
+            "ct_batch_profile_read": [P, ctypes.POINTER(ct_kernel_times)],
             "ct_job_footprint": [ctypes.POINTER(ct_geom_desc), ctypes.POINTER(ct_solver_params),
                                  ctypes.POINTER(ctypes.c_size_t)],
             "ct_last_error": [],
@@ -458,3 +460,14 @@ def ct_batch_job_epoch(batch: Batch, jid: int) -> int:
     e = i32()
     _check(lib().ct_batch_job_epoch(batch.handle, int(jid), ctypes.byref(e)))
     return int(e.value)
+
+
+def ct_batch_profile(batch: Batch, enable: bool = True):
+    _check(lib().ct_batch_profile(batch.handle, 1 if enable else 0))
+
+
+def ct_batch_profile_read(batch: Batch) -> dict:
+    """{kernel: (ms, launches)} of the batched launches since the last read."""
+    t = ct_kernel_times()
+    _check(lib().ct_batch_profile_read(batch.handle, ctypes.byref(t)))
+    return {name: (float(t.ms[k]), int(t.launches[k])) for k, name in enumerate(KERNEL_NAMES)}
