@@ -14,7 +14,9 @@ Other workloads (--workload): par2d_64 (the small parallel-beam case),
 cone3d_256 (256^3 cone beam, 360 views of 384^2, 12 view groups x 8 z-slabs,
 4 groups of 3, Poisson noise at 1e5 photons), batch64 (64 fan slices of
 uneven sizes, all jobs advanced by shared launches, against the same jobs
-solved one at a time).
+solved one at a time), serve40 (a Poisson stream of mixed fan and cone jobs
+at 40 jobs/s served for a fixed wall-clock window by the continuous-batching
+server, against the same stream served one job at a time).
 
 Printed as one JSON line.  value = ray-voxel updates per second over the
 timed epochs (2 nnz(A_{I_G}^J) per group update, from the exact density
@@ -43,6 +45,8 @@ VALU_PEAK_TFLOPS = 78.6          # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, n
 FLOPS_PER_UPDATE = 5.0           # select next crossing, segment length, advance, multiply-add
 GATHER_BYTES_PER_UPDATE = 4.0    # what an explicit-A SpMV would stream per nonzero
 BATCH_SIZES = (128, 256, 384, 512, 768, 1024)
+SERVE_FAN = (256, 384, 512, 768, 1024)
+SERVE_CONE = (64, 96, 128, 160, 192)
 
 
 def single_workload(name):
@@ -359,14 +363,126 @@ def run_batch(args):
     return out
 
 
+def serve_stream(n_jobs, seed=5000, rate=40.0):
+    """Arrival times and job kinds of the mixed serving stream."""
+    rng = np.random.default_rng(seed)
+    arr = np.cumsum(rng.exponential(1.0 / rate, n_jobs))
+    out = []
+    for k in range(n_jobs):
+        if rng.random() < 0.7:
+            out.append((float(arr[k]), "fan", int(rng.choice(SERVE_FAN)), int(rng.integers(2))))
+        else:
+            out.append((float(arr[k]), "cone", int(rng.choice(SERVE_CONE)), int(rng.integers(2))))
+    return out
+
+
+def run_serve(args):
+    """Serve the same Poisson stream twice for a fixed window: with the
+    continuous-batching server (capacity C) and one job at a time
+    (capacity 1).  Noise-free jobs, stop at true relative residual 1e-3 or
+    500 epochs."""
+    import torch
+    from paper_1709_00953_amd import ct, inputs
+
+    stream = serve_stream(args.jobs)
+    geo, pool = {}, {}
+    t_setup = time.perf_counter()
+    for _, kind, N, ph in stream:
+        key = (kind, N)
+        if key not in geo:
+            geo[key] = inputs.slice_fan(N) if kind == "fan" else inputs.slice_cone(N)
+        if (kind, N, ph) not in pool:
+            g = geo[key]
+            G = ct.ct_geom_create(g)
+            xt = torch.as_tensor(inputs.phantom_for(g, inputs.seed_for(5, 100 * len(pool) + ph))
+                                 .astype(np.float32), device="cuda")
+            p = torch.zeros(G.M, device="cuda")
+            for J in range(G.n):
+                ct.ct_block_fwd(G, list(range(G.m)), J, xt, p, flags=ct.CT_ACCUMULATE if J else 0)
+            pool[(kind, N, ph)] = p.cpu().numpy()
+            del G, xt, p
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    print(f"[bench] serve: {len(pool)} distinct measurement sets ready in {t_setup:.1f} s",
+          file=sys.stderr, flush=True)
+
+    def serve(capacity):
+        # density threshold: 1e-5 of the smallest voxel pitch in the mix (0.25 mm)
+        srv = ct.ct_server_create(capacity=capacity, hbm_budget=0, rel_tol=1e-3, check_every=10,
+                                  tau=2.5e-6, graph=True)
+        done, i, st = [], 0, None
+        t0 = time.perf_counter()
+        last = t0
+        while True:
+            now = time.perf_counter() - t0
+            if now >= args.window:
+                break
+            while i < len(stream) and stream[i][0] <= now:
+                _, kind, N, ph = stream[i]
+                p = (ct.sched_params(500, 1.0, 1.0, 4, 1.0, seed=inputs.seed_for(5, i)) if kind == "fan"
+                     else ct.sched_params(500, 1.0, 1.0, 3, 2.0, seed=inputs.seed_for(5, i)))
+                ct.ct_server_submit(srv, geo[(kind, N)], p, pool[(kind, N, ph)], tag=i)
+                i += 1
+            st = ct.ct_server_tick(srv)
+            done += ct.ct_server_poll(srv)
+            if st["active"] == 0 and st["queued"] == 0 and i < len(stream):
+                time.sleep(max(0.0, min(0.01, stream[i][0] - (time.perf_counter() - t0))))
+            if time.perf_counter() - last > 10:
+                last = time.perf_counter()
+                print(f"[bench] serve cap {capacity}: t={now:.0f}s submitted {i} active "
+                      f"{st['active']} queued {st['queued']} done {len(done)}",
+                      file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        upd = st["updates"] if st else 0
+        lat = np.array([d["t_done"] - d["t_submit"] for d in done])
+        wait = np.array([d["t_admit"] - d["t_submit"] for d in done])
+        conv = sum(1 for d in done if d["status"] == ct.CT_OK)
+        res = {"capacity": capacity, "window_s": round(wall, 3), "submitted": i,
+               "completed": len(done), "converged": conv,
+               "jobs_per_s": len(done) / wall,
+               "updates_per_s": upd / wall,
+               "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
+               "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
+               "p50_queue_wait_s": float(np.percentile(wait, 50)) if len(wait) else None,
+               "mean_epochs": float(np.mean([d["epochs"] for d in done])) if done else None,
+               "still_active": st["active"] if st else 0, "still_queued": st["queued"] if st else 0,
+               "completed_sizes": sorted(stream[d["tag"]][1][0] + str(stream[d["tag"]][2])
+                                         for d in done)}
+        del srv
+        return res
+
+    served = serve(args.capacity)
+    plain = serve(1)
+    out = base_record(args, served["updates_per_s"], served["window_s"] * 1e3, 1)
+    out["config"] = {
+        "workload": ("Poisson stream, mean 40 jobs/s (seed 5000): 70% fan slices N in "
+                     f"{list(SERVE_FAN)} (4x4 blocks, alpha 1, s 4, b 1), 30% cone N in "
+                     f"{list(SERVE_CONE)} (360 views of (1.5N)^2, 12x8 blocks, alpha 1, s 3, b 2), "
+                     "noise-free y from one of 2 seeded phantoms per size, stop at true rel. "
+                     "residual 1e-3 (checked every 10 epochs) or 500 epochs, HBM budget 80% of free"),
+        "setup_s": round(t_setup, 3)}
+    out["served"] = served
+    out["plain"] = plain
+    out["jobs_per_s"] = served["jobs_per_s"]
+    out["p50_latency_s"] = served["p50_latency_s"]
+    out["p99_latency_s"] = served["p99_latency_s"]
+    out["roofline"] = None
+    out["cpu_baseline"] = None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fan2d_512",
-                    choices=["fan2d_512", "par2d_64", "cone3d_256", "batch64"])
-    ap.add_argument("--jobs", type=int, default=64, help="batch64: number of slices")
+                    choices=["fan2d_512", "par2d_64", "cone3d_256", "batch64", "serve40"])
+    ap.add_argument("--jobs", type=int, default=None,
+                    help="batch64: slices (64); serve40: jobs in the stream (1000)")
+    ap.add_argument("--window", type=float, default=30.0, help="serve40: seconds served")
+    ap.add_argument("--capacity", type=int, default=16, help="serve40: resident jobs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     args = ap.parse_args()
@@ -379,7 +495,14 @@ def main():
 
     import torch
     torch.cuda.set_device(0)
-    out = run_batch(args) if args.workload == "batch64" else run_single(args)
+    if args.workload == "batch64":
+        args.jobs = args.jobs or 64
+        out = run_batch(args)
+    elif args.workload == "serve40":
+        args.jobs = args.jobs or 1000
+        out = run_serve(args)
+    else:
+        out = run_single(args)
     print(json.dumps(out), flush=True)
 
 

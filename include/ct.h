@@ -214,6 +214,12 @@ int ct_solver_state(const ct_solver* solver, float** z, float** r);
  * synchronous on `stream`. */
 int ct_true_residual(ct_solver* solver, const float* y, const float* x, double* rel,
                      void* stream);
+/* Asynchronous form for convergence checks that must not stall the stream:
+ * out (device, 2 doubles) receives ||y - A x||^2 and ||y||^2, each a
+ * fixed-order float64 sum.  Uses the solver's scratch (do not overlap with
+ * an epoch of the same solver on another stream). */
+int ct_residual_norms(ct_solver* solver, const float* y, const float* x, double* out,
+                      void* stream);
 
 /* Kernel timing: while enabled, every kernel a solver enqueues is bracketed
  * by HIP events on its stream (a small per-launch cost).  Reading syncs those
@@ -293,6 +299,65 @@ int ct_batch_job_epoch(const ct_batch* batch, int32_t id, int32_t* epoch);
  * ignored and the launches go out one by one). */
 int ct_batch_profile(ct_batch* batch, int32_t enable);
 int ct_batch_profile_read(ct_batch* batch, ct_kernel_times* out);
+
+/* ---- serving ---------------------------------------------------------------
+ * A request loop over a batch (continuous batching): jobs are submitted with
+ * their geometry, schedule parameters and measurements, wait in a FIFO queue,
+ * and enter the batch at a tick boundary when a slot is free and their device
+ * footprint fits the HBM budget.  While resident, a job's geometry tables,
+ * y, x and z^j stay on the device; every tick runs one batch epoch for all
+ * resident jobs, and every check_every epochs (and at the epoch cap) a job's
+ * true relative residual is computed asynchronously and read back at the next
+ * tick, which retires the job once it is <= rel_tol or the cap is reached.
+ * A retired job's x is copied to the host and its device memory freed.  The
+ * server allocates device memory itself (hipMalloc).  All ticks of a server
+ * must use the same stream. */
+typedef struct ct_server ct_server;
+typedef struct ct_server_params {
+    int32_t capacity;           /* most resident jobs (1..256)                  */
+    int64_t hbm_budget;         /* device bytes resident jobs may use; 0 = 80% of
+                                   free memory when the server is created      */
+    double rel_tol;             /* retire at true relative residual <= rel_tol  */
+    int32_t check_every;        /* epochs between residual checks (>= 1)        */
+    double tau;                 /* nnz threshold of the density table (mm)      */
+    int32_t use_graph;          /* replay batch epochs from a HIP graph         */
+} ct_server_params;
+typedef struct ct_server_job {
+    const ct_geom_desc* geom;   /* copied at submit                             */
+    ct_sched_params sched;      /* sched.epochs = epoch cap                     */
+    ct_solver_params solver;
+    const float* y;             /* host [M], copied at submit                   */
+    int64_t tag;                /* caller's label, returned with the result     */
+} ct_server_job;
+typedef struct ct_server_done {
+    int64_t tag;
+    int32_t id;
+    int32_t status;             /* CT_OK: converged; CT_NOT_CONVERGED: cap; <0 error */
+    int32_t epochs;             /* epochs run                                   */
+    double rel_residual;        /* last checked true relative residual          */
+    double t_submit, t_admit, t_done;   /* seconds on the server's clock        */
+    int64_t bytes;              /* device bytes charged to the budget           */
+    int64_t updates;            /* ray-voxel updates of its epochs (2 nnz per
+                                   group update)                                */
+} ct_server_done;
+typedef struct ct_server_stats {
+    int32_t active, queued;
+    int64_t admitted, retired;
+    int64_t updates;            /* ray-voxel updates of all epochs run so far   */
+    int64_t bytes_in_use, budget;
+    double now;                 /* server clock (s)                             */
+} ct_server_stats;
+int ct_server_create(const ct_server_params* params, ct_server** out);
+void ct_server_destroy(ct_server* server);
+/* Queues a job; CT_EINVAL if its geometry is invalid or it can never fit the
+ * budget. */
+int ct_server_submit(ct_server* server, const ct_server_job* job, int32_t* id);
+/* Retire finished jobs, admit queued ones, run one batch epoch. */
+int ct_server_tick(ct_server* server, void* stream, ct_server_stats* stats);
+/* Up to max finished jobs (oldest first), removed from the server's list. */
+int ct_server_poll(ct_server* server, ct_server_done* out, int32_t max, int32_t* n);
+/* x (host, [N]) of a finished job; each result can be taken once. */
+int ct_server_result(ct_server* server, int32_t id, float* x);
 
 /* Device bytes one job needs (geometry tables + workspace): for admission
  * by memory budget. */

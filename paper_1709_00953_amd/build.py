@@ -35,7 +35,7 @@ def build(verbose: bool = False) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs = []
-    for src, lang in (("ct_kernels.hip", "hip"), ("ct_api.cpp", "hip")):
+    for src, lang in (("ct_kernels.hip", "hip"), ("ct_api.cpp", "hip"), ("ct_server.cpp", "hip")):
         obj = os.path.join(bdir, src + ".o")
         cmd = [cc, "-x", lang, "-c", os.path.join(CSRC, src), "-o", obj] + common
         if verbose:

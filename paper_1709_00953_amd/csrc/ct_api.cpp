@@ -25,7 +25,7 @@ using namespace ct;
 // ---------------------------------------------------------------------------
 static thread_local std::string g_err;
 
-static int fail(int code, const char* fmt, ...) {
+int ct::fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -73,7 +73,6 @@ struct ct_geom {
     DGeom G{};
     Entry* d_all = nullptr;
     unsigned long long* d_nnz = nullptr;
-    double* d_part = nullptr;          // residual-norm partials
     Box* d_boxes = nullptr;            // [n]
 };
 
@@ -434,7 +433,7 @@ static void build_frames(const ct_geom* g, std::vector<Ray2F>& rayf, std::vector
 struct DevLayout {
     size_t off_view, off_rayf, off_rayb, off_flags, off_tiles, off_rbt, off_troff, off_chunks, off_rbc, off_wch,
         off_rbj, off_all,
-        off_nnz, off_part, off_boxes, total;
+        off_nnz, off_boxes, total;
 };
 
 static DevLayout dev_layout(const ct_geom* g) {
@@ -458,7 +457,6 @@ static DevLayout dev_layout(const ct_geom* g) {
     L.off_rbj = take(g->rbj_chunk_ptr.size() * sizeof(int32_t));
     L.off_all = take(g->all_entries.size() * sizeof(Entry));
     L.off_nnz = take((size_t)g->m * g->n * sizeof(unsigned long long));
-    L.off_part = take(2 * 1024 * sizeof(double));
     L.off_boxes = take(g->boxes.size() * sizeof(Box));
     L.total = o;
     return L;
@@ -543,7 +541,6 @@ static int geom_ensure_device(ct_geom* g) {
     G.n_cols = g->n;
     g->d_all = (Entry*)(base + L.off_all);
     g->d_nnz = (unsigned long long*)(base + L.off_nnz);
-    g->d_part = (double*)(base + L.off_part);
     g->d_boxes = (Box*)(base + L.off_boxes);
     g->dbytes = L.total;
     g->device = dev;
@@ -1061,8 +1058,10 @@ extern "C" int ct_schedule_export(const ct_schedule* s, ct_sched_view* out) {
 // ---------------------------------------------------------------------------
 // solver
 // ---------------------------------------------------------------------------
+constexpr int kResBlocks = 1024;        // work-groups of the residual-norm reduction
+
 struct WsLayout {
-    size_t z, r, q, xg, pg, pq, mu, total;
+    size_t z, r, q, xg, pg, pq, mu, part, total;
 };
 
 static WsLayout ws_layout(const ct_geom* g) {
@@ -1080,6 +1079,7 @@ static WsLayout ws_layout(const ct_geom* g) {
     L.pg = take((size_t)g->m * g->max_tiles * sizeof(double));
     L.pq = take((size_t)std::max(g->total_chunks, g->max_step_wchunks) * sizeof(double));
     L.mu = take((size_t)g->m * sizeof(double));
+    L.part = take((2 * (size_t)kResBlocks + 2) * sizeof(double));
     L.total = o;
     return L;
 }
@@ -1155,6 +1155,7 @@ struct ct_solver {
     double* pg = nullptr;
     double* pq = nullptr;
     double* mu = nullptr;
+    double* part = nullptr;             // residual-norm partials, then the two sums
 };
 
 extern "C" int ct_solver_workspace_bytes(const ct_geom* g, const ct_solver_params* p, size_t* bytes) {
@@ -1187,6 +1188,7 @@ extern "C" int ct_solver_create(ct_geom* g, const ct_solver_params* p, void* ws,
     s->pg = (double*)(s->ws + L.pg);
     s->pq = (double*)(s->ws + L.pq);
     s->mu = (double*)(s->ws + L.mu);
+    s->part = (double*)(s->ws + L.part);
     *out = s;
     return CT_OK;
 }
@@ -1358,12 +1360,9 @@ extern "C" int ct_block_epoch(ct_solver* s, const ct_schedule* sc, int32_t e, co
     return CT_OK;
 }
 
-extern "C" int ct_true_residual(ct_solver* s, const float* y, const float* x, double* rel, void* stream) {
-    if (!s || !y || !x || !rel) return fail(CT_EINVAL, "NULL argument");
+// ||y - A x||^2 and ||y||^2 (float64, fixed order) into s->part[2K], s->part[2K+1].
+static int enqueue_norms(ct_solver* s, const float* y, const float* x, hipStream_t st) {
     ct_geom* g = s->geom;
-    int rc = check_device(g);
-    if (rc) return rc;
-    hipStream_t st = (hipStream_t)stream;
     for (int J = 0; J < g->n; ++J) {
         FwdArgs a = fwd_all(g, J);
         a.mode = 0;
@@ -1372,17 +1371,32 @@ extern "C" int ct_true_residual(ct_solver* s, const float* y, const float* x, do
         a.out = s->q;
         HIPCHK(launch_fwd(g->G, a, st));
     }
-    const int nblk = (int)std::min<int64_t>(1024, (g->M + 255) / 256);
-    HIPCHK(launch_resnorm(y, s->q, g->M, g->d_part, nblk, st));
-    std::vector<double> part(2 * (size_t)nblk);
-    HIPCHK(hipMemcpyAsync(part.data(), g->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    const int nblk = (int)std::min<int64_t>(kResBlocks, (g->M + 255) / 256);
+    HIPCHK(launch_resnorm(y, s->q, g->M, s->part, nblk, st));
+    HIPCHK(launch_sum_pairs(s->part, nblk, s->part + 2 * kResBlocks, st));
+    return CT_OK;
+}
+
+extern "C" int ct_residual_norms(ct_solver* s, const float* y, const float* x, double* out, void* stream) {
+    if (!s || !y || !x || !out) return fail(CT_EINVAL, "NULL argument");
+    int rc = check_device(s->geom);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = enqueue_norms(s, y, x, st))) return rc;
+    HIPCHK(hipMemcpyAsync(out, s->part + 2 * kResBlocks, 2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return CT_OK;
+}
+
+extern "C" int ct_true_residual(ct_solver* s, const float* y, const float* x, double* rel, void* stream) {
+    if (!s || !y || !x || !rel) return fail(CT_EINVAL, "NULL argument");
+    int rc = check_device(s->geom);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = enqueue_norms(s, y, x, st))) return rc;
+    double ab[2];
+    HIPCHK(hipMemcpyAsync(ab, s->part + 2 * kResBlocks, sizeof ab, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    double a = 0.0, b = 0.0;
-    for (int i = 0; i < nblk; ++i) {
-        a += part[2 * i];
-        b += part[2 * i + 1];
-    }
-    *rel = b > 0 ? std::sqrt(a / b) : 0.0;
+    *rel = ab[1] > 0 ? std::sqrt(ab[0] / ab[1]) : 0.0;
     return CT_OK;
 }
 

@@ -264,6 +264,9 @@ struct BatchArgs {
 
 enum { kPhBack = 0, kPhFwd = 1, kPhStep = 2, kPhFin = 3, kPhRes = 4 };
 
+// Records a message for ct_last_error() and returns code.
+int fail(int code, const char* fmt, ...);
+
 hipError_t launch_fwd(const DGeom& G, const FwdArgs& a, hipStream_t st);
 hipError_t launch_back(const DGeom& G, const BackArgs& a, int n_groups, hipStream_t st);
 hipError_t launch_step(const StepArgs& s, int n_groups, hipStream_t st);
@@ -275,6 +278,7 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
 // forward phases); `blocks` is prefix[n_jobs].
 hipError_t launch_batch(int phase, int kind, const BatchArgs& b, int blocks, hipStream_t st);
 hipError_t launch_batch_advance(const BatchArgs& b, hipStream_t st);
+hipError_t launch_sum_pairs(const double* part, int nblk, double* out, hipStream_t st);
 hipError_t launch_resnorm(const float* y, const float* p, int64_t n, double* part, int nblk,
                           hipStream_t st);
 

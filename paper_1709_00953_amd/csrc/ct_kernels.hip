@@ -1217,6 +1217,23 @@ __global__ __launch_bounds__(256) void k_resnorm(const float* y, const float* p,
     }
 }
 
+// Fixed-order sum of nblk (a, b) partial pairs into out[0], out[1] (one work-group).
+__global__ __launch_bounds__(256) void k_sum_pairs(const double* part, int nblk, double* out) {
+    __shared__ double sh[4];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += 256) {
+        a += part[2 * i];
+        b += part[2 * i + 1];
+    }
+    const double ta = block_sum256(a, sh);
+    __syncthreads();
+    const double tb = block_sum256(b, sh);
+    if (threadIdx.x == 0) {
+        out[0] = ta;
+        out[1] = tb;
+    }
+}
+
 // ----------------------------------------------------------------------------
 // host-side launchers (internal linkage for the API file)
 // ----------------------------------------------------------------------------
@@ -1343,6 +1360,11 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st) {
 hipError_t launch_resnorm(const float* y, const float* p, int64_t n, double* part, int nblk,
                           hipStream_t st) {
     hipLaunchKernelGGL(k_resnorm, dim3(nblk), dim3(256), 0, st, y, p, n, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_pairs(const double* part, int nblk, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, st, part, nblk, out);
     return hipGetLastError();
 }
 

@@ -29,10 +29,12 @@ EXPORTS = (
     "ct_block_fwd", "ct_block_back",
     "ct_schedule_create", "ct_schedule_import", "ct_schedule_export", "ct_schedule_destroy",
     "ct_solver_workspace_bytes", "ct_solver_create", "ct_solver_destroy", "ct_solver_reset",
-    "ct_block_epoch", "ct_solver_state", "ct_true_residual", "ct_solve",
+    "ct_block_epoch", "ct_solver_state", "ct_true_residual", "ct_residual_norms", "ct_solve",
     "ct_solver_profile", "ct_solver_profile_read",
     "ct_batch_create", "ct_batch_destroy", "ct_batch_add", "ct_batch_remove", "ct_batch_epoch",
-    "ct_batch_job_epoch", "ct_batch_profile", "ct_batch_profile_read", "ct_job_footprint",
+    "ct_batch_job_epoch", "ct_batch_profile", "ct_batch_profile_read",
+    "ct_server_create", "ct_server_destroy", "ct_server_submit", "ct_server_tick", "ct_server_poll",
+    "ct_server_result", "ct_job_footprint",
     "ct_last_error",
 )
 
@@ -86,6 +88,27 @@ class ct_solver_params(ctypes.Structure):
     _fields_ = [("sync", i32)]
 
 
+class ct_server_params(ctypes.Structure):
+    _fields_ = [("capacity", i32), ("hbm_budget", i64), ("rel_tol", f64), ("check_every", i32),
+                ("tau", f64), ("use_graph", i32)]
+
+
+class ct_server_job(ctypes.Structure):
+    _fields_ = [("geom", ctypes.POINTER(ct_geom_desc)), ("sched", ct_sched_params),
+                ("solver", ct_solver_params), ("y", P), ("tag", i64)]
+
+
+class ct_server_done(ctypes.Structure):
+    _fields_ = [("tag", i64), ("id", i32), ("status", i32), ("epochs", i32), ("rel_residual", f64),
+                ("t_submit", f64), ("t_admit", f64), ("t_done", f64), ("bytes", i64),
+                ("updates", i64)]
+
+
+class ct_server_stats(ctypes.Structure):
+    _fields_ = [("active", i32), ("queued", i32), ("admitted", i64), ("retired", i64),
+                ("updates", i64), ("bytes_in_use", i64), ("budget", i64), ("now", f64)]
+
+
 class ct_solve_params(ctypes.Structure):
     _fields_ = [("sched", ct_sched_params), ("solver", ct_solver_params), ("tau", f64),
                 ("rel_tol", f64), ("check_every", i32)]
@@ -125,6 +148,13 @@ def lib():
             "ct_block_epoch": [P, P, i32, P, P, P],
             "ct_solver_state": [P, ctypes.POINTER(P), ctypes.POINTER(P)],
             "ct_true_residual": [P, P, P, ctypes.POINTER(f64), P],
+            "ct_residual_norms": [P, P, P, P, P],
+            "ct_server_create": [ctypes.POINTER(ct_server_params), ctypes.POINTER(P)],
+            "ct_server_destroy": [P],
+            "ct_server_submit": [P, ctypes.POINTER(ct_server_job), ctypes.POINTER(i32)],
+            "ct_server_tick": [P, P, ctypes.POINTER(ct_server_stats)],
+            "ct_server_poll": [P, ctypes.POINTER(ct_server_done), i32, ctypes.POINTER(i32)],
+            "ct_server_result": [P, i32, P],
             "ct_solve": [P, ctypes.POINTER(ct_solve_params), P, P, ctypes.POINTER(ct_solve_stats), P],
             "ct_solver_profile": [P, i32],
             "ct_solver_profile_read": [P, ctypes.POINTER(ct_kernel_times)],
@@ -389,6 +419,16 @@ def ct_true_residual(solver: Solver, y, x, stream=None) -> float:
     return float(rel.value)
 
 
+def ct_residual_norms(solver: Solver, y, x, out, stream=None):
+    """Asynchronous: out (device float64 [2]) <- ||y - A x||^2, ||y||^2."""
+    import torch
+    g = solver.geom
+    if out.dtype != torch.float64 or out.numel() < 2 or not out.is_cuda:
+        raise ValueError("out must be a device float64 tensor of 2 elements")
+    _check(lib().ct_residual_norms(solver.handle, _dev(y, g.M, "y"), _dev(x, g.N, "x"),
+                                   P(out.data_ptr()), _stream(stream)))
+
+
 def ct_solver_profile(solver: Solver, enable: bool = True):
     _check(lib().ct_solver_profile(solver.handle, 1 if enable else 0))
 
@@ -471,3 +511,61 @@ def ct_batch_profile_read(batch: Batch) -> dict:
     t = ct_kernel_times()
     _check(lib().ct_batch_profile_read(batch.handle, ctypes.byref(t)))
     return {name: (float(t.ms[k]), int(t.launches[k])) for k, name in enumerate(KERNEL_NAMES)}
+
+
+# ----------------------------------------------------------------------------
+# serving
+# ----------------------------------------------------------------------------
+class Server:
+    def __init__(self, handle):
+        self.handle = handle
+        self.n_vox = {}         # job id -> N
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.ct_server_destroy(h)
+
+
+def ct_server_create(capacity=16, hbm_budget=0, rel_tol=1e-3, check_every=10, tau=0.0,
+                     graph=True) -> Server:
+    p = ct_server_params(int(capacity), int(hbm_budget), float(rel_tol), int(check_every), float(tau),
+                         1 if graph else 0)
+    h = P()
+    _check(lib().ct_server_create(ctypes.byref(p), ctypes.byref(h)))
+    return Server(h)
+
+
+def ct_server_submit(server: Server, g, params: ct_sched_params, y, sync=CT_SYNC_COLUMN, tag=0) -> int:
+    """Queue a job: geometry ``g`` (inputs.Geometry), schedule parameters,
+    host measurements ``y`` (float32 [M])."""
+    d, keep = make_desc(g)
+    yh = np.ascontiguousarray(y, dtype=np.float32)
+    if yh.size != g.n_rays:
+        raise ValueError(f"y has {yh.size} values, the geometry {g.n_rays} rays")
+    job = ct_server_job(ctypes.pointer(d), params, ct_solver_params(sync), _np_ptr(yh), int(tag))
+    jid = i32()
+    _check(lib().ct_server_submit(server.handle, ctypes.byref(job), ctypes.byref(jid)))
+    server.n_vox[int(jid.value)] = g.n_vox
+    return int(jid.value)
+
+
+def ct_server_tick(server: Server, stream=None) -> dict:
+    st = ct_server_stats()
+    _check(lib().ct_server_tick(server.handle, _stream(stream), ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in ct_server_stats._fields_}
+
+
+def ct_server_poll(server: Server, max_n: int = 256) -> list:
+    arr = (ct_server_done * max_n)()
+    n = i32()
+    _check(lib().ct_server_poll(server.handle, arr, int(max_n), ctypes.byref(n)))
+    return [{k: getattr(arr[i], k) for k, _ in ct_server_done._fields_} for i in range(n.value)]
+
+
+def ct_server_result(server: Server, jid: int) -> np.ndarray:
+    if int(jid) not in server.n_vox:
+        raise CtError(CT_EINVAL, f"no job {jid} was submitted to this server")
+    x = np.zeros(server.n_vox[int(jid)], dtype=np.float32)
+    _check(lib().ct_server_result(server.handle, int(jid), _np_ptr(x)))
+    return x
