@@ -56,3 +56,28 @@ def rays(geom):
         raise ValueError(f"unknown geometry kind {geom.kind}")
     return (np.ascontiguousarray(org.reshape(-1, 3)),
             np.ascontiguousarray(dirn.reshape(-1, 3)), divergent)
+
+
+def rays_at(geom, idx):
+    """Rays of the given ray indices only (same definitions as ``rays``), for
+    geometries too large to hold every ray."""
+    idx = np.asarray(idx, dtype=np.int64)
+    V = np.asarray(geom.views, dtype=np.float64)
+    nv = geom.nv if geom.kind == CONE3D_FLAT else 1
+    view = idx // (nv * geom.nu)
+    iv = (idx // geom.nu) % nv
+    iu = idx % geom.nu
+    a, c, eu, ev = V[view, 0:3], V[view, 3:6], V[view, 6:9], V[view, 9:12]
+    u = ((iu - 0.5 * (geom.nu - 1)) * geom.pu)[:, None]
+    if geom.kind == PAR2D:
+        return c + u * eu, a.copy(), False
+    if geom.kind == FAN2D_FLAT:
+        return a.copy(), c + u * eu - a, True
+    if geom.kind == FAN2D_CURVED:
+        axis = c - a
+        axis = axis / np.linalg.norm(axis, axis=1, keepdims=True)
+        return a.copy(), np.cos(u) * axis + np.sin(u) * eu, True
+    if geom.kind == CONE3D_FLAT:
+        v = ((iv - 0.5 * (geom.nv - 1)) * geom.pv)[:, None]
+        return a.copy(), c + u * eu + v * ev - a, True
+    raise ValueError(f"unknown geometry kind {geom.kind}")

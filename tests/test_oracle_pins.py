@@ -319,3 +319,16 @@ def test_large_relaxation_diverges_small_converges():
     large = csgd.run(S, y, sampler.make_schedule(P, 20, 0.5, 1.0, 1, 8.0, 1000))
     assert csgd.true_rel_residual(S, y, small.x) < 0.2 * r0
     assert csgd.true_rel_residual(S, y, large.x) > 10 * r0
+
+
+@pytest.mark.parametrize("name", ["par2d", "fan_flat", "fan_curved", "cone"])
+def test_rays_at_matches_all_rays(name):
+    """The subset ray generator used at full sizes gives the same lines as the
+    whole-geometry one (same origin, same direction up to rounding)."""
+    g = tiny_geoms()[name]
+    org, dirn, div = rays.rays(g)
+    idx = np.random.default_rng(3).choice(org.shape[0], size=min(50, org.shape[0]), replace=False)
+    o2, d2, div2 = rays.rays_at(g, idx)
+    assert div2 == div
+    np.testing.assert_allclose(o2, org[idx], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(d2, dirn[idx], rtol=1e-14, atol=1e-14)
