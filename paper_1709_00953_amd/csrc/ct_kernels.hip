@@ -645,25 +645,32 @@ __global__ __launch_bounds__(256) void k_back2(DGeom G, BA a) {
 // frame coordinates A = (c-S).n, Bu = (c-S).e_u, Bv = (c-S).e_v.  The ray of
 // bin (u, v) is S + t D~ with D~ = n + (u/sdd) e_u + (v/sdd) e_v; at depth
 // A + s it lies at  s D~ - du e_u - dv e_v  from c, where du = Bu - A u/sdd and
-// dv = Bv - A v/sdd (float64: they cancel lever arms of the source distance).
-// Its x/y/z slabs of the voxel are then s-intervals centred on
+// dv = Bv - A v/sdd.  Its x/y/z slabs of the voxel are s-intervals centred on
 //   s_k = du a_k + dv b_k,  a_k = e_u,k / D~_k,  b_k = e_v,k / D~_k
 // with half-widths w_k = h_k / |D~_k|, and the clip length is
 //   |D~| max(0, min_k(s_k + w_k) - max_k(s_k - w_k)).
 // A work-group owns an 8 x 8 x 4 voxel tile (one voxel per lane) and walks the
-// views of the group; per (tile, view) it bounds the tile's shadow by the
-// projection of its bounding sphere, stages the per-ray constants of that
-// detector window (and r) in LDS, and every voxel then clips the candidate
-// rays of its own shadow window.
+// views of the group.  Per (tile, view), one lane forms in float64 the tile
+// centre's frame coordinates, the bases of du and dv along the detector, and
+// a linearised shadow: the bin coordinate sdd B / A of a voxel centre is
+// affine in the voxel's offset from the tile centre up to a remainder bounded
+// by the Hessian of B/A (norm <= 2 (1 + |B/A|) / A^2) over the tile's
+// bounding sphere, and so is the half-extent of the voxel's own projection.
+// Each voxel thus gets a rigorous candidate window of bins from a few float32
+// FMAs; du at the window's first bin needs one float64 FMA (it cancels lever
+// arms of the source distance), the steps along the window are float32.  The
+// per-ray constants of the tile's detector window and r are staged in LDS,
+// and each voxel runs one flattened loop over its window.
 struct ViewP3 {
-    double At, But, Bvt;          // frame coordinates of the tile centre
-    double ax, ay, az;            // A per voxel step in x, y, z
-    double bux, buy, buz, bvx, bvy, bvz;
-    double isdd;                  // 1 / sdd
-    float n[3], eu[3], ev[3];
-    float sdd;
+    double D0u, D0v, slu, slv;    // du = D0u + (iu - uref) slu + dBu - dA us(iu) (same for v)
+    float ax, ay, az;             // A, Bu, Bv per voxel step in x, y, z
+    float bux, buy, buz, bvx, bvy, bvz;
+    float gux, guy, guz, gvx, gvy, gvz;   // bin coordinates per voxel step
+    float betu, betv, Wu, Wv;     // tile-centre bins, window half-widths (bins)
+    float usr, vsr, dus, dvs;     // u/sdd at uref and per bin (same for v)
+    float eu[3], ev[3];
     int32_t view, fu0, fu1, fv0, fv1;     // detector window [fu0, fu1) x [fv0, fv1)
-    int32_t flags, pad;
+    int32_t uref, vref, flags;
 };
 
 constexpr int kRayC = 256;        // staged rays per pass
@@ -671,48 +678,123 @@ constexpr int kRayC = 256;        // staged rays per pass
 __device__ __forceinline__ void view_params3(const DGeom& G, const Tile& tl, const double tc[3],
                                              const double tr, ViewP3& P) {
     const double* V = view_of(G, tl.view);
+    const double sdd = V[15], isdd = V[16];
     const double q[3] = {tc[0] - V[0], tc[1] - V[1], tc[2] - V[2]};
-    P.At = fma(q[0], V[12], fma(q[1], V[13], q[2] * V[14]));
-    P.But = fma(q[0], V[6], fma(q[1], V[7], q[2] * V[8]));
-    P.Bvt = fma(q[0], V[9], fma(q[1], V[10], q[2] * V[11]));
-    P.ax = V[12] * G.vx;
-    P.ay = V[13] * G.vy;
-    P.az = V[14] * G.vz;
-    P.bux = V[6] * G.vx;
-    P.buy = V[7] * G.vy;
-    P.buz = V[8] * G.vz;
-    P.bvx = V[9] * G.vx;
-    P.bvy = V[10] * G.vy;
-    P.bvz = V[11] * G.vz;
-    P.isdd = V[16];
+    const double At = fma(q[0], V[12], fma(q[1], V[13], q[2] * V[14]));
+    const double But = fma(q[0], V[6], fma(q[1], V[7], q[2] * V[8]));
+    const double Bvt = fma(q[0], V[9], fma(q[1], V[10], q[2] * V[11]));
+    const double h[3] = {G.vx, G.vy, G.vz};
+    P.ax = (float)(V[12] * h[0]);
+    P.ay = (float)(V[13] * h[1]);
+    P.az = (float)(V[14] * h[2]);
+    P.bux = (float)(V[6] * h[0]);
+    P.buy = (float)(V[7] * h[1]);
+    P.buz = (float)(V[8] * h[2]);
+    P.bvx = (float)(V[9] * h[0]);
+    P.bvy = (float)(V[10] * h[1]);
+    P.bvz = (float)(V[11] * h[2]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         P.eu[k] = (float)V[6 + k];
         P.ev[k] = (float)V[9 + k];
-        P.n[k] = (float)V[12 + k];
     }
-    P.sdd = (float)V[15];
     P.view = tl.view;
     P.flags = G.view_flags[tl.view];
-    // shadow of the sphere of radius tr around the tile centre: a point
-    // c + r (|r| <= tr) moves the bin coordinate sdd B / A by at most
-    // sdd tr sqrt(1 + (B/A)^2) / (A - tr)
     const double c0u = 0.5 * (double)(G.nu - 1), c0v = 0.5 * (double)(G.nv - 1);
+    const double R = (double)G.radius;
     int u0 = tl.u0, u1 = tl.u1, v0 = tl.v0, v1 = tl.v1;
-    if (P.At > 1.0001 * tr) {
-        const double tu = P.But / P.At, tv = P.Bvt / P.At;
-        const double den = V[15] * tr / (P.At - tr);
-        const double bu = V[15] * tu / G.pu + c0u, wu = den * sqrt(1.0 + tu * tu) / G.pu + 1e-3;
-        const double bv = V[15] * tv / G.pv + c0v, wv = den * sqrt(1.0 + tv * tv) / G.pv + 1e-3;
+    double bu = c0u, bv = c0v, Wu = 1e9, Wv = 1e9;
+    double gu[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
+    if (At > 1.0001 * (tr + R)) {
+        const double tu = But / At, tv = Bvt / At;
+        bu = sdd * tu / G.pu + c0u;
+        bv = sdd * tv / G.pv + c0v;
+        // detector window of the tile: shadow of its bounding sphere
+        const double den = sdd * tr / (At - tr);
+        const double wu = den * sqrt(1.0 + tu * tu) / G.pu + 1e-3, wv = den * sqrt(1.0 + tv * tv) / G.pv + 1e-3;
         u0 = max(u0, (int)fmax(ceil(bu - wu), -1.0));
         u1 = min(u1, (int)fmin(floor(bu + wu), 2e9) + 1);
         v0 = max(v0, (int)fmax(ceil(bv - wv), -1.0));
         v1 = min(v1, (int)fmin(floor(bv + wv), 2e9) + 1);
+        // gradient of the bin coordinates at the tile centre (per mm), the
+        // voxel's own half-extent there, and the linearisation remainders
+        double hu = 0.0, hv = 0.0, hs = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double du_k = sdd * (V[6 + k] - tu * V[12 + k]) / At / G.pu;
+            const double dv_k = sdd * (V[9 + k] - tv * V[12 + k]) / At / G.pv;
+            gu[k] = du_k * h[k];
+            gv[k] = dv_k * h[k];
+            hu += 0.5 * h[k] * fabs(du_k);
+            hv += 0.5 * h[k] * fabs(dv_k);
+            hs += 0.5 * h[k];
+        }
+        const double amin = At - tr - R;
+        const double Hu = 2.0 * sdd * (1.0 + (fabs(But) + tr + R) / amin) / (amin * amin) / G.pu;
+        const double Hv = 2.0 * sdd * (1.0 + (fabs(Bvt) + tr + R) / amin) / (amin * amin) / G.pv;
+        Wu = hu + Hu * (tr * hs + 0.5 * tr * tr + 0.5 * R * R);
+        Wv = hv + Hv * (tr * hs + 0.5 * tr * tr + 0.5 * R * R);
     }
     P.fu0 = u0;
     P.fu1 = max(u0, u1);
     P.fv0 = v0;
     P.fv1 = max(v0, v1);
+    P.betu = (float)bu;
+    P.betv = (float)bv;
+    P.gux = (float)gu[0];
+    P.guy = (float)gu[1];
+    P.guz = (float)gu[2];
+    P.gvx = (float)gv[0];
+    P.gvy = (float)gv[1];
+    P.gvz = (float)gv[2];
+    // float32 rounding of the window centre (|beta| <= a few thousand bins)
+    P.Wu = (float)fmin(Wu, 1e9) + 2e-3f + 1e-6f * fabsf((float)bu);
+    P.Wv = (float)fmin(Wv, 1e9) + 2e-3f + 1e-6f * fabsf((float)bv);
+    // bases of du, dv: reference bins near the tile centre's shadow
+    const int uref = (int)fmin(fmax(rint(bu), -1e6), 1e6), vref = (int)fmin(fmax(rint(bv), -1e6), 1e6);
+    const double usr = ((double)uref - c0u) * G.pu * isdd, vsr = ((double)vref - c0v) * G.pv * isdd;
+    P.uref = uref;
+    P.vref = vref;
+    P.D0u = fma(-At, usr, But);
+    P.D0v = fma(-At, vsr, Bvt);
+    P.slu = -At * G.pu * isdd;
+    P.slv = -At * G.pv * isdd;
+    P.usr = (float)usr;
+    P.vsr = (float)vsr;
+    P.dus = (float)(G.pu * isdd);
+    P.dvs = (float)(G.pv * isdd);
+}
+
+// Clip length of a staged ray with the voxel at offsets (du, dv); a zero
+// direction component (careful views only) is a membership test of the
+// half-open slab instead.
+__device__ __forceinline__ float clip3(float du, float dv, const float4& q0, const float4& q1,
+                                       const float4& q2, const ViewP3& P, const float hh[3],
+                                       bool careful) {
+    const float s0 = fmaf(du, q0.x, dv * q1.x);
+    const float s1 = fmaf(du, q0.y, dv * q1.y);
+    const float s2 = fmaf(du, q0.z, dv * q1.z);
+    float lo = fmaxf(fmaxf(s0 - q0.w, s1 - q1.w), s2 - q2.x);
+    float hi = fminf(fminf(s0 + q0.w, s1 + q1.w), s2 + q2.x);
+    if (careful) {
+        const int zero = __float_as_int(q2.w);
+        if (zero) {
+            const float ss[3] = {s0, s1, s2}, ww[3] = {q0.w, q1.w, q2.x};
+            lo = -INFINITY;
+            hi = INFINITY;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if ((zero >> k) & 1) {
+                    const float g = du * P.eu[k] + dv * P.ev[k];
+                    if (!(g > -hh[k] && g <= hh[k])) hi = -INFINITY;
+                } else {
+                    lo = fmaxf(lo, ss[k] - ww[k]);
+                    hi = fminf(hi, ss[k] + ww[k]);
+                }
+            }
+        }
+    }
+    return fmaxf(hi - lo, 0.f) * q2.y;
 }
 
 template <class BA>
@@ -739,14 +821,11 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
                           G.oz + ((double)zs + 0.5 * nvz) * G.vz};
     const double trad = 0.5 * sqrt((nvx * G.vx) * (nvx * G.vx) + (nvy * G.vy) * (nvy * G.vy) +
                                    (nvz * G.vz) * (nvz * G.vz)) * (1.0 + 1e-9);
-    const double ox = (double)lx - 0.5 * (nvx - 1), oy = (double)ly - 0.5 * (nvy - 1);
-    const double oz = (double)lz - 0.5 * (nvz - 1);
+    const float ox = (float)lx - 0.5f * (float)(nvx - 1), oy = (float)ly - 0.5f * (float)(nvy - 1);
+    const float oz = (float)lz - 0.5f * (float)(nvz - 1);
     const float hh[3] = {(float)(0.5 * G.vx), (float)(0.5 * G.vy), (float)(0.5 * G.vz)};
-    const float R = G.radius;
     const double pu = G.pu, pv = G.pv;
     const double c0u = 0.5 * (double)(G.nu - 1), c0v = 0.5 * (double)(G.nv - 1);
-    const float ipu = (float)(1.0 / pu), ipv = (float)(1.0 / pv);
-    const float c0uf = (float)c0u, c0vf = (float)c0v;
 
     int e0 = 0, e1 = a.n_ent;
     if (a.gptr) {
@@ -778,33 +857,35 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
         const int nb = min(64, nt - base);
         for (int j = 0; j < nb; ++j) {
             const ViewP3& P = vp[j];
-            const int view = P.view;
-            const int fu0 = P.fu0, fu1 = P.fu1, fv0 = P.fv0, fv1 = P.fv1;
+            const int view = __builtin_amdgcn_readfirstlane(P.view);
+            const int fu0 = __builtin_amdgcn_readfirstlane(P.fu0), fu1 = __builtin_amdgcn_readfirstlane(P.fu1);
+            const int fv0 = __builtin_amdgcn_readfirstlane(P.fv0), fv1 = __builtin_amdgcn_readfirstlane(P.fv1);
+            const bool careful = (__builtin_amdgcn_readfirstlane(P.flags) & 1) != 0;
             const int fw = fu1 - fu0, fh = fv1 - fv0;
             if (fw <= 0 || fh <= 0) continue;
-            // this voxel's frame coordinates and shadow window
-            const double A = fma(oz, P.az, fma(oy, P.ay, fma(ox, P.ax, P.At)));
-            const double Bu = fma(oz, P.buz, fma(oy, P.buy, fma(ox, P.bux, P.But)));
-            const double Bv = fma(oz, P.bvz, fma(oy, P.bvy, fma(ox, P.bvx, P.Bvt)));
-            const double Ai = A * P.isdd;
-            const float Af = (float)A;
-            const float tu = (float)Bu / Af, tv = (float)Bv / Af;
-            const float den = P.sdd * R / (Af - R);
-            const float betu = P.sdd * tu * ipu + c0uf, betv = P.sdd * tv * ipv + c0vf;
-            const float wu = den * (1.f + fabsf(tu)) * ipu + 1e-3f;
-            const float wv = den * (1.f + fabsf(tv)) * ipv + 1e-3f;
-            const int ulo = valid ? (int)ceilf(betu - wu) : 1, uhi = valid ? (int)floorf(betu + wu) : 0;
-            const int vlo = valid ? (int)ceilf(betv - wv) : 1, vhi = valid ? (int)floorf(betv + wv) : 0;
-            // the window in passes of at most kRayC rays
+            // this voxel's offsets and candidate window
+            const float dA = fmaf(oz, P.az, fmaf(oy, P.ay, ox * P.ax));
+            const float dBu = fmaf(oz, P.buz, fmaf(oy, P.buy, ox * P.bux));
+            const float dBv = fmaf(oz, P.bvz, fmaf(oy, P.bvy, ox * P.bvx));
+            const float betu = fmaf(oz, P.guz, fmaf(oy, P.guy, fmaf(ox, P.gux, P.betu)));
+            const float betv = fmaf(oz, P.gvz, fmaf(oy, P.gvy, fmaf(ox, P.gvx, P.betv)));
+            const int ulo = valid ? (int)ceilf(betu - P.Wu) : 1, uhi = valid ? (int)floorf(betu + P.Wu) : 0;
+            const int vlo = valid ? (int)ceilf(betv - P.Wv) : 1, vhi = valid ? (int)floorf(betv + P.Wv) : 0;
+            const float stu = fmaf(-dA, P.dus, (float)P.slu), stv = fmaf(-dA, P.dvs, (float)P.slv);
+            // the detector window in passes of at most kRayC rays
             const int cw = min(fw, kRayC), chh = max(1, kRayC / cw);
             for (int cv0 = fv0; cv0 < fv1; cv0 += chh) {
                 const int cv1 = min(fv1, cv0 + chh);
                 for (int cu0 = fu0; cu0 < fu1; cu0 += cw) {
                     const int cu1 = min(fu1, cu0 + cw);
                     const int pw = cu1 - cu0, np = pw * (cv1 - cv0);
+                    // row of lane t in the pass: (t + 1/2) / pw lies at least 1/(2 pw)
+                    // from an integer, far beyond float32 rounding for t < 256
+                    const float ipw = 1.f / (float)pw;
                     __syncthreads();                    // previous pass fully read
                     if (t < np) {
-                        const int iu = cu0 + t % pw, iv = cv0 + t / pw;
+                        const int row = (int)(((float)t + 0.5f) * ipw);
+                        const int iu = cu0 + (t - row * pw), iv = cv0 + row;
                         const double u = ((double)iu - c0u) * pu, v = ((double)iv - c0v) * pv;
                         const double* V = view_of(G, view);
                         float d[3];
@@ -812,64 +893,45 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
 #pragma unroll
                         for (int k = 0; k < 3; ++k) {
                             const double Dk = fma(v, V[9 + k], fma(u, V[6 + k], V[15] * V[12 + k]));
-                            d[k] = (float)(Dk * P.isdd);
+                            d[k] = (float)(Dk * V[16]);
                             zero |= (d[k] == 0.f) ? (1 << k) : 0;
                         }
                         float al[3], be[3], w[3];
 #pragma unroll
                         for (int k = 0; k < 3; ++k) {
-                            const float inv = (zero >> k) & 1 ? 0.f : 1.f / d[k];
+                            const float inv = (zero >> k) & 1 ? 0.f : __builtin_amdgcn_rcpf(d[k]);
                             al[k] = P.eu[k] * inv;
                             be[k] = P.ev[k] * inv;
                             w[k] = (zero >> k) & 1 ? INFINITY : hh[k] * fabsf(inv);
                         }
-                        const float nrm = sqrtf(fmaf(d[0], d[0], fmaf(d[1], d[1], d[2] * d[2])));
+                        const float nrm = __builtin_amdgcn_sqrtf(fmaf(d[0], d[0], fmaf(d[1], d[1], d[2] * d[2])));
                         const float rv = a.r[((size_t)view * G.nv + iv) * G.nu + iu];
                         rc0[t] = make_float4(al[0], al[1], al[2], w[0]);
                         rc1[t] = make_float4(be[0], be[1], be[2], w[1]);
                         rc2[t] = make_float4(w[2], nrm, rv, __int_as_float(zero));
                     }
                     __syncthreads();
-                    const int va = max(vlo, cv0), vb = min(vhi, cv1 - 1);
                     const int ua = max(ulo, cu0), ub = min(uhi, cu1 - 1);
-                    if (ua > ub) continue;
-                    // du, dv at (ua, iv) in float64, stepped along u
-                    const double du0 = fma(-Ai, ((double)ua - c0u) * pu, Bu);
-                    const double ddu = -Ai * pu;
-                    for (int iv = va; iv <= vb; ++iv) {
-                        const float dv = (float)fma(-Ai, ((double)iv - c0v) * pv, Bv);
-                        double dud = du0;
-                        const int row = (iv - cv0) * pw - cu0;
-                        for (int iu = ua; iu <= ub; ++iu) {
-                            const float du = (float)dud;
-                            dud += ddu;
-                            const float4 q0 = rc0[row + iu], q1 = rc1[row + iu], q2 = rc2[row + iu];
-                            const float s0 = fmaf(du, q0.x, dv * q1.x);
-                            const float s1 = fmaf(du, q0.y, dv * q1.y);
-                            const float s2 = fmaf(du, q0.z, dv * q1.z);
-                            float lo = fmaxf(fmaxf(s0 - q0.w, s1 - q1.w), s2 - q2.x);
-                            float hi = fminf(fminf(s0 + q0.w, s1 + q1.w), s2 + q2.x);
-                            const int zero = __float_as_int(q2.w);
-                            if (zero) {
-                                // an axis the ray never crosses: it lies in one
-                                // half-open voxel slab or misses the voxel
-                                const float g[3] = {du * P.eu[0] + dv * P.ev[0], du * P.eu[1] + dv * P.ev[1],
-                                                    du * P.eu[2] + dv * P.ev[2]};
-                                const float ss[3] = {s0, s1, s2}, ww[3] = {q0.w, q1.w, q2.x};
-                                lo = -INFINITY;
-                                hi = INFINITY;
-#pragma unroll
-                                for (int k = 0; k < 3; ++k) {
-                                    if ((zero >> k) & 1) {
-                                        if (!(g[k] > -hh[k] && g[k] <= hh[k])) hi = -INFINITY;
-                                    } else {
-                                        lo = fmaxf(lo, ss[k] - ww[k]);
-                                        hi = fminf(hi, ss[k] + ww[k]);
-                                    }
-                                }
-                            }
-                            acc = fmaf(fmaxf(hi - lo, 0.f) * q2.y, q2.z, acc);
-                        }
+                    const int va = max(vlo, cv0), vb = min(vhi, cv1 - 1);
+                    const int nu_w = ub - ua + 1, n_c = (ua <= ub && va <= vb) ? nu_w * (vb - va + 1) : 0;
+                    if (n_c == 0) continue;
+                    // du, dv at (ua, va): float64 base of the tile plus the
+                    // voxel's small float32 offsets
+                    const float du0 = (float)fma((double)(ua - P.uref), P.slu, P.D0u) +
+                                      fmaf(-dA, fmaf((float)(ua - P.uref), P.dus, P.usr), dBu);
+                    const float dv0 = (float)fma((double)(va - P.vref), P.slv, P.D0v) +
+                                      fmaf(-dA, fmaf((float)(va - P.vref), P.dvs, P.vsr), dBv);
+                    int ku = 0, kv = 0;
+                    int li = (va - cv0) * pw + (ua - cu0);
+                    for (int c = 0; c < n_c; ++c) {
+                        const float du = fmaf((float)ku, stu, du0);
+                        const float dv = fmaf((float)kv, stv, dv0);
+                        const float4 q0 = rc0[li + ku], q1 = rc1[li + ku], q2 = rc2[li + ku];
+                        acc = fmaf(clip3(du, dv, q0, q1, q2, P, hh, careful), q2.z, acc);
+                        const bool wrap = ku + 1 == nu_w;
+                        ku = wrap ? 0 : ku + 1;
+                        kv = wrap ? kv + 1 : kv;
+                        li = wrap ? li + pw : li;
                     }
                 }
             }
