@@ -45,6 +45,15 @@ VALU_PEAK_TFLOPS = 78.6          # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, n
 FLOPS_PER_UPDATE = 5.0           # select next crossing, segment length, advance, multiply-add
 GATHER_BYTES_PER_UPDATE = 4.0    # what an explicit-A SpMV would stream per nonzero
 BATCH_SIZES = (128, 256, 384, 512, 768, 1024)
+# HBM traffic of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs (KiB per dispatch), scaled by what the same counters read
+# for a plain 256 MiB device copy (workload copy256): fetch x 2.0, write x 1.0.
+# An entry holds only for the kernel version the counters were taken on.
+PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
+TRAFFIC_KIB = {
+    ("fan2d_512", "back"): {"fetch": 11596.0, "write": 2112.0,
+                            "profile": "profiles/fan2d_512_back_projection_hbm_traffic.md"},
+}
 SERVE_FAN = (256, 384, 512, 768, 1024)
 SERVE_CONE = (64, 96, 128, 160, 192)
 
@@ -123,7 +132,7 @@ def cpu_baseline(g, y, ex, budget_s=15.0, note=""):
             "seconds": t_run}
 
 
-def roofline_of(kt, prof_updates):
+def roofline_of(kt, prof_updates, workload=None):
     """Roofline object of the dominant kernel from per-class (ms, launches)."""
     dom = max(kt, key=lambda k: kt[k][0])
     dom_ms, dom_n = kt[dom]
@@ -132,11 +141,17 @@ def roofline_of(kt, prof_updates):
         units = prof_updates / 2                # ray-voxel pairs handled by one projector
         per_launch = units / dom_n
         achieved = per_launch * FLOPS_PER_UPDATE / (avg_ms * 1e-3) / 1e12
+        tr = TRAFFIC_KIB.get((workload, dom))
+        traffic = (None if tr is None else
+                   (tr["fetch"] * PMC_FETCH_SCALE + tr["write"] * PMC_WRITE_SCALE) * 1024.0)
         roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": VALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 5),
-                "traffic": None, "kernel": dom, "avg_launch_ms": round(avg_ms, 5),
+                "traffic": traffic, "kernel": dom, "avg_launch_ms": round(avg_ms, 5),
                 "launches": dom_n, "units_per_launch": per_launch,
                 "flops_per_unit": FLOPS_PER_UPDATE}
+        if tr is not None:
+            roof["traffic_note"] = (f"HBM bytes per launch (FETCH_SIZE x {PMC_FETCH_SCALE} + "
+                                    f"WRITE_SIZE x {PMC_WRITE_SCALE}), {tr['profile']}")
         gbytes = per_launch * GATHER_BYTES_PER_UPDATE / (avg_ms * 1e-3) / 1e9
         gather = {"achieved": round(gbytes, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": round(gbytes / HBM_PEAK_GBS, 5)}
@@ -227,7 +242,7 @@ def run_single(args):
 
     timed_updates = sum(upd[args.warmup:E])
     out = base_record(args, timed_updates / (ms * 1e-3), ms, args.steps)
-    roof, gather = roofline_of(kt, prof_updates)
+    roof, gather = roofline_of(kt, prof_updates, args.workload)
     out["config"] = {"workload": desc, "epoch_updates": upd[args.warmup], "b": cfg["b"],
                      "rel_residual_after": rel, "setup_s": round(t_setup, 3)}
     out["roofline"] = roof
@@ -472,13 +487,42 @@ def run_serve(args):
     return out
 
 
+def run_copy(args):
+    """A plain 256 MiB device-to-device copy (torch), three times: the
+    reference for scaling the HBM byte counters and a measured bandwidth."""
+    import torch
+    n = 64 * 1024 * 1024
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(3):
+        b.copy_(a)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / 3
+    gbs = 2 * 4 * n / (ms * 1e-3) / 1e9
+    return {"metric": "device copy bandwidth (read + write)", "value": gbs, "unit": "GB/s",
+            "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "256 MiB float32 copy"},
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "traffic": 2 * 4 * n},
+            "cpu_baseline": None}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fan2d_512",
-                    choices=["fan2d_512", "par2d_64", "cone3d_256", "batch64", "serve40"])
+                    choices=["fan2d_512", "par2d_64", "cone3d_256", "batch64", "serve40",
+                             "copy256"])
     ap.add_argument("--jobs", type=int, default=None,
                     help="batch64: slices (64); serve40: jobs in the stream (1000)")
     ap.add_argument("--window", type=float, default=30.0, help="serve40: seconds served")
@@ -498,6 +542,8 @@ def main():
     if args.workload == "batch64":
         args.jobs = args.jobs or 64
         out = run_batch(args)
+    elif args.workload == "copy256":
+        out = run_copy(args)
     elif args.workload == "serve40":
         args.jobs = args.jobs or 1000
         out = run_serve(args)
