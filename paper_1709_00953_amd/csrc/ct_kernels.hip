@@ -659,8 +659,9 @@ __global__ __launch_bounds__(256) void k_back2(DGeom G, BA a) {
 // Each voxel thus gets a rigorous candidate window of bins from a few float32
 // FMAs; du at the window's first bin needs one float64 FMA (it cancels lever
 // arms of the source distance), the steps along the window are float32.  The
-// per-ray constants of the tile's detector window and r are staged in LDS,
-// and each voxel runs one flattened loop over its window.
+// per-ray constants of the tile's detector window (the bounding rectangle of
+// its box's projected corners) and r are staged in LDS, and each voxel runs
+// one flattened loop over its window.
 struct ViewP3 {
     double D0u, D0v, slu, slv;    // du = D0u + (iu - uref) slu + dBu - dA us(iu) (same for v)
     float ax, ay, az;             // A, Bu, Bv per voxel step in x, y, z
@@ -676,7 +677,8 @@ struct ViewP3 {
 constexpr int kRayC = 256;        // staged rays per pass
 
 __device__ __forceinline__ void view_params3(const DGeom& G, const Tile& tl, const double tc[3],
-                                             const double tr, ViewP3& P) {
+                                             const double tr, const double tlo[3], const double thi[3],
+                                             ViewP3& P) {
     const double* V = view_of(G, tl.view);
     const double sdd = V[15], isdd = V[16];
     const double q[3] = {tc[0] - V[0], tc[1] - V[1], tc[2] - V[2]};
@@ -709,13 +711,25 @@ __device__ __forceinline__ void view_params3(const DGeom& G, const Tile& tl, con
         const double tu = But / At, tv = Bvt / At;
         bu = sdd * tu / G.pu + c0u;
         bv = sdd * tv / G.pv + c0v;
-        // detector window of the tile: shadow of its bounding sphere
-        const double den = sdd * tr / (At - tr);
-        const double wu = den * sqrt(1.0 + tu * tu) / G.pu + 1e-3, wv = den * sqrt(1.0 + tv * tv) / G.pv + 1e-3;
-        u0 = max(u0, (int)fmax(ceil(bu - wu), -1.0));
-        u1 = min(u1, (int)fmin(floor(bu + wu), 2e9) + 1);
-        v0 = max(v0, (int)fmax(ceil(bv - wv), -1.0));
-        v1 = min(v1, (int)fmin(floor(bv + wv), 2e9) + 1);
+        // detector window of the tile: its box lies in front of the source, so
+        // the box's image is the convex hull of its eight projected corners
+        double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+        const double hx = 0.5 * (thi[0] - tlo[0]), hy = 0.5 * (thi[1] - tlo[1]), hz = 0.5 * (thi[2] - tlo[2]);
+#pragma unroll 1
+        for (int c = 0; c < 8; ++c) {
+            const double sx = (c & 1) ? hx : -hx, sy = (c & 2) ? hy : -hy, sz = (c & 4) ? hz : -hz;
+            const double ia = 1.0 / fma(sz, V[14], fma(sy, V[13], fma(sx, V[12], At)));
+            const double cu = sdd * fma(sz, V[8], fma(sy, V[7], fma(sx, V[6], But))) * ia;
+            const double cv = sdd * fma(sz, V[11], fma(sy, V[10], fma(sx, V[9], Bvt))) * ia;
+            umin = fmin(umin, cu);
+            umax = fmax(umax, cu);
+            vmin = fmin(vmin, cv);
+            vmax = fmax(vmax, cv);
+        }
+        u0 = max(u0, (int)fmax(ceil(umin / G.pu + c0u - 1e-3), -1.0));
+        u1 = min(u1, (int)fmin(floor(umax / G.pu + c0u + 1e-3), 2e9) + 1);
+        v0 = max(v0, (int)fmax(ceil(vmin / G.pv + c0v - 1e-3), -1.0));
+        v1 = min(v1, (int)fmin(floor(vmax / G.pv + c0v + 1e-3), 2e9) + 1);
         // gradient of the bin coordinates at the tile centre (per mm), the
         // voxel's own half-extent there, and the linearisation remainders
         double hu = 0.0, hv = 0.0, hs = 0.0;
@@ -821,6 +835,9 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
                           G.oz + ((double)zs + 0.5 * nvz) * G.vz};
     const double trad = 0.5 * sqrt((nvx * G.vx) * (nvx * G.vx) + (nvy * G.vy) * (nvy * G.vy) +
                                    (nvz * G.vz) * (nvz * G.vz)) * (1.0 + 1e-9);
+    const double tlo[3] = {G.ox + (double)xs * G.vx, G.oy + (double)ys * G.vy, G.oz + (double)zs * G.vz};
+    const double thi[3] = {G.ox + (double)(xs + nvx) * G.vx, G.oy + (double)(ys + nvy) * G.vy,
+                           G.oz + (double)(zs + nvz) * G.vz};
     const float ox = (float)lx - 0.5f * (float)(nvx - 1), oy = (float)ly - 0.5f * (float)(nvy - 1);
     const float oz = (float)lz - 0.5f * (float)(nvz - 1);
     const float hh[3] = {(float)(0.5 * G.vx), (float)(0.5 * G.vy), (float)(0.5 * G.vz)};
@@ -846,7 +863,7 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
                 const int rb = get_entry(a, e).rb;
                 const int cnt = G.rb_tile_ptr[rb + 1] - G.rb_tile_ptr[rb];
                 if (off < cnt) {
-                    view_params3(G, G.tiles[G.rb_tile_ptr[rb] + off], tc, trad, vp[t]);
+                    view_params3(G, G.tiles[G.rb_tile_ptr[rb] + off], tc, trad, tlo, thi, vp[t]);
                     break;
                 }
                 off -= cnt;
