@@ -651,14 +651,13 @@ __global__ __launch_bounds__(256) void k_back2(DGeom G, BA a) {
 //   |D~| max(0, min_k(s_k + w_k) - max_k(s_k - w_k)).
 // A work-group owns an 8 x 8 x 4 voxel tile (one voxel per lane) and walks the
 // views of the group.  Per (tile, view), one lane forms in float64 the tile
-// centre's frame coordinates, the bases of du and dv along the detector, and
-// a linearised shadow: the bin coordinate sdd B / A of a voxel centre is
-// affine in the voxel's offset from the tile centre up to a remainder bounded
-// by the Hessian of B/A (norm <= 2 (1 + |B/A|) / A^2) over the tile's
-// bounding sphere, and so is the half-extent of the voxel's own projection.
-// Each voxel thus gets a rigorous candidate window of bins from a few float32
-// FMAs; du at the window's first bin needs one float64 FMA (it cancels lever
-// arms of the source distance), the steps along the window are float32.  The
+// centre's frame coordinates and the bases of du and dv along the detector.
+// Each voxel's candidate window is its shadow centre sdd B / A plus the
+// half-extent of its box from the gradient at its centre, widened by the
+// remainder (Hessian of B/A, norm <= 2 (1 + |B/A|) / A^2, over the tile's
+// bounding sphere, times R^2 / 2); du at the window's first bin needs one
+// float64 FMA (it cancels lever arms of the source distance), the steps along
+// the window are float32.  The
 // per-ray constants of the tile's detector window (the bounding rectangle of
 // its box's projected corners) and r are staged in LDS, and each voxel runs
 // one flattened loop over its window.
@@ -666,10 +665,11 @@ struct ViewP3 {
     double D0u, D0v, slu, slv;    // du = D0u + (iu - uref) slu + dBu - dA us(iu) (same for v)
     float ax, ay, az;             // A, Bu, Bv per voxel step in x, y, z
     float bux, buy, buz, bvx, bvy, bvz;
-    float gux, guy, guz, gvx, gvy, gvz;   // bin coordinates per voxel step
-    float betu, betv, Wu, Wv;     // tile-centre bins, window half-widths (bins)
+    float At, But, Bvt;           // tile centre (float32: shadow windows only)
+    float su, sv;                 // sdd / pu, sdd / pv
+    float e2u, e2v;               // curvature remainder over a voxel + float32 margins (bins)
     float usr, vsr, dus, dvs;     // u/sdd at uref and per bin (same for v)
-    float eu[3], ev[3];
+    float eu[3], ev[3], n[3];
     int32_t view, fu0, fu1, fv0, fv1;     // detector window [fu0, fu1) x [fv0, fv1)
     int32_t uref, vref, flags;
 };
@@ -699,14 +699,19 @@ __device__ __forceinline__ void view_params3(const DGeom& G, const Tile& tl, con
     for (int k = 0; k < 3; ++k) {
         P.eu[k] = (float)V[6 + k];
         P.ev[k] = (float)V[9 + k];
+        P.n[k] = (float)V[12 + k];
     }
     P.view = tl.view;
     P.flags = G.view_flags[tl.view];
+    P.At = (float)At;
+    P.But = (float)But;
+    P.Bvt = (float)Bvt;
+    P.su = (float)(sdd / G.pu);
+    P.sv = (float)(sdd / G.pv);
     const double c0u = 0.5 * (double)(G.nu - 1), c0v = 0.5 * (double)(G.nv - 1);
     const double R = (double)G.radius;
     int u0 = tl.u0, u1 = tl.u1, v0 = tl.v0, v1 = tl.v1;
-    double bu = c0u, bv = c0v, Wu = 1e9, Wv = 1e9;
-    double gu[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
+    double bu = c0u, bv = c0v, e2u = 1e9, e2v = 1e9;
     if (At > 1.0001 * (tr + R)) {
         const double tu = But / At, tv = Bvt / At;
         bu = sdd * tu / G.pu + c0u;
@@ -730,40 +735,22 @@ __device__ __forceinline__ void view_params3(const DGeom& G, const Tile& tl, con
         u1 = min(u1, (int)fmin(floor(umax / G.pu + c0u + 1e-3), 2e9) + 1);
         v0 = max(v0, (int)fmax(ceil(vmin / G.pv + c0v - 1e-3), -1.0));
         v1 = min(v1, (int)fmin(floor(vmax / G.pv + c0v + 1e-3), 2e9) + 1);
-        // gradient of the bin coordinates at the tile centre (per mm), the
-        // voxel's own half-extent there, and the linearisation remainders
-        double hu = 0.0, hv = 0.0, hs = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double du_k = sdd * (V[6 + k] - tu * V[12 + k]) / At / G.pu;
-            const double dv_k = sdd * (V[9 + k] - tv * V[12 + k]) / At / G.pv;
-            gu[k] = du_k * h[k];
-            gv[k] = dv_k * h[k];
-            hu += 0.5 * h[k] * fabs(du_k);
-            hv += 0.5 * h[k] * fabs(dv_k);
-            hs += 0.5 * h[k];
-        }
+        // second-order remainder of a voxel's shadow about its own centre:
+        // Hessian norm of sdd B / A over the tile's sphere times R^2 / 2
         const double amin = At - tr - R;
         const double Hu = 2.0 * sdd * (1.0 + (fabs(But) + tr + R) / amin) / (amin * amin) / G.pu;
         const double Hv = 2.0 * sdd * (1.0 + (fabs(Bvt) + tr + R) / amin) / (amin * amin) / G.pv;
-        Wu = hu + Hu * (tr * hs + 0.5 * tr * tr + 0.5 * R * R);
-        Wv = hv + Hv * (tr * hs + 0.5 * tr * tr + 0.5 * R * R);
+        e2u = 0.5 * Hu * R * R;
+        e2v = 0.5 * Hv * R * R;
     }
     P.fu0 = u0;
     P.fu1 = max(u0, u1);
     P.fv0 = v0;
     P.fv1 = max(v0, v1);
-    P.betu = (float)bu;
-    P.betv = (float)bv;
-    P.gux = (float)gu[0];
-    P.guy = (float)gu[1];
-    P.guz = (float)gu[2];
-    P.gvx = (float)gv[0];
-    P.gvy = (float)gv[1];
-    P.gvz = (float)gv[2];
-    // float32 rounding of the window centre (|beta| <= a few thousand bins)
-    P.Wu = (float)fmin(Wu, 1e9) + 2e-3f + 1e-6f * fabsf((float)bu);
-    P.Wv = (float)fmin(Wv, 1e9) + 2e-3f + 1e-6f * fabsf((float)bv);
+    // plus the float32 rounding of the voxel's shadow centre and half-extent
+    // (|beta| <= a few thousand bins)
+    P.e2u = (float)fmin(e2u, 1e9) + 2e-3f + 2e-6f * fabsf((float)bu);
+    P.e2v = (float)fmin(e2v, 1e9) + 2e-3f + 2e-6f * fabsf((float)bv);
     // bases of du, dv: reference bins near the tile centre's shadow
     const int uref = (int)fmin(fmax(rint(bu), -1e6), 1e6), vref = (int)fmin(fmax(rint(bv), -1e6), 1e6);
     const double usr = ((double)uref - c0u) * G.pu * isdd, vsr = ((double)vref - c0v) * G.pv * isdd;
@@ -880,14 +867,24 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
             const bool careful = (__builtin_amdgcn_readfirstlane(P.flags) & 1) != 0;
             const int fw = fu1 - fu0, fh = fv1 - fv0;
             if (fw <= 0 || fh <= 0) continue;
-            // this voxel's offsets and candidate window
+            // this voxel's offsets and candidate window: its shadow centre
+            // sdd B / A and the half-extent of its box, from the gradient at
+            // its own centre, plus the remainder e2
             const float dA = fmaf(oz, P.az, fmaf(oy, P.ay, ox * P.ax));
             const float dBu = fmaf(oz, P.buz, fmaf(oy, P.buy, ox * P.bux));
             const float dBv = fmaf(oz, P.bvz, fmaf(oy, P.bvy, ox * P.bvx));
-            const float betu = fmaf(oz, P.guz, fmaf(oy, P.guy, fmaf(ox, P.gux, P.betu)));
-            const float betv = fmaf(oz, P.gvz, fmaf(oy, P.gvy, fmaf(ox, P.gvx, P.betv)));
-            const int ulo = valid ? (int)ceilf(betu - P.Wu) : 1, uhi = valid ? (int)floorf(betu + P.Wu) : 0;
-            const int vlo = valid ? (int)ceilf(betv - P.Wv) : 1, vhi = valid ? (int)floorf(betv + P.Wv) : 0;
+            const float iA = __builtin_amdgcn_rcpf(P.At + dA);
+            const float tu = (P.But + dBu) * iA, tv = (P.Bvt + dBv) * iA;
+            float hu = 0.f, hv = 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                hu = fmaf(hh[k], fabsf(fmaf(-tu, P.n[k], P.eu[k])), hu);
+                hv = fmaf(hh[k], fabsf(fmaf(-tv, P.n[k], P.ev[k])), hv);
+            }
+            const float betu = fmaf(P.su, tu, (float)c0u), betv = fmaf(P.sv, tv, (float)c0v);
+            const float Wu = fmaf(P.su * iA, hu, P.e2u), Wv = fmaf(P.sv * iA, hv, P.e2v);
+            const int ulo = valid ? (int)ceilf(betu - Wu) : 1, uhi = valid ? (int)floorf(betu + Wu) : 0;
+            const int vlo = valid ? (int)ceilf(betv - Wv) : 1, vhi = valid ? (int)floorf(betv + Wv) : 0;
             const float stu = fmaf(-dA, P.dus, (float)P.slu), stv = fmaf(-dA, P.dvs, (float)P.slv);
             // the detector window in passes of at most kRayC rays
             const int cw = min(fw, kRayC), chh = max(1, kRayC / cw);
@@ -975,8 +972,9 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
     }
 }
 
+// (at most 128 VGPRs: four waves per SIMD)
 template <class BA>
-__global__ __launch_bounds__(256) void k_back3(DGeom G, BA a) {
+__global__ __launch_bounds__(256, 4) void k_back3(DGeom G, BA a) {
     back3_body(G, a, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
@@ -1123,7 +1121,7 @@ __device__ __forceinline__ int box_vox(const Box& b) {
 }
 
 template <int KIND>
-__global__ __launch_bounds__(256) void kb_back(BatchArgs B) {
+__global__ __launch_bounds__(256, 4) void kb_back(BatchArgs B) {
     const int k = batch_job(B, blockIdx.x);
     const int L = blockIdx.x - B.prefix[k];
     const BJob J = cld(B.jobs, k);
