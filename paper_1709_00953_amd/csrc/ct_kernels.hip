@@ -449,8 +449,9 @@ __device__ __forceinline__ float chord2_axis(float delta, const Ray2B& R, float 
 // Per (tile, view) parameters.  For a voxel at index offset (lx, ly) from the
 // tile centre: view-frame offset A = Ac + lx ax + ly ay, B = Bc + lx bx + ly by
 // (exact, both are affine in position); bin coordinate of its shadow centre
-// ~ bc + lx bxs + ly bys, with W (bins) covering the voxel's own half-width,
-// the curvature of the projection over the tile and float32 rounding.
+// ~ bc + lx bxs + ly bys, with W (bins) covering the half-extent of the
+// voxel's box (from the gradient), the curvature of the projection over the
+// tile and float32 rounding.
 struct ViewP {
     double Ac, Bc, ax, ay, bx, by;
     float bc, bxs, bys, W;
@@ -479,7 +480,7 @@ __device__ __forceinline__ void view_params(const DGeom& G, const Tile& tl, doub
         bc = P.Bc * s + c0;
         bxs = P.bx * s;
         bys = P.by * s;
-        W = R / (fabs(V[15]) * G.pu);
+        W = 0.5 * (fabs(bxs) + fabs(bys));          // affine: the box's exact half-extent
     } else {
         const double qx = cx - V[0], qy = cy - V[1];
         P.Ac = fma(qx, V[12], qy * V[13]);
@@ -499,8 +500,13 @@ __device__ __forceinline__ void view_params(const DGeom& G, const Tile& tl, doub
             bc = (double)atan2f((float)B, (float)A) / G.pu + c0;
             bxs = (A * P.bx - B * P.ax) * ir2 / G.pu;
             bys = (A * P.by - B * P.ay) * ir2 / G.pu;
+            // half-extent of a voxel's box from the gradient at the tile centre,
+            // plus its variation over the tile, the linearisation of the
+            // centre and the voxel's own curvature (Hessian norm <= 1/rmin^2)
+            const double hs = 0.5 * (G.vx + G.vy);
             W = (rmin > 1.0001 * R)
-                    ? (R / sqrt(rmin * rmin - R * R) + 0.5 * dt * dt / (rmin * rmin) + 1e-6) / G.pu
+                    ? 0.5 * (fabs(bxs) + fabs(bys)) +
+                          ((dt * hs + 0.5 * dt * dt + 0.5 * R * R) / ((rmin - R) * (rmin - R)) + 1e-6) / G.pu
                     : 1e9;
         } else {
             // u = sdd * B / A; Hessian norm of B/A <= 2 (1 + |B/A|) / A^2
@@ -510,8 +516,12 @@ __device__ __forceinline__ void view_params(const DGeom& G, const Tile& tl, doub
             bc = sdd * B * ia / G.pu + c0;
             bxs = sdd * (A * P.bx - B * P.ax) * ia * ia / G.pu;
             bys = sdd * (A * P.by - B * P.ay) * ia * ia / G.pu;
+            // Hessian bound over the tile's sphere widened by a voxel radius
+            const double hs = 0.5 * (G.vx + G.vy);
+            const double tbr = (fabs(B) + dt + R) / (amin - R);
+            const double H = 2.0 * sdd * (1.0 + tbr) / ((amin - R) * (amin - R)) / G.pu;
             W = (amin > 1.0001 * R)
-                    ? sdd * ((1.0 + tb) * R / (amin - R) + (1.0 + tb) * dt * dt / (amin * amin)) / G.pu
+                    ? 0.5 * (fabs(bxs) + fabs(bys)) + H * (dt * hs + 0.5 * dt * dt + 0.5 * R * R)
                     : 1e9;
         }
     }
