@@ -114,6 +114,14 @@ int ct_geom_get_info(const ct_geom* geom, ct_geom_info* out);
  * drives the importance sampling of Sec. II-C (reading C6).  host_nnz is a
  * host array [m][n] (row-block major).  Synchronous on `stream`. */
 int ct_geom_block_nnz(ct_geom* geom, double tau, int64_t* host_nnz, void* stream);
+/* The paper's own density estimate (Sec. II-C, Alg. 5): host_area[I*n + J] =
+ * P_S, the area (detector units: mm, radians on a curved detector, mm^2 in
+ * 3D) that the projection of column block J's box covers on the tiles of row
+ * block I, summed over its views; computed exactly (hull of the projected
+ * box corners, intersected with each tile's rectangle of bin edges) on the
+ * host in float64.  Normalised per column (P = P_S / sum_I P_S) it feeds
+ * ct_schedule_create_w.  host_area: caller memory of m*n doubles. */
+int ct_geom_block_area(const ct_geom* geom, double* host_area);
 
 /* ---- block projectors (Alg. 3) ---------------------------------------------
  * ct_block_fwd:  y_{I} (= or +=) A_I^J x_J   for I = union of row_blocks.
@@ -173,6 +181,10 @@ typedef struct ct_sched_view {
 /* nnz: host [m][n] block densities (e.g. from ct_geom_block_nnz). */
 int ct_schedule_create(const ct_geom* geom, const ct_sched_params* params, const int64_t* nnz,
                        ct_schedule** out);
+/* As ct_schedule_create with any nonnegative block density weights w[m*n]
+ * (e.g. ct_geom_block_area): P(I,J) = w / sum_I w, summed in ascending I. */
+int ct_schedule_create_w(const ct_geom* geom, const ct_sched_params* params, const double* w,
+                         ct_schedule** out);
 /* Import an explicit schedule (host arrays, copied).  Each column block may
  * appear at most once per epoch and the row blocks of one column entry must
  * be distinct. */

@@ -52,6 +52,20 @@ def count_of(frac: float, total: int) -> int:
     return max(1, min(total, k))
 
 
+def density_w(w: np.ndarray) -> np.ndarray:
+    """P(I,J) = w[I,J] / sum_I w[I,J] for float weights (e.g. projection
+    areas), the column sum taken in ascending I (zero column -> zero P)."""
+    w = np.asarray(w, dtype=np.float64)
+    P = np.zeros(w.shape, dtype=np.float64)
+    for J in range(w.shape[1]):
+        col = 0.0
+        for I in range(w.shape[0]):
+            col += float(w[I, J])
+        if col > 0:
+            P[:, J] = w[:, J] / col
+    return P
+
+
 def density(nnz: np.ndarray) -> np.ndarray:
     """P(I,J) = nnz[I,J] / sum_I nnz[I,J] (zero column -> zero P)."""
     nnz = np.asarray(nnz, dtype=np.int64)

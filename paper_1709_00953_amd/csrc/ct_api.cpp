@@ -694,6 +694,130 @@ extern "C" int ct_block_back(ct_geom* g, const int32_t* rbs, int32_t n_rb, int32
 }
 
 // ---------------------------------------------------------------------------
+// projection-area densities (Sec. II-C): P_S of every (row block, column block)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct P2 {
+    double x, y;
+};
+
+inline double cross2(double ax, double ay, double bx, double by) { return ax * by - ay * bx; }
+
+// Detector coordinate of the ray through point (px, py) in a 2D view.
+double proj2(int kind, const double* V, double px, double py) {
+    const double ax = V[0], ay = V[1], cx = V[3], cy = V[4], ux = V[6], uy = V[7];
+    if (kind == CT_PAR2D) return cross2(px - cx, py - cy, ax, ay) / cross2(ux, uy, ax, ay);
+    const double dx = px - ax, dy = py - ay;
+    if (kind == CT_FAN2D_FLAT) return cross2(ax - cx, ay - cy, dx, dy) / cross2(ux, uy, dx, dy);
+    const double nx = cx - ax, ny = cy - ay, nn = std::sqrt(nx * nx + ny * ny);
+    return std::atan2(dx * ux + dy * uy, (dx * nx + dy * ny) / nn);
+}
+
+// Area of the convex polygon `poly` (any orientation) inside [u0,u1] x [v0,v1].
+double clipped_area(std::vector<P2> poly, double u0, double u1, double v0, double v1) {
+    auto clip = [&](int axis, double bound, bool below) {
+        std::vector<P2> outp;
+        const size_t k = poly.size();
+        auto coord = [&](const P2& q) { return axis == 0 ? q.x : q.y; };
+        auto in = [&](const P2& q) { return below ? coord(q) <= bound : coord(q) >= bound; };
+        for (size_t i = 0; i < k; ++i) {
+            const P2& a = poly[(i + k - 1) % k];
+            const P2& b = poly[i];
+            const bool ia = in(a), ib = in(b);
+            if (ia != ib) {
+                const double t = (bound - coord(a)) / (coord(b) - coord(a));
+                outp.push_back(P2{a.x + t * (b.x - a.x), a.y + t * (b.y - a.y)});
+            }
+            if (ib) outp.push_back(b);
+        }
+        poly.swap(outp);
+    };
+    clip(0, u0, false);
+    if (poly.size() >= 3) clip(0, u1, true);
+    if (poly.size() >= 3) clip(1, v0, false);
+    if (poly.size() >= 3) clip(1, v1, true);
+    if (poly.size() < 3) return 0.0;
+    double a = 0.0;
+    for (size_t i = 0; i < poly.size(); ++i) {
+        const P2& p = poly[(i + poly.size() - 1) % poly.size()];
+        const P2& q = poly[i];
+        a += p.x * q.y - p.y * q.x;
+    }
+    return 0.5 * std::fabs(a);
+}
+
+// Convex hull of points (counter-clockwise), by gift wrapping from the
+// lowest point: fine for the eight projected corners of a box.
+std::vector<P2> hull(const std::vector<P2>& pts) {
+    std::vector<P2> h;
+    size_t start = 0;
+    for (size_t i = 1; i < pts.size(); ++i)
+        if (pts[i].y < pts[start].y || (pts[i].y == pts[start].y && pts[i].x < pts[start].x)) start = i;
+    size_t cur = start;
+    for (size_t guard = 0; guard <= pts.size(); ++guard) {
+        h.push_back(pts[cur]);
+        size_t nxt = (cur + 1) % pts.size();
+        for (size_t i = 0; i < pts.size(); ++i) {
+            const double c = cross2(pts[nxt].x - pts[cur].x, pts[nxt].y - pts[cur].y, pts[i].x - pts[cur].x,
+                                    pts[i].y - pts[cur].y);
+            const double dn = std::hypot(pts[nxt].x - pts[cur].x, pts[nxt].y - pts[cur].y);
+            const double di = std::hypot(pts[i].x - pts[cur].x, pts[i].y - pts[cur].y);
+            if (c < 0 || (c == 0 && di > dn)) nxt = i;          // i is to the right of cur->nxt
+        }
+        cur = nxt;
+        if (cur == start) break;
+    }
+    return h;
+}
+
+}  // namespace
+
+extern "C" int ct_geom_block_area(const ct_geom* g, double* out) {
+    if (!g || !out) return fail(CT_EINVAL, "NULL argument");
+    const ct_geom_desc& d = g->d;
+    const bool cone = d.kind == CT_CONE3D_FLAT;
+    const double c0u = 0.5 * (double)(d.nu - 1), c0v = 0.5 * (double)(d.nv - 1);
+    for (int I = 0; I < g->m; ++I)
+        for (int J = 0; J < g->n; ++J) {
+            const Box& b = g->boxes[J];
+            const double xs[2] = {d.ox + b.x0 * d.vx, d.ox + b.x1 * d.vx};
+            const double ys[2] = {d.oy + b.y0 * d.vy, d.oy + b.y1 * d.vy};
+            const double zs[2] = {d.oz + b.z0 * d.vz, d.oz + b.z1 * d.vz};
+            double acc = 0.0;
+            for (int t = g->rb_tile_ptr[I]; t < g->rb_tile_ptr[I + 1]; ++t) {
+                const Tile& tl = g->tiles[t];
+                const double* V = &g->views[(size_t)tl.view * 12];
+                const double ulo = (tl.u0 - 0.5 - c0u) * d.pu, uhi = (tl.u1 - 0.5 - c0u) * d.pu;
+                if (!cone) {
+                    double mn = INFINITY, mx = -INFINITY;
+                    for (int c = 0; c < 4; ++c) {
+                        const double u = proj2(d.kind, V, xs[c & 1], ys[(c >> 1) & 1]);
+                        mn = std::min(mn, u);
+                        mx = std::max(mx, u);
+                    }
+                    acc += std::max(0.0, std::min(uhi, mx) - std::max(ulo, mn));
+                } else {
+                    const double vlo = (tl.v0 - 0.5 - c0v) * d.pv, vhi = (tl.v1 - 0.5 - c0v) * d.pv;
+                    const double a[3] = {V[0], V[1], V[2]};
+                    double n3[3] = {V[3] - a[0], V[4] - a[1], V[5] - a[2]};
+                    const double sdd = std::sqrt(dot3(n3, n3));
+                    for (double& q : n3) q /= sdd;
+                    std::vector<P2> pts;
+                    for (int c = 0; c < 8; ++c) {
+                        const double p[3] = {xs[c & 1] - a[0], ys[(c >> 1) & 1] - a[1], zs[(c >> 2) & 1] - a[2]};
+                        const double dep = dot3(p, n3);
+                        pts.push_back(P2{sdd * dot3(p, V + 6) / dep, sdd * dot3(p, V + 9) / dep});
+                    }
+                    acc += clipped_area(hull(pts), ulo, uhi, vlo, vhi);
+                }
+            }
+            out[(size_t)I * g->n + J] = acc;
+        }
+    return CT_OK;
+}
+
+// ---------------------------------------------------------------------------
 // schedule
 // ---------------------------------------------------------------------------
 struct ct_schedule {
@@ -877,10 +1001,7 @@ extern "C" void ct_schedule_destroy(ct_schedule* s) {
     delete s;
 }
 
-extern "C" int ct_schedule_create(const ct_geom* g, const ct_sched_params* p, const int64_t* nnz,
-                                  ct_schedule** out) {
-    if (!g || !p || !nnz || !out) return fail(CT_EINVAL, "NULL argument");
-    *out = nullptr;
+static int sched_check_params(const ct_sched_params* p) {
     if (p->epochs < 0) return fail(CT_EINVAL, "epochs < 0");
     if (!(p->alpha > 0 && p->alpha <= 1) || !(p->gamma > 0 && p->gamma <= 1))
         return fail(CT_EINVAL, "alpha and gamma must lie in (0, 1]");
@@ -888,6 +1009,18 @@ extern "C" int ct_schedule_create(const ct_geom* g, const ct_sched_params* p, co
     if (!std::isfinite(p->b)) return fail(CT_EINVAL, "b not finite");
     if (p->sampling < CT_SAMPLE_DENSITY || p->sampling > CT_SAMPLE_MIXED) return fail(CT_EINVAL, "bad sampling");
     if (p->sampling == CT_SAMPLE_MIXED && !(p->theta_step >= 0)) return fail(CT_EINVAL, "theta_step < 0");
+    return CT_OK;
+}
+
+static int sched_draw(const ct_geom* g, const ct_sched_params* p, const std::vector<double>& P,
+                      ct_schedule** out);
+
+extern "C" int ct_schedule_create(const ct_geom* g, const ct_sched_params* p, const int64_t* nnz,
+                                  ct_schedule** out) {
+    if (!g || !p || !nnz || !out) return fail(CT_EINVAL, "NULL argument");
+    *out = nullptr;
+    int rc = sched_check_params(p);
+    if (rc) return rc;
     const int m = g->m, n = g->n;
     for (int i = 0; i < m * n; ++i)
         if (nnz[i] < 0) return fail(CT_EINVAL, "negative density");
@@ -899,6 +1032,32 @@ extern "C" int ct_schedule_create(const ct_geom* g, const ct_sched_params* p, co
         if (col > 0)
             for (int I = 0; I < m; ++I) P[(size_t)I * n + J] = (double)nnz[(size_t)I * n + J] / (double)col;
     }
+    return sched_draw(g, p, P, out);
+}
+
+extern "C" int ct_schedule_create_w(const ct_geom* g, const ct_sched_params* p, const double* w,
+                                    ct_schedule** out) {
+    if (!g || !p || !w || !out) return fail(CT_EINVAL, "NULL argument");
+    *out = nullptr;
+    int rc = sched_check_params(p);
+    if (rc) return rc;
+    const int m = g->m, n = g->n;
+    for (int i = 0; i < m * n; ++i)
+        if (!(w[i] >= 0) || !std::isfinite(w[i])) return fail(CT_EINVAL, "density weights must be finite and >= 0");
+    // P(I,J) = w / sum_I w (ascending I)
+    std::vector<double> P((size_t)m * n, 0.0);
+    for (int J = 0; J < n; ++J) {
+        double col = 0.0;
+        for (int I = 0; I < m; ++I) col += w[(size_t)I * n + J];
+        if (col > 0)
+            for (int I = 0; I < m; ++I) P[(size_t)I * n + J] = w[(size_t)I * n + J] / col;
+    }
+    return sched_draw(g, p, P, out);
+}
+
+static int sched_draw(const ct_geom* g, const ct_sched_params* p, const std::vector<double>& P,
+                      ct_schedule** out) {
+    const int m = g->m, n = g->n;
     ct_schedule* s = new (std::nothrow) ct_schedule();
     if (!s) return fail(CT_ENOMEM, "host allocation failed");
     s->m = m;

@@ -26,6 +26,7 @@ CT_BATCH_GRAPH = 1
 
 EXPORTS = (
     "ct_geom_create", "ct_geom_destroy", "ct_geom_get_info", "ct_geom_block_nnz",
+    "ct_geom_block_area", "ct_schedule_create_w",
     "ct_block_fwd", "ct_block_back",
     "ct_schedule_create", "ct_schedule_import", "ct_schedule_export", "ct_schedule_destroy",
     "ct_solver_workspace_bytes", "ct_solver_create", "ct_solver_destroy", "ct_solver_reset",
@@ -133,6 +134,8 @@ def lib():
             "ct_geom_destroy": [P],
             "ct_geom_get_info": [P, ctypes.POINTER(ct_geom_info)],
             "ct_geom_block_nnz": [P, f64, P, P],
+            "ct_geom_block_area": [P, P],
+            "ct_schedule_create_w": [P, ctypes.POINTER(ct_sched_params), P, ctypes.POINTER(P)],
             "ct_block_fwd": [P, P, i32, i32, P, P, i32, P],
             "ct_block_back": [P, P, i32, i32, P, P, i32, P],
             "ct_schedule_create": [P, ctypes.POINTER(ct_sched_params), P, ctypes.POINTER(P)],
@@ -258,6 +261,13 @@ def ct_geom_block_nnz(geom: Geom, tau: float, stream=None) -> np.ndarray:
     return out
 
 
+def ct_geom_block_area(geom: Geom) -> np.ndarray:
+    """P_S per (row block, column block), float64 [m, n] (host only)."""
+    out = np.zeros((geom.m, geom.n), dtype=np.float64)
+    _check(lib().ct_geom_block_area(geom.handle, _np_ptr(out)))
+    return out
+
+
 def ct_job_footprint(g, sync: int = CT_SYNC_COLUMN) -> int:
     d, keep = make_desc(g)
     sp = ct_solver_params(sync)
@@ -312,6 +322,16 @@ def ct_schedule_create(geom: Geom, params: ct_sched_params, nnz) -> Schedule:
         raise ValueError(f"nnz must be {(geom.m, geom.n)}")
     h = P()
     _check(lib().ct_schedule_create(geom.handle, ctypes.byref(params), _np_ptr(nnz), ctypes.byref(h)))
+    return Schedule(h, geom)
+
+
+def ct_schedule_create_w(geom: Geom, params: ct_sched_params, w) -> Schedule:
+    """Schedule from any nonnegative block density weights [m, n]."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    if w.shape != (geom.m, geom.n):
+        raise ValueError(f"weights must be [{geom.m}, {geom.n}]")
+    h = P()
+    _check(lib().ct_schedule_create_w(geom.handle, ctypes.byref(params), _np_ptr(w), ctypes.byref(h)))
     return Schedule(h, geom)
 
 

@@ -223,7 +223,7 @@ def cone3d(n=256, pitch=0.5, n_views=360, nd=384, pd=1.0, sid=500.0, sdd=1000.0,
                     box_blocks(n, n, n, bxy, bxy, bz))
 
 
-# Configurations of the benchmark suite (sizes as stated in the design doc).
+# Configurations of the benchmark suite.
 def config_c1():
     """2D parallel, 64^2 at 1 mm, 90 views over [0,180), 96 bins at 1 mm;
     4 angle groups x 4 quadrants."""

@@ -123,3 +123,57 @@ def test_footprint_and_workspace_are_consistent():
     fp = ct.ct_job_footprint(g)
     assert fp > ws
     assert fp < ws + 64 * 1024 * 1024
+
+
+def _area_geoms():
+    return {
+        "c1_par2d": inputs.config_c1(),
+        "fan_curved": inputs.fan2d(100, 2.56, 120, 160, 4e-3, 500.0, 1000.0, m=6, bx=3, by=2),
+        "fan_flat": inputs.fan2d(90, 2.8, 90, 170, 4e-3, 500.0, 1000.0, m=5, bx=2, by=3, curved=False,
+                                 pu_flat=3.2),
+        "fan_split": inputs.fan2d(64, 2.0, 60, 96, 4e-3, 500.0, 1000.0, m=6, bx=2, by=2, u_split=3),
+        "cone": inputs.cone3d(40, 3.2, 60, 60, 6.4, 500.0, 1000.0, m=6, bz=3, bxy=2),
+    }
+
+
+@pytest.mark.parametrize("name", list(_area_geoms()))
+def test_library_area_densities_equal_oracle(name):
+    """The library's projection-area table (its own C++ code) equals the
+    oracle's (numpy) to rounding, on every geometry kind."""
+    from oracle import area
+    g = _area_geoms()[name]
+    G = ct.ct_geom_create(g)
+    got = ct.ct_geom_block_area(G)
+    ref = area.shadow_area_table(g)
+    np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())
+    assert (ref > 0).any()
+
+
+def test_area_weighted_schedule_equals_oracle():
+    """Schedules drawn from area weights: bit-identical to the oracle's draws
+    on the oracle's own area densities (same normalisation order)."""
+    from oracle import area
+    g = _area_geoms()["fan_split"]
+    G = ct.ct_geom_create(g)
+    w = ct.ct_geom_block_area(G)
+    params = ct.sched_params(7, 0.5, 1.0, 2, 1.5, ct.CT_SAMPLE_DENSITY, 0.0, seed=4242)
+    ex = ct.ct_schedule_export(ct.ct_schedule_create_w(G, params, w))
+    o = sampler.make_schedule(sampler.density_w(area.shadow_area_table(g)), 7, 0.5, 1.0, 2, 1.5, 4242)
+    for k in ("epoch_col_ptr", "cols", "col_group_ptr", "group_rb_ptr", "rbs"):
+        assert np.array_equal(ex[k], getattr(o, k)), k
+    np.testing.assert_allclose(ex["beta"], o.beta, rtol=1e-12)
+    bad = w.copy()
+    bad[0, 0] = -1.0
+    _err(ct.ct_schedule_create_w, G, params, bad)
+
+
+def test_area_and_nnz_densities_agree_roughly():
+    """The paper's area estimate and the exact nnz density describe the same
+    sparsity: on the small parallel case they agree to a few per cent."""
+    from oracle import area
+    from oracle import csgd, siddon
+    g = inputs.config_c1()
+    S = csgd.BlockSystem(siddon.system_matrix(g), g)
+    P_nnz = sampler.density(S.nnz_table(1e-5))
+    P_area = area.area_density(g)
+    assert np.abs(P_nnz - P_area).max() < 0.03

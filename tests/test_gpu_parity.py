@@ -145,7 +145,11 @@ def _run_pair(ct, name, epochs, alpha, gamma, s, b, seed, sync="column",
     g, S = system(name)
     G = ct.ct_geom_create(g)
     x_true, y = phantom_y(g, S, seed, noise)
-    P = sampler.density(S.nnz_table(tau_for(g)))
+    if sampling == "area":                  # the paper's projection-area densities
+        from oracle import area
+        P, sampling = area.area_density(g), sampler.DENSITY
+    else:
+        P = sampler.density(S.nnz_table(tau_for(g)))
     sch = sampler.make_schedule(P, epochs, alpha, gamma, s, b, seed, sampling, 1.0 / 40)
     ref = csgd.run(S, y.astype(np.float64), sch, sync=sync)
     sc = ct.ct_schedule_import(G, sch)
@@ -168,6 +172,8 @@ def _run_pair(ct, name, epochs, alpha, gamma, s, b, seed, sync="column",
     ("fan_curved", 10, 1.0, 1.0, 3, 1.0, 2001, "column", sampler.MIXED),
     ("fan_flat", 12, 0.6, 1.0, 2, 2.0, 2100, "epoch", sampler.DENSITY),
     ("cone", 10, 1.0, 1.0, 3, 1.0, 3000, "column", sampler.DENSITY),
+    ("fan_curved", 15, 0.5, 1.0, 2, 1.0, 2002, "column", "area"),
+    ("cone", 6, 0.5, 1.0, 2, 1.0, 3001, "column", "area"),
 ])
 def test_epoch_parity(ct, case):
     name, E, a, gm, s, b, seed, sync, samp = case

@@ -332,3 +332,88 @@ def test_rays_at_matches_all_rays(name):
     assert div2 == div
     np.testing.assert_allclose(o2, org[idx], rtol=0, atol=1e-12)
     np.testing.assert_allclose(d2, dirn[idx], rtol=1e-14, atol=1e-14)
+
+
+# ----------------------------------------------------------------------------
+# projection-area densities (Sec. II-C, Alg. 5)
+# ----------------------------------------------------------------------------
+def _one_view(g, view):
+    """g restricted to one view and one row block holding the whole detector."""
+    import dataclasses
+    tiles = [np.array([[0, 0, g.nu, 0, g.nv]], dtype=np.int32)]
+    return dataclasses.replace(g, views=g.views[view:view + 1].copy(), row_blocks=tiles)
+
+
+def test_area_parallel_axis_aligned_quadrant():
+    """At 0 degrees the parallel rays run along +y and the detector axis is +x:
+    the first quadrant [-32, 0) x [-32, 0) projects onto exactly its 32 mm
+    width, inside the 96 mm detector."""
+    from oracle import area
+    g = _one_view(inputs.config_c1(), 0)
+    S = area.shadow_area_table(g)
+    assert S[0, 0] == pytest.approx(32.0, abs=1e-12)
+
+
+def test_area_fan_centred_square_closed_form():
+    """A square of side s centred on the central ray at distance D from the
+    source projects onto a flat detector at sdd as the interval of its near
+    corners: length 2 sdd (s/2) / (D - s/2)."""
+    import dataclasses
+    from oracle import area
+    g = inputs.fan2d(8, 2.0, 4, 400, 4e-3, 500.0, 1000.0, m=1, bx=1, by=1, curved=False, pu_flat=1.0)
+    g = dataclasses.replace(_one_view(g, 0), col_blocks=np.array([[0, 8, 0, 8, 0, 1]], dtype=np.int32))
+    s, D, sdd = 16.0, 500.0, 1000.0
+    assert area.shadow_area_table(g)[0, 0] == pytest.approx(2 * sdd * (s / 2) / (D - s / 2), rel=1e-12)
+
+
+def test_area_cone_centred_cube_closed_form():
+    """A cube of side s centred on the central ray projects onto the flat
+    detector as the square of its near face: area (sdd s / (D - s/2))^2."""
+    from oracle import area
+    g = _one_view(inputs.cone3d(8, 2.0, 4, 100, 1.0, 500.0, 1000.0, m=1, bz=1), 0)
+    s, D, sdd = 16.0, 500.0, 1000.0
+    assert area.shadow_area_table(g)[0, 0] == pytest.approx((sdd * s / (D - s / 2)) ** 2, rel=1e-12)
+
+
+@pytest.mark.parametrize("name", ["par2d", "fan_flat", "fan_curved", "cone"])
+def test_area_tiles_are_additive(name):
+    """Splitting every tile in two (along u) leaves P_S unchanged."""
+    import dataclasses
+    from oracle import area
+    g = tiny_geoms()[name]
+    split = []
+    for tiles in g.row_blocks:
+        out = []
+        for (v, u0, u1, v0, v1) in tiles:
+            um = (u0 + u1) // 2
+            out += [[v, u0, um, v0, v1], [v, um, u1, v0, v1]]
+        split.append(np.array(out, dtype=np.int32))
+    g2 = dataclasses.replace(g, row_blocks=split)
+    np.testing.assert_allclose(area.shadow_area_table(g2), area.shadow_area_table(g), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["par2d", "fan_flat", "fan_curved", "cone"])
+def test_area_matches_hit_bins_and_normalises(name):
+    """P_S counted independently: the bins whose Siddon row meets the column
+    block, times the bin size, agree with P_S up to the bins straddling the
+    shadow's edges; and every column of P sums to one."""
+    from oracle import area
+    g = tiny_geoms()[name]
+    A = siddon.system_matrix(g).tocsc()
+    S = area.shadow_area_table(g)
+    cell = g.pu * (g.pv if g.is3d else 1.0)
+    for J in range(g.n):
+        hit = np.zeros(g.n_rays, dtype=bool)
+        sub = A[:, g.col_block_vox(J)]
+        hit[np.unique(sub.indices[sub.data > 0])] = True
+        for I in range(g.m):
+            rays_I = g.row_block_rays(I)
+            counted = hit[rays_I].sum() * cell
+            n_views = len(g.row_blocks[I])
+            edge = (2 * g.pu * n_views if not g.is3d else
+                    2 * (g.pu + g.pv) * max(g.nu * g.pu, g.nv * g.pv) * n_views)
+            assert abs(counted - S[I, J]) <= edge + 1e-9, (I, J, counted, S[I, J])
+    P = area.area_density(g)
+    for J in range(g.n):
+        if S[:, J].sum() > 0:
+            assert P[:, J].sum() == pytest.approx(1.0, abs=1e-12)
