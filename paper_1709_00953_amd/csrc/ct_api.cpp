@@ -389,20 +389,31 @@ static void build_frames(const ct_geom* g, std::vector<Ray2F>& rayf, std::vector
                     R.p = W[17] * sdd / nD;
                     R.q = W[17] * u / nD;
                 }
+                if (std::fabs(dx) <= kAxisEps) dx = 0.0;
+                if (std::fabs(dy) <= kAxisEps) dy = 0.0;
                 F.dx = dx;
                 F.dy = dy;
                 F.idx = dx != 0.0 ? 1.0 / dx : 0.0;
                 F.idy = dy != 0.0 ? 1.0 / dy : 0.0;
-                R.pad = 0.f;
+                // the origin the forward walk starts from; a ray with a zero
+                // component stays in its origin's slab of that axis (the
+                // forward kernel's float64 half-open rule, same operations)
+                const double o0 = d.kind == CT_PAR2D ? std::fma(u, W[6], W[3]) : W[0];
+                const double o1 = d.kind == CT_PAR2D ? std::fma(u, W[7], W[4]) : W[1];
+                auto slab = [](double o, double org, double ih) {
+                    return (float)std::fmin(std::fmax(std::floor((o - org) * ih), -1e7), 1e7);
+                };
                 if (dx == 0.0) {
                     R.K = (float)dy;
                     R.S = (float)(2.0 * hy / std::fabs(dy));
                     R.M = -1.f;
+                    R.slab = slab(o0, d.ox, 1.0 / d.vx);
                     flags[k] |= 1;
                 } else if (dy == 0.0) {
                     R.K = (float)(-dx);
                     R.S = (float)(2.0 * hx / std::fabs(dx));
                     R.M = -2.f;
+                    R.slab = slab(o1, d.oy, 1.0 / d.vy);
                     flags[k] |= 1;
                 } else {
                     const double wx = hx / std::fabs(dx), wy = hy / std::fabs(dy);
@@ -413,6 +424,7 @@ static void build_frames(const ct_geom* g, std::vector<Ray2F>& rayf, std::vector
             }
         } else {
             // flag views whose rays (as the kernels form them) have a zero component
+            // (or one at most kAxisEps)
             const double sdd = W[15];
             bool z = false;
             for (int iv = 0; iv < d.nv && !z; ++iv) {
@@ -421,7 +433,8 @@ static void build_frames(const ct_geom* g, std::vector<Ray2F>& rayf, std::vector
                     const double u = ((double)iu - 0.5 * (double)(d.nu - 1)) * d.pu;
                     for (int c = 0; c < 3; ++c) {
                         const double Dk = std::fma(v, W[9 + c], std::fma(u, W[6 + c], sdd * W[12 + c]));
-                        if (Dk == 0.0 || (float)Dk == 0.f) z = true;
+                        // the kernels' staged component and their zero test
+                        if (std::fabs((float)(Dk * W[16])) <= kAxisEpsF) z = true;
                     }
                 }
             }
@@ -603,7 +616,7 @@ extern "C" int ct_geom_block_nnz(ct_geom* g, double tau, int64_t* host_nnz, void
         a.nnz = g->d_nnz;
         a.n_cols = g->n;
         a.col = J;
-        a.tau = (float)tau;
+        a.tau = tau;
         HIPCHK(launch_fwd(g->G, a, st));
     }
     std::vector<unsigned long long> tmp((size_t)g->m * g->n);

@@ -14,6 +14,12 @@ constexpr int kTile2 = 8;          // 2D back-projection tile: 8 x 8 voxels, 4 w
 constexpr int kTile3x = 8, kTile3y = 8, kTile3z = 4;   // 3D tile: 8 x 8 x 4
 // Per-view float64 frame: a(3) c(3) e_u(3) e_v(3) n(3) sdd|kappa, 1/sdd, sigma.
 constexpr int kViewStride = 24;
+// A unit ray direction component at most this large is taken as exactly zero:
+// it is float64 residue of an axis-parallel ray (cos of a quarter turn is
+// 6e-17), a tilt the float32 slab clip cannot resolve (its slab interval
+// endpoints would cancel), while the exact-zero half-open membership test can.
+constexpr double kAxisEps = 1e-12;
+constexpr float kAxisEpsF = 1e-12f;
 enum { kPar2D = 0, kFanFlat = 1, kFanCurved = 2, kCone = 3 };
 
 // J-local (x, g) pairs of a group are stored twice: copy 0 x-fastest
@@ -68,11 +74,11 @@ struct Ray2F {
 // wy = hy/|dy|), so the clip length is
 //   max(0, min(2 wx, 2 wy, wx + wy - |delta (kx - ky)|))
 // stored as K = kx - ky, S = wx + wy, M = min(2 wx, 2 wy).  A zero direction
-// component is marked by M = -1 (dx = 0) or M = -2 (dy = 0); then K turns
-// delta into the ray's offset along that axis and S is the full chord.
+// component is marked by M = -1 (dx = 0) or M = -2 (dy = 0); then S is the
+// full chord and slab the index of the one x (or y) slab the ray lies in.
 struct Ray2B {
     double p, q;
-    float K, S, M, pad;
+    float K, S, M, slab;
 };
 
 // Device-side geometry, passed by value.
@@ -119,7 +125,7 @@ struct FwdCore {
     double* partial;              // fused: per chunk sum (A g)^2
     unsigned long long* nnz;      // count: [m][n]
     int32_t n_cols, col;          // count: column count and this column
-    float tau;                    // count threshold
+    double tau;                   // count threshold
 };
 struct FwdArgs : FwdCore {
     static constexpr bool kInl = true;

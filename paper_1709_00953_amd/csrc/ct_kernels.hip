@@ -35,6 +35,7 @@
 
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <type_traits>
 
 namespace ct {
 
@@ -175,8 +176,11 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
     constexpr int DIMS = (KIND == kCone) ? 3 : 2;
     constexpr bool DIVERGENT = (KIND != kPar2D);
     constexpr int U = 4;                       // segments formed before their gathers
-    // the count mode needs whole segment lengths, so it walks each ray in one piece
+    // the count mode needs whole segment lengths, so it walks each ray in one
+    // piece, and in float64: it decides length > tau, and a float32 walk gives
+    // a touch of a voxel corner (length 0) lengths of about 1e-7 of the chord
     constexpr int K = (MODE == 2) ? 1 : kSplit;
+    using WT = typename std::conditional<MODE == 2, double, float>::type;
     __shared__ float pacc[K][kChunk], pacc2[K][kChunk];
 
     const int ei = find_entry(a, bid);
@@ -210,7 +214,8 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
             const double inv = 1.0 / sqrt(fma(D[0], D[0], fma(D[1], D[1], D[2] * D[2])));
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                d[c] = D[c] * inv;
+                // the back-projection's test on the same component (D / sdd)
+                d[c] = fabsf((float)(D[c] * V[16])) <= kAxisEpsF ? 0.0 : D[c] * inv;
                 id[c] = d[c] != 0.0 ? 1.0 / d[c] : 0.0;
                 o[c] = V[c];
             }
@@ -237,12 +242,19 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
         double t0 = DIVERGENT ? 0.0 : -INFINITY, t1 = INFINITY;
         bool hit = true;
         double lo[3];
+        int zs[3] = {0, 0, 0};
 #pragma unroll
         for (int c = 0; c < DIMS; ++c) {
             lo[c] = fma((double)b0[c], h[c], org[c]);
             const double hi = fma((double)b1[c], h[c], org[c]);
             if (d[c] == 0.0) {
-                hit = hit && (o[c] >= lo[c]) && (o[c] < hi);
+                // the ray keeps its origin's coordinate: it lies in one slab,
+                // by the half-open rule in float64 (the back-projection takes
+                // the same slab)
+                const double sl = floor((o[c] - org[c]) * ih[c]);
+                const bool in = sl >= (double)b0[c] && sl < (double)b1[c];
+                hit = hit && in;
+                zs[c] = in ? (int)(sl - (double)b0[c]) : 0;
             } else {
                 const double ta = (lo[c] - o[c]) * id[c];
                 const double tb = (hi - o[c]) * id[c];
@@ -258,31 +270,31 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
             // box-local walk: ii = voxel, dl = distance (voxel units) to the
             // next plane, inv = mm per voxel along the ray, tk = crossing
             int nb[3], ii[3], sg[3];
-            float dl[3], inv[3], tk[3];
-            float T = (float)Lc;
+            WT dl[3], inv[3], tk[3];
+            WT T = (WT)Lc;
 #pragma unroll
             for (int c = 0; c < DIMS; ++c) {
                 nb[c] = b1[c] - b0[c];
-                const float ef = (float)((fma(t0, d[c], o[c]) - lo[c]) * ih[c]);
-                int i = (int)floorf(ef);
-                if (d[c] < 0.0 && (float)i == ef) i -= 1;
+                const WT ef = (WT)((fma(t0, d[c], o[c]) - lo[c]) * ih[c]);
+                int i = (int)floor(ef);
+                if (d[c] < 0.0 && (WT)i == ef) i -= 1;
                 i = min(max(i, 0), nb[c] - 1);
-                ii[c] = i;
+                ii[c] = d[c] == 0.0 ? zs[c] : i;
                 if (d[c] > 0.0) {
                     sg[c] = 1;
-                    dl[c] = (float)(i + 1) - ef;
-                    inv[c] = (float)(h[c] * id[c]);
+                    dl[c] = (WT)(i + 1) - ef;
+                    inv[c] = (WT)(h[c] * id[c]);
                     tk[c] = dl[c] * inv[c];
                 } else if (d[c] < 0.0) {
                     sg[c] = -1;
-                    dl[c] = ef - (float)i;
-                    inv[c] = (float)(-h[c] * id[c]);
+                    dl[c] = ef - (WT)i;
+                    inv[c] = (WT)(-h[c] * id[c]);
                     tk[c] = dl[c] * inv[c];
                 } else {                       // never crossed: dl * inv stays +inf
                     sg[c] = 0;
-                    dl[c] = 1.f;
-                    inv[c] = INFINITY;
-                    tk[c] = INFINITY;
+                    dl[c] = (WT)1;
+                    inv[c] = (WT)INFINITY;
+                    tk[c] = (WT)INFINITY;
                 }
             }
             // linear voxel index and its step per axis.  The fused path uses
@@ -317,15 +329,15 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
 #pragma unroll
             for (int c = 0; c < DIMS; ++c) sst[c] = sg[c] * step[c];
             const int maxit = (nb[0] + nb[1] + (DIMS == 3 ? nb[2] : 0) + 4 + U - 1) / U;
-            float tau = 0.f;
+            WT tau = 0;
             for (int it = 0; it < maxit; ++it) {
                 int sid[U];
-                float sl[U];
+                WT sl[U];
 #pragma unroll
                 for (int q = 0; q < U; ++q) {
                     // segment q: from tau to the nearest crossing (or the exit)
-                    float tn = fminf(fminf(tk[0], tk[1]), T);
-                    if constexpr (DIMS == 3) tn = fminf(tn, tk[2]);
+                    WT tn = fmin(fmin(tk[0], tk[1]), T);
+                    if constexpr (DIMS == 3) tn = fmin(tn, tk[2]);
                     sl[q] = tn - tau;
                     tau = tn;
                     sid[q] = idx;
@@ -436,12 +448,12 @@ __device__ __forceinline__ float chord2(float delta, const Ray2B& R) {
     return fmaxf(fminf(R.M, R.S - fabsf(delta * R.K)), 0.f);
 }
 
-// Same, for rays with an exactly zero direction component (half-open voxels).
-__device__ __forceinline__ float chord2_axis(float delta, const Ray2B& R, float hx, float hy) {
+// Same, for rays with a zero direction component: such a ray lies in one
+// slab of that axis (index R.slab) and meets the voxels of that slab only.
+__device__ __forceinline__ float chord2_axis(float delta, const Ray2B& R, int ix, int iy) {
     if (R.M < 0.f) {
-        const float off = delta * R.K;
-        const float h = (R.M == -1.f) ? hx : hy;
-        return (off >= -h && off < h) ? R.S : 0.f;
+        const float mine = (R.M == -1.f) ? (float)ix : (float)iy;
+        return mine == R.slab ? R.S : 0.f;
     }
     return chord2(delta, R);
 }
@@ -512,7 +524,6 @@ __device__ __forceinline__ void view_params(const DGeom& G, const Tile& tl, doub
             // u = sdd * B / A; Hessian norm of B/A <= 2 (1 + |B/A|) / A^2
             const double sdd = V[15];
             const double ia = 1.0 / A;
-            const double tb = (fabs(B) + dt) / amin;   // bound of |B/A| over the tile
             bc = sdd * B * ia / G.pu + c0;
             bxs = sdd * (A * P.bx - B * P.ax) * ia * ia / G.pu;
             bys = sdd * (A * P.by - B * P.ay) * ia * ia / G.pu;
@@ -553,7 +564,6 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
     const double dt = sqrt((hkx * G.vx) * (hkx * G.vx) + (hky * G.vy) * (hky * G.vy));
     const float lxf = (float)lx - (float)hkx, lyf = (float)ly - (float)hky;
     const double lxd = (double)lxf, lyd = (double)lyf;
-    const float hx = (float)(0.5 * G.vx), hy = (float)(0.5 * G.vy);
 
     int e0 = 0, e1 = a.n_ent;
     if (a.gptr) {
@@ -604,7 +614,7 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
                     for (int b = blo; b <= bhi; ++b) {
                         const Ray2B Rb = ldu(RB, (unsigned)b);
                         const float dlt = (float)fma(Rb.p, B, -Rb.q * A);
-                        acc = fmaf(chord2_axis(dlt, Rb, hx, hy), ldu(rr, (unsigned)b), acc);
+                        acc = fmaf(chord2_axis(dlt, Rb, ix, iy), ldu(rr, (unsigned)b), acc);
                     }
                 } else {
                     for (int b = blo; b <= bhi; ++b) {
@@ -682,6 +692,7 @@ struct ViewP3 {
     float eu[3], ev[3], n[3];
     int32_t view, fu0, fu1, fv0, fv1;     // detector window [fu0, fu1) x [fv0, fv1)
     int32_t uref, vref, flags;
+    int32_t sk[3];                // the source's slab per axis (rays with a zero component stay in it)
 };
 
 constexpr int kRayC = 256;        // staged rays per pass
@@ -713,6 +724,11 @@ __device__ __forceinline__ void view_params3(const DGeom& G, const Tile& tl, con
     }
     P.view = tl.view;
     P.flags = G.view_flags[tl.view];
+    {
+        const double org[3] = {G.ox, G.oy, G.oz}, ih[3] = {G.ivx, G.ivy, G.ivz};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) P.sk[k] = (int)fmin(fmax(floor((V[k] - org[k]) * ih[k]), -1e9), 1e9);
+    }
     P.At = (float)At;
     P.But = (float)But;
     P.Bvt = (float)Bvt;
@@ -776,11 +792,11 @@ __device__ __forceinline__ void view_params3(const DGeom& G, const Tile& tl, con
     P.dvs = (float)(G.pv * isdd);
 }
 
-// Clip length of a staged ray with the voxel at offsets (du, dv); a zero
-// direction component (careful views only) is a membership test of the
-// half-open slab instead.
+// Clip length of a staged ray with the voxel at offsets (du, dv); for a zero
+// direction component (careful views only) the ray stays in the source's slab
+// of that axis, so the voxel (indices vi) meets it only in that slab.
 __device__ __forceinline__ float clip3(float du, float dv, const float4& q0, const float4& q1,
-                                       const float4& q2, const ViewP3& P, const float hh[3],
+                                       const float4& q2, const ViewP3& P, const int vi[3],
                                        bool careful) {
     const float s0 = fmaf(du, q0.x, dv * q1.x);
     const float s1 = fmaf(du, q0.y, dv * q1.y);
@@ -796,8 +812,7 @@ __device__ __forceinline__ float clip3(float du, float dv, const float4& q0, con
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 if ((zero >> k) & 1) {
-                    const float g = du * P.eu[k] + dv * P.ev[k];
-                    if (!(g > -hh[k] && g <= hh[k])) hi = -INFINITY;
+                    if (vi[k] != P.sk[k]) hi = -INFINITY;
                 } else {
                     lo = fmaxf(lo, ss[k] - ww[k]);
                     hi = fminf(hi, ss[k] + ww[k]);
@@ -823,6 +838,7 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
     const int iy = a.box.y0 + ty * kTile3y + ly;
     const int iz = a.box.z0 + tz * kTile3z + lz;
     const bool valid = ix < a.box.x1 && iy < a.box.y1 && iz < a.box.z1;
+    const int vi[3] = {ix, iy, iz};
 
     // tile centre, bounding-sphere radius, and this voxel's offset from the centre
     const int xs = a.box.x0 + tx * kTile3x, ys = a.box.y0 + ty * kTile3y, zs = a.box.z0 + tz * kTile3z;
@@ -918,7 +934,7 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
                         for (int k = 0; k < 3; ++k) {
                             const double Dk = fma(v, V[9 + k], fma(u, V[6 + k], V[15] * V[12 + k]));
                             d[k] = (float)(Dk * V[16]);
-                            zero |= (d[k] == 0.f) ? (1 << k) : 0;
+                            zero |= (fabsf(d[k]) <= kAxisEpsF) ? (1 << k) : 0;
                         }
                         float al[3], be[3], w[3];
 #pragma unroll
@@ -951,7 +967,7 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
                         const float du = fmaf((float)ku, stu, du0);
                         const float dv = fmaf((float)kv, stv, dv0);
                         const float4 q0 = rc0[li + ku], q1 = rc1[li + ku], q2 = rc2[li + ku];
-                        acc = fmaf(clip3(du, dv, q0, q1, q2, P, hh, careful), q2.z, acc);
+                        acc = fmaf(clip3(du, dv, q0, q1, q2, P, vi, careful), q2.z, acc);
                         const bool wrap = ku + 1 == nu_w;
                         ku = wrap ? 0 : ku + 1;
                         kv = wrap ? kv + 1 : kv;

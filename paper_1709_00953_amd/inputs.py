@@ -100,9 +100,19 @@ class Geometry:
 # scan trajectories
 # ----------------------------------------------------------------------------
 
+def _cos_sin(thetas):
+    """cos and sin of view angles, exact at quarter turns: float64 leaves
+    residues such as cos(pi/2) = 6e-17 there, which would tilt a ray that runs
+    along a voxel face by that much and split it between two voxel columns."""
+    c, s = np.cos(thetas), np.sin(thetas)
+    c[np.abs(c) < 1e-12] = 0.0
+    s[np.abs(s) < 1e-12] = 0.0
+    return c, s
+
+
 def _par2d_views(thetas):
     v = np.zeros((len(thetas), 12))
-    c, s = np.cos(thetas), np.sin(thetas)
+    c, s = _cos_sin(thetas)
     v[:, 0], v[:, 1] = -s, c              # ray direction
     v[:, 6], v[:, 7] = c, s               # detector axis, detector centre at 0
     return v
@@ -110,7 +120,7 @@ def _par2d_views(thetas):
 
 def _circular_views(thetas, sid, sdd, third_axis=False):
     v = np.zeros((len(thetas), 12))
-    c, s = np.cos(thetas), np.sin(thetas)
+    c, s = _cos_sin(thetas)
     v[:, 0], v[:, 1] = sid * c, sid * s               # source
     v[:, 3], v[:, 4] = -(sdd - sid) * c, -(sdd - sid) * s  # detector centre
     v[:, 6], v[:, 7] = -s, c                          # e_u
@@ -250,6 +260,30 @@ def config_c3():
 def config_p3():
     """Parity-scale C3: 48^3 at 128/48 mm, 360 views of 72^2 at 256/48 mm."""
     return cone3d(48, 128.0 / 48, 360, 72, 256.0 / 48, 500.0, 1000.0, m=12, bz=8)
+
+
+def config_paper2d():
+    """The paper's 2D setting (Sec. III): 64^2 pixels of 1, flat 187-pixel
+    detector of spacing 1, source and detector centre on circles of radius
+    115 (SDD 230), 360 views over 360 degrees; one row block per (view,
+    detector half), 720 in all; 2 x 2 image quadrants."""
+    n_views, nu = 360, 187
+    th = np.deg2rad(360.0) * np.arange(n_views) / n_views
+    return Geometry(FAN2D_FLAT, 64, 64, 1, 1.0, 1.0, 1.0, -32.0, -32.0, 0.0,
+                    nu, 1, 1.0, 1.0, _circular_views(th, 115.0, 230.0),
+                    detector_area_blocks(n_views, nu, 1, 2), box_blocks(64, 64, 1, 2, 2, 1))
+
+
+def config_paper3d(n=128, nd=202, n_views=720, m=60, seed=5300):
+    """The paper's 3D setting (Sec. III-G): n^3 voxels over a 32^3 volume, a
+    square detector of side 101 (nd x nd pixels), 720 source positions drawn
+    at random on a sphere of radius 66, detector plane perpendicular at
+    distance 132; m view groups (whole detector) x 2 x 2 x 2 volume blocks."""
+    pitch, pd = 32.0 / n, 101.0 / nd
+    half = 16.0
+    return Geometry(CONE3D_FLAT, n, n, n, pitch, pitch, pitch, -half, -half, -half,
+                    nd, nd, pd, pd, sphere_views(n_views, 66.0, 132.0, seed),
+                    angle_group_blocks(n_views, m, nd, nd), box_blocks(n, n, n, 2, 2, 2))
 
 
 def slice_fan(nn: int, m=4, bx=2, by=2):

@@ -40,11 +40,34 @@ def geom_cone():
     return inputs.cone3d(40, 3.2, 120, 60, 6.4, 500.0, 1000.0, m=6, bz=3, bxy=2)
 
 
+# Rays on voxel faces: odd detectors whose central bin looks through the
+# rotation centre, which is a grid corner of an even voxel grid, with views at
+# quarter turns.  Parallel rays at every integer offset lie on faces there; in
+# the cone the central detector row lies in the face plane z = 0 and the
+# central ray runs along an edge.  The diagonal views pass through corners.
+def geom_par_axis():
+    return inputs.par2d(32, 1.0, 8, 360.0, 47, 1.0, m=4, bx=2, by=2)
+
+
+def geom_fan_axis():
+    return inputs.fan2d(40, 1.0, 8, 61, 8e-3, 100.0, 200.0, m=4, bx=2, by=2)
+
+
+def geom_fan_flat_axis():
+    return inputs.fan2d(40, 1.0, 8, 61, 8e-3, 100.0, 200.0, m=4, bx=2, by=2, curved=False,
+                        pu_flat=1.0)
+
+
+def geom_cone_axis():
+    return inputs.cone3d(24, 1.0, 8, 41, 1.0, 100.0, 200.0, m=4, bz=2, bxy=2)
+
+
 GEOMS = {"c1_par2d": geom_c1, "fan_curved": geom_fan_curved, "fan_flat": geom_fan_flat,
-         "cone": geom_cone}
+         "cone": geom_cone, "par_axis": geom_par_axis, "fan_axis": geom_fan_axis,
+         "fan_flat_axis": geom_fan_flat_axis, "cone_axis": geom_cone_axis}
 
 
-@functools.lru_cache(maxsize=8)
+@functools.lru_cache(maxsize=len(GEOMS))
 def system(name):
     g = GEOMS[name]()
     return g, csgd.BlockSystem(siddon.system_matrix(g), g)

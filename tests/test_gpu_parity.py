@@ -136,8 +136,8 @@ def test_block_density_table(ct, name):
     tau = tau_for(g)
     gpu = ct.ct_geom_block_nnz(G, tau)
     ref = S.nnz_table(tau)
-    assert np.array_equal(gpu == 0, ref == 0)
-    assert np.abs(gpu - ref).sum() <= 1e-4 * ref.sum()
+    # integer work, decided on float64 lengths on both sides: exact
+    assert np.array_equal(gpu, ref), np.abs(gpu - ref).sum()
 
 
 def _run_pair(ct, name, epochs, alpha, gamma, s, b, seed, sync="column",
@@ -240,3 +240,70 @@ def test_solve_counts_updates_and_converges(ct):
                 want += 2 * nnz[sch["rbs"][k], J]
     assert st["ray_voxel_updates"] == want
     assert abs(ct.ct_true_residual(ct.ct_solver_create(G), dev(y), xd) - st["rel_residual"]) < 1e-6
+
+
+def _residue_views(n_views, sid, sdd, third_axis):
+    """Circular views from plain float64 cos/sin: the quarter turns keep the
+    residue cos(pi/2) = 6e-17, a tilt of that size of every ray that should be
+    parallel to an axis."""
+    th = 2 * np.pi * np.arange(n_views) / n_views
+    c, s = np.cos(th), np.sin(th)
+    v = np.zeros((n_views, 12))
+    v[:, 0], v[:, 1] = sid * c, sid * s
+    v[:, 3], v[:, 4] = -(sdd - sid) * c, -(sdd - sid) * s
+    v[:, 6], v[:, 7] = -s, c
+    if third_axis:
+        v[:, 11] = 1.0
+    return v
+
+
+@pytest.mark.parametrize("name", ["fan_flat_axis", "cone_axis"])
+def test_residue_axis_rays(ct, name):
+    """Rays on voxel faces whose direction carries float64 residue of an axis
+    (the exact geometry puts them on the face; the oracle's float64 walk
+    splits them between the two voxels at the face where the residue tilt
+    crosses it, a split float32 cannot resolve).  What is unique must match:
+    every other ray and voxel to 1e-5, the chord length of every ray (row sum
+    of A) to 1e-5, and the back-projection of every row block keeps the total
+    length of its rays (none lost or counted twice)."""
+    import dataclasses
+    from oracle import rays, siddon
+    g0 = GEOMS[name]()
+    g = dataclasses.replace(g0, views=_residue_views(g0.n_views, 100.0, 200.0, g0.is3d))
+    G = ct.ct_geom_create(g)
+    A = siddon.system_matrix(g).tocsr()
+    S = csgd.BlockSystem(A, g)
+    _, d, _ = rays.rays(g)
+    ad = np.abs(d) / np.linalg.norm(d, axis=1, keepdims=True)
+    degen = np.any((ad > 0) & (ad <= 1e-12), axis=1)
+    assert degen.sum() > 0
+    print(f"[residue] {name}: {degen.sum()} residue-tilted rays", flush=True)
+    ones = dev(np.ones(g.n_vox))
+    yd = torch.zeros(G.M, device="cuda")
+    for J in range(g.n):
+        ct.ct_block_fwd(G, list(range(g.m)), J, ones, yd, flags=ct.CT_ACCUMULATE)
+    rowsum = np.asarray(A.sum(axis=1)).ravel()
+    assert np.all(np.abs(host(yd) - rowsum) <= 1e-5 * rowsum.max())
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0.0, 1.0, g.n_vox).astype(np.float32)
+    r = rng.normal(0.0, 1.0, g.n_rays).astype(np.float32)
+    r[degen] = 0.0
+    for I in range(g.m):
+        rows = S.rows[I]
+        for J in range(g.n):
+            yd = torch.zeros(G.M, device="cuda")
+            ct.ct_block_fwd(G, [I], J, dev(x), yd)
+            keep = ~degen[rows]
+            ref = csgd.block_fwd(S, [I], J, x.astype(np.float64))
+            assert rel_l2(host(yd)[rows][keep], ref[keep]) <= 1e-5, (I, J)
+            gd = torch.zeros(G.N, device="cuda")
+            ct.ct_block_back(G, [I], J, dev(r), gd)
+            refb = csgd.block_back(S, [I], J, r.astype(np.float64))
+            assert rel_l2(host(gd)[S.vox[J]], refb) <= 1e-5, (I, J)
+        gd = torch.zeros(G.N, device="cuda")
+        ri = np.zeros(g.n_rays, np.float32)
+        ri[rows] = 1.0
+        for J in range(g.n):
+            ct.ct_block_back(G, [I], J, dev(ri), gd, flags=ct.CT_ACCUMULATE)
+        tot = rowsum[rows].sum()
+        assert abs(host(gd).sum() - tot) <= 1e-5 * tot, I

@@ -91,6 +91,24 @@ def test_axis_aligned_rows_config_c1():
     np.testing.assert_allclose(p[45 * nu + 16:45 * nu + 80], img.sum(axis=1), rtol=1e-12, atol=1e-12)
 
 
+
+def test_face_rays_follow_half_open_voxels():
+    """The 2D setting of Sec. III: 187 bins, the central one looking through
+    the rotation centre, a corner of the 64^2 grid.  At quarter turns (exact
+    views) that ray runs along the grid line x = 0 or y = 0, a face shared by
+    pixel columns / rows 31 and 32; half-open pixels [i, i+1) give it wholly
+    to index 32, 64 entries of 1."""
+    g = inputs.config_paper2d()
+    V = np.asarray(g.views)
+    for view in (0, 90, 180, 270):
+        assert np.count_nonzero(V[view, [0, 1, 3, 4, 6, 7]]) == 3, view
+    A = siddon.system_matrix(g)
+    for view, axis in ((0, "row"), (90, "col"), (180, "row"), (270, "col")):
+        row = A.getrow(view * g.nu + 93)
+        expect = (32 * 64 + np.arange(64)) if axis == "row" else (np.arange(64) * 64 + 32)
+        assert sorted(row.indices.tolist()) == sorted(expect.tolist()), view
+        np.testing.assert_allclose(row.data, 1.0, rtol=0, atol=1e-12)
+
 def _disk_error(n):
     g = inputs.par2d(n, 64.0 / n, 8, 180.0, 90, 0.6, m=1, bx=1, by=1)
     R, mu, cx, cy = 20.0, 0.7, 3.3, -2.1
