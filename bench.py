@@ -51,8 +51,10 @@ BATCH_SIZES = (128, 256, 384, 512, 768, 1024)
 # An entry holds only for the kernel version the counters were taken on.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 TRAFFIC_KIB = {
-    ("fan2d_512", "back"): {"fetch": 11596.0, "write": 2112.0,
+    ("fan2d_512", "back"): {"fetch": 11584.0, "write": 2112.0,
                             "profile": "profiles/fan2d_512_back_projection_hbm_traffic.md"},
+    ("cone3d_256", "back"): {"fetch": 169028.0, "write": 132098.0,
+                             "profile": "profiles/cone3d_256_counters.md"},
 }
 SERVE_FAN = (256, 384, 512, 768, 1024)
 SERVE_CONE = (64, 96, 128, 160, 192)
@@ -71,6 +73,23 @@ def single_workload(name):
         return (inputs.config_c3(), dict(alpha=1.0, gamma=1.0, s=3, b=1.0, seed=3000, photons=1e5),
                 "cone3d 256^3 0.5mm, 360 views/360deg of 384x384 1mm, SID 500 SDD 1000, 12 view "
                 "groups x 8 z-slabs, alpha 1, s 3 (4 groups), Poisson 1e5 photons")
+    if name == "fan2d_512_parallel":
+        return (inputs.config_c2(), dict(alpha=0.5, gamma=0.5, s=1, b=1.0, seed=2000, noise=0.01,
+                                         sync="epoch"),
+                "fan2d_curved 512x512 as fan2d_512, fully parallel reading: r refreshed once per "
+                "epoch, half of the column blocks per epoch (gamma 0.5), alpha 0.5, s 1")
+    if name == "paper2d_64":
+        return (inputs.config_paper2d(), dict(alpha=0.5, gamma=1.0, s=100, b=2.0, seed=6000,
+                                              noise=0.01),
+                "paper 2D setting: fan2d_flat 64x64 1mm, 360 views/360deg, 187 bins 1mm, SID 115 "
+                "SDD 230, 720 row blocks (view x detector half) x 4 quadrants, alpha 0.5, s 100, b 2")
+    if name == "paper3d_128":
+        return (inputs.config_paper3d(), dict(alpha=0.5, gamma=1.0, s=90, b=1.0, seed=6200,
+                                              noise=0.01,
+                                              cpu_geom=lambda: inputs.config_paper3d(24, 40, 360)),
+                "paper 3D setting: cone3d_flat 128^3 over 32^3, 720 random views on a sphere of "
+                "radius 66, 202^2 bins over 101^2, SDD 132, 720 row blocks (views) x 8 blocks, "
+                "alpha 0.5, s 90, b 1")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -213,7 +232,7 @@ def run_single(args):
     sched = ct.ct_schedule_create(G, params, nnz)
     ex = ct.ct_schedule_export(sched)
     upd = updates_per_epoch(ex, nnz)
-    sol = ct.ct_solver_create(G)
+    sol = ct.ct_solver_create(G, ct.CT_SYNC_EPOCH if cfg.get("sync") == "epoch" else ct.CT_SYNC_COLUMN)
     x = torch.zeros(G.N, device="cuda")
     ct.ct_solver_reset(sol, y)
     torch.cuda.synchronize()
@@ -255,14 +274,15 @@ def run_single(args):
         if g.is3d:
             # the explicit FP64 A of the full volume does not fit; time the
             # oracle on the same geometry at parity scale instead
-            gs = inputs.config_p3()
+            gs = cfg["cpu_geom"]() if "cpu_geom" in cfg else inputs.config_p3()
             Gs = ct.ct_geom_create(gs)
             ys_np, _ = make_y(ct, inputs, Gs, gs, cfg, cfg["seed"])
             nnzs = ct.ct_geom_block_nnz(Gs, 1e-5 * min(gs.vx, gs.vy))
             exs = ct.ct_schedule_export(ct.ct_schedule_create(Gs, params, nnzs))
             out["cpu_baseline"] = cpu_baseline(
                 gs, ys_np, exs, args.cpu_budget,
-                note="parity-scale version of the cone geometry (48^3, 360 views of 72^2): ")
+                note=f"parity-scale version of the cone geometry ({gs.nx}^3, {gs.n_views} views of "
+                     f"{gs.nu}^2): ")
         else:
             out["cpu_baseline"] = cpu_baseline(g, y_np, ex, args.cpu_budget)
     return out
@@ -521,7 +541,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fan2d_512",
-                    choices=["fan2d_512", "par2d_64", "cone3d_256", "batch64", "serve40",
+                    choices=["fan2d_512", "par2d_64", "cone3d_256", "fan2d_512_parallel", "paper2d_64",
+                             "paper3d_128", "batch64", "serve40",
                              "copy256"])
     ap.add_argument("--jobs", type=int, default=None,
                     help="batch64: slices (64); serve40: jobs in the stream (1000)")

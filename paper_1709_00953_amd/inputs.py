@@ -274,16 +274,17 @@ def config_paper2d():
                     detector_area_blocks(n_views, nu, 1, 2), box_blocks(64, 64, 1, 2, 2, 1))
 
 
-def config_paper3d(n=128, nd=202, n_views=720, m=60, seed=5300):
+def config_paper3d(n=128, nd=202, n_views=720, seed=5300):
     """The paper's 3D setting (Sec. III-G): n^3 voxels over a 32^3 volume, a
     square detector of side 101 (nd x nd pixels), 720 source positions drawn
     at random on a sphere of radius 66, detector plane perpendicular at
-    distance 132; m view groups (whole detector) x 2 x 2 x 2 volume blocks."""
+    distance 132; every projection one row block (no detector split) x
+    2 x 2 x 2 volume blocks."""
     pitch, pd = 32.0 / n, 101.0 / nd
     half = 16.0
     return Geometry(CONE3D_FLAT, n, n, n, pitch, pitch, pitch, -half, -half, -half,
                     nd, nd, pd, pd, sphere_views(n_views, 66.0, 132.0, seed),
-                    angle_group_blocks(n_views, m, nd, nd), box_blocks(n, n, n, 2, 2, 2))
+                    detector_area_blocks(n_views, nd, nd, 1), box_blocks(n, n, n, 2, 2, 2))
 
 
 def slice_fan(nn: int, m=4, bx=2, by=2):

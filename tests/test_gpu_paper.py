@@ -36,7 +36,7 @@ def host(t):
 
 @functools.lru_cache(maxsize=2)
 def system(name):
-    g = inputs.config_paper2d() if name == "paper2d" else inputs.config_paper3d(24, 40, 360, 30)
+    g = inputs.config_paper2d() if name == "paper2d" else inputs.config_paper3d(24, 40, 360)
     return g, csgd.BlockSystem(siddon.system_matrix(g), g)
 
 
@@ -108,8 +108,10 @@ def test_paper2d_area_sampling(ct):
 
 
 def test_paper3d_sphere_epochs(ct):
-    """Random-sphere trajectory (general view frames, no circular structure)."""
-    ref, x, z, r, y = _epochs(ct, "paper3d_small", 3, 0.5, 3, 2.0, 6200)
+    """Random-sphere trajectory (general view frames, no circular structure),
+    the paper's 3D parameters: every projection a row block, groups of 90,
+    b = 1, alpha = 0.5."""
+    ref, x, z, r, y = _epochs(ct, "paper3d_small", 3, 0.5, 90, 1.0, 6200)
     assert rel_l2(x, ref.x) <= 1e-4
     assert rel_l2(z, ref.z) <= 1e-4
     assert np.linalg.norm(r - ref.r) <= 1e-4 * np.linalg.norm(y)
@@ -124,7 +126,7 @@ def test_paper3d_fullsize_sampled(ct):
     G = ct.ct_geom_create(g)
     rng = np.random.default_rng(8)
     x = rng.uniform(0.0, 1.0, g.n_vox).astype(np.float32)
-    rbs, J = [3, 17, 40], 5
+    rbs, J = [3, 17, 40, 411], 5
     yd = torch.full((G.M,), 7.0, device="cuda")
     ct.ct_block_fwd(G, rbs, J, dev(x), yd)
     got = host(yd)
