@@ -25,12 +25,16 @@ enum { kPar2D = 0, kFanFlat = 1, kFanCurved = 2, kCone = 3 };
 // J-local (x, g) pairs of a group are stored twice: copy 0 x-fastest
 // ([z][y][x]) and copy 1 y-fastest ([z][x][y]).  The forward pass reads the
 // copy whose fast axis runs across its rays, so the lanes of a wave (adjacent
-// rays) gather adjacent pixels.  Each copy has xg_pad zero elements before and
-// after it, so the walk may step a few voxels past the exit without a bounds
-// check: those segments have zero length and read finite values.
+// rays) gather adjacent pixels.  The walk forms kWalkU segments before their
+// gathers, so it can step past the box by one crossing that float32 rounding
+// places before the exit, then by up to kWalkU - 1 more to the end of the
+// batch, each by at most the largest index stride.  Each copy has xg_pad zero
+// elements before and after it, enough for those steps and one more: they
+// read finite values for segments of zero length, with no bounds check.
+constexpr int kWalkU = 4;
 __host__ __device__ inline int xg_pad(int nx, int ny, int nz) {
     const int step = nz > 1 ? nx * ny : (nx > ny ? nx : ny);
-    return 4 * step + 64;
+    return (kWalkU + 1) * step + 64;
 }
 __host__ __device__ inline int xg_copy(int nx, int ny, int nz) { return nx * ny * nz + 2 * xg_pad(nx, ny, nz); }
 __host__ __device__ inline int xg_size(int nx, int ny, int nz) { return 2 * xg_copy(nx, ny, nz); }

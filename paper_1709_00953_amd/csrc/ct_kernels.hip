@@ -175,7 +175,7 @@ template <int KIND, int MODE, class FA>
 __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int bid) {
     constexpr int DIMS = (KIND == kCone) ? 3 : 2;
     constexpr bool DIVERGENT = (KIND != kPar2D);
-    constexpr int U = 4;                       // segments formed before their gathers
+    constexpr int U = kWalkU;                  // segments formed before their gathers (padding: xg_pad)
     // the count mode needs whole segment lengths, so it walks each ray in one
     // piece, and in float64: it decides length > tau, and a float32 walk gives
     // a touch of a voxel corner (length 0) lengths of about 1e-7 of the chord
@@ -547,7 +547,6 @@ template <int KIND, class BA>
 __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const int gi, const int tile,
                                            const int n_tiles) {
     __shared__ ViewP vp[4][64];
-    __shared__ float red[4][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wu = __builtin_amdgcn_readfirstlane(w);
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
@@ -616,11 +615,20 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
                         const float dlt = (float)fma(Rb.p, B, -Rb.q * A);
                         acc = fmaf(chord2_axis(dlt, Rb, ix, iy), ldu(rr, (unsigned)b), acc);
                     }
-                } else {
+                } else if (blo <= bhi) {
+                    // the next candidate's loads are issued before this one's
+                    // clip, so their latency overlaps the arithmetic
+                    Ray2B Rn = ldu(RB, (unsigned)blo);
+                    float rn = ldu(rr, (unsigned)blo);
                     for (int b = blo; b <= bhi; ++b) {
-                        const Ray2B Rb = ldu(RB, (unsigned)b);
+                        const Ray2B Rb = Rn;
+                        const float rv = rn;
+                        if (b < bhi) {
+                            Rn = ldu(RB, (unsigned)(b + 1));
+                            rn = ldu(rr, (unsigned)(b + 1));
+                        }
                         const float dlt = (float)fma(Rb.p, B, -Rb.q * A);
-                        acc = fmaf(chord2(dlt, Rb), ldu(rr, (unsigned)b), acc);
+                        acc = fmaf(chord2(dlt, Rb), rv, acc);
                     }
                 }
             }
@@ -629,9 +637,11 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
     }
 
     // the four waves' partial sums, added in a fixed order
-    red[w][lane] = acc;
+    // the view parameters are dead here: their LDS holds the partial sums
+    float* red = reinterpret_cast<float*>(&vp[0][0]);
+    red[w * 64 + lane] = acc;
     __syncthreads();
-    const float gsum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    const float gsum = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
     const int nxJ = a.box.x1 - a.box.x0;
     if (a.fused) {
         if (w == 0) {
@@ -652,8 +662,10 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
     }
 }
 
+// 20 KB of LDS and at most 64 VGPRs: eight work-groups per CU, so a launch of
+// 2048 tiles (four groups of a 128 x 256 block) is resident in one round
 template <int KIND, class BA>
-__global__ __launch_bounds__(256) void k_back2(DGeom G, BA a) {
+__global__ __launch_bounds__(256, 8) void k_back2(DGeom G, BA a) {
     back2_body<KIND>(G, a, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
@@ -1146,8 +1158,9 @@ __device__ __forceinline__ int box_vox(const Box& b) {
     return (b.x1 - b.x0) * (b.y1 - b.y0) * (b.z1 - b.z0);
 }
 
+// occupancy as the single-job kernels: eight waves per SIMD in 2D, four in 3D
 template <int KIND>
-__global__ __launch_bounds__(256, 4) void kb_back(BatchArgs B) {
+__global__ __launch_bounds__(256, KIND == kCone ? 4 : 8) void kb_back(BatchArgs B) {
     const int k = batch_job(B, blockIdx.x);
     const int L = blockIdx.x - B.prefix[k];
     const BJob J = cld(B.jobs, k);
