@@ -973,18 +973,30 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
                                       fmaf(-dA, fmaf((float)(ua - P.uref), P.dus, P.usr), dBu);
                     const float dv0 = (float)fma((double)(va - P.vref), P.slv, P.D0v) +
                                       fmaf(-dA, fmaf((float)(va - P.vref), P.dvs, P.vsr), dBv);
-                    int ku = 0, kv = 0;
-                    int li = (va - cv0) * pw + (ua - cu0);
-                    for (int c = 0; c < n_c; ++c) {
-                        const float du = fmaf((float)ku, stu, du0);
-                        const float dv = fmaf((float)kv, stv, dv0);
-                        const float4 q0 = rc0[li + ku], q1 = rc1[li + ku], q2 = rc2[li + ku];
-                        acc = fmaf(clip3(du, dv, q0, q1, q2, P, vi, careful), q2.z, acc);
-                        const bool wrap = ku + 1 == nu_w;
-                        ku = wrap ? 0 : ku + 1;
-                        kv = wrap ? kv + 1 : kv;
-                        li = wrap ? li + pw : li;
-                    }
+                    // the rectangle row by row in one flat loop: the offsets
+                    // (exact small integers) are kept as floats and the LDS
+                    // index jumps to the next row at the end of one; one copy
+                    // of the loop per kind of view (a uniform branch)
+                    const int li0 = (va - cv0) * pw + (ua - cu0);
+                    const int li_end = li0 + (vb - va + 1) * pw;     // where the last wrap lands
+                    const int jump = pw - nu_w + 1;
+                    const float last = (float)(nu_w - 1);
+                    auto candidates = [&](auto careful_c) {
+                        float kuf = 0.f, kvf = 0.f;
+                        int li = li0;
+                        do {
+                            const float du = fmaf(kuf, stu, du0);
+                            const float dv = fmaf(kvf, stv, dv0);
+                            const float4 q0 = rc0[li], q1 = rc1[li], q2 = rc2[li];
+                            acc = fmaf(clip3(du, dv, q0, q1, q2, P, vi, decltype(careful_c)::value), q2.z, acc);
+                            const bool wrap = kuf == last;
+                            kuf = wrap ? 0.f : kuf + 1.f;
+                            kvf = wrap ? kvf + 1.f : kvf;
+                            li += wrap ? jump : 1;
+                        } while (li != li_end);
+                    };
+                    if (careful) candidates(std::true_type{});
+                    else candidates(std::false_type{});
                 }
             }
         }
