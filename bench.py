@@ -232,6 +232,10 @@ def run_single(args):
     sched = ct.ct_schedule_create(G, params, nnz)
     ex = ct.ct_schedule_export(sched)
     upd = updates_per_epoch(ex, nnz)
+    # launch shapes of the projectors, timed once per size class (set-up)
+    t_tune = time.perf_counter()
+    shape = ct.ct_geom_tune(G, sched)
+    t_tune = time.perf_counter() - t_tune
     sol = ct.ct_solver_create(G, ct.CT_SYNC_EPOCH if cfg.get("sync") == "epoch" else ct.CT_SYNC_COLUMN)
     x = torch.zeros(G.N, device="cuda")
     ct.ct_solver_reset(sol, y)
@@ -263,7 +267,11 @@ def run_single(args):
     out = base_record(args, timed_updates / (ms * 1e-3), ms, args.steps)
     roof, gather = roofline_of(kt, prof_updates, args.workload)
     out["config"] = {"workload": desc, "epoch_updates": upd[args.warmup], "b": cfg["b"],
-                     "rel_residual_after": rel, "setup_s": round(t_setup, 3)}
+                     "rel_residual_after": rel, "setup_s": round(t_setup, 3),
+                     "launch_shape": {"fwd_split": shape["fwd_split"], "back_waves": shape["back_waves"],
+                                      "tuned_ms_per_epoch": round(shape["ms"], 4),
+                                      "default_ms_per_epoch": round(shape["ms_default"], 4)},
+                     "tune_s": round(t_tune, 3)}
     out["roofline"] = roof
     out["gather_equivalent_hbm"] = gather
     out["kernels_ms"] = {k: round(v[0], 4) for k, v in kt.items()}
@@ -327,6 +335,23 @@ def run_batch(args):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
 
+    # launch shapes: the tuner times each size class of the mix once; the jobs'
+    # geometries take the batch's choice, so the one-at-a-time runs below use
+    # the same shapes as the batched ones
+    t_tune = time.perf_counter()
+    Bt = ct.ct_batch_create(n_jobs)
+    tids = [ct.ct_batch_add(Bt, j["sol"], j["sched"], j["y"], j["x"]) for j in jobs]
+    shapes = ct.ct_batch_tune(Bt)
+    for t in tids:
+        ct.ct_batch_remove(Bt, t)
+    del Bt
+    t_tune = time.perf_counter() - t_tune
+
+    def set_shapes(batch):
+        for kind, t in enumerate(shapes):
+            if t is not None:
+                ct.ct_batch_set_tuning(batch, kind, t["fwd_split"], t["back_waves"])
+
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
 
@@ -349,6 +374,7 @@ def run_batch(args):
     torch.cuda.synchronize()
     start.record()
     B = ct.ct_batch_create(n_jobs)
+    set_shapes(B)
     for j in jobs:
         ct.ct_batch_add(B, j["sol"], j["sched"], j["y"], j["x"])
     for e in range(E):
@@ -362,6 +388,7 @@ def run_batch(args):
     # per-kernel replay of the batched epochs with events
     reset_all()
     B2 = ct.ct_batch_create(n_jobs)
+    set_shapes(B2)
     for j in jobs:
         ct.ct_batch_add(B2, j["sol"], j["sched"], j["y"], j["x"])
     ct.ct_batch_profile(B2, True)
@@ -375,7 +402,10 @@ def run_batch(args):
         "workload": (f"{n_jobs} fan2d_curved slices, N drawn from {list(BATCH_SIZES)} (seed 4000), "
                      "pixel 256/N mm, 1.5N views/360deg, 1.5N bins over 0.768 rad, 4 view groups x "
                      "4 quadrants, alpha 1, s 2, b 1, 1% noise, epochs = steps"),
-        "sizes": sizes, "total_updates": total_updates, "setup_s": round(t_setup, 3)}
+        "sizes": sizes, "total_updates": total_updates, "setup_s": round(t_setup, 3),
+        "launch_shapes": {("par2d", "fan2d_flat", "fan2d_curved", "cone3d")[k]: t for k, t in enumerate(shapes)
+                          if t is not None},
+        "tune_s": round(t_tune, 3)}
     out["jobs_per_s"] = n_jobs / (ms_batch * 1e-3)
     out["plain"] = {"value": total_updates / (ms_plain * 1e-3), "ms": ms_plain,
                     "jobs_per_s": n_jobs / (ms_plain * 1e-3),

@@ -312,6 +312,54 @@ int ct_batch_job_epoch(const ct_batch* batch, int32_t id, int32_t* epoch);
 int ct_batch_profile(ct_batch* batch, int32_t enable);
 int ct_batch_profile_read(ct_batch* batch, ct_kernel_times* out);
 
+/* ---- launch shapes and their tuner ------------------------------------------
+ * Two launch-shape choices of the projectors leave what is computed unchanged
+ * (only the order of float32 sums moves): how many pieces each chord of the
+ * fused forward pass is walked in (fwd_split: 1, 2 or 4 waves per 64 rays),
+ * and how many waves share the views of a 2D back-projection tile
+ * (back_waves: 1, 2 or 4; the 3D tile always takes 4).  They are not steps
+ * of the method: they serve the batched and served system patterns, whose
+ * jobs range from small slices to large volumes.  Default: 4 and 4.
+ *
+ * ct_geom_tune times every shape as whole epochs of a scratch solver on the
+ * schedule's first epoch (zero data: the projectors do the same work), keeps
+ * the fastest for the geometry, and caches the table of times per (geometry
+ * kind, voxels per column block and rays per row block rounded to powers of
+ * two, GPU architecture), so later geometries of that size class are not
+ * timed again.  It allocates scratch device memory (a solver workspace, y
+ * and x) for the length of the call and synchronises the stream.  Calls that
+ * use the geometry must not run meanwhile.  Errors: CT_EINVAL (NULL, unknown
+ * flags, a schedule of another geometry, a shape outside the sets above),
+ * CT_EDEVICE. */
+typedef struct ct_tuning {
+    int32_t fwd_split;
+    int32_t back_waves;
+    double ms;                  /* tuner: mean epoch time of the chosen shape */
+    double ms_default;          /* tuner: the same for the default shape */
+    int32_t trials;             /* shapes timed by this call (0: from the cache) */
+    int32_t cached;             /* 1: the times came from the cache */
+} ct_tuning;
+
+enum { CT_TUNE_REFRESH = 1 };   /* time again even if the size class is cached */
+
+/* Set / read the shapes a geometry's launches use (solver steps and the
+ * back-projection primitive). */
+int ct_geom_set_tuning(ct_geom* geom, const ct_tuning* t);
+int ct_geom_get_tuning(const ct_geom* geom, ct_tuning* t);
+int ct_geom_tune(ct_geom* geom, const ct_schedule* sched, int32_t flags, ct_tuning* out,
+                 void* stream);
+
+/* For each geometry kind among a batch's jobs, the shape whose epoch times
+ * summed over those jobs (each from its size class, timed as above if not
+ * cached) are smallest.  The jobs' geometries take it too, so that a job run
+ * alone reproduces its batch results bit for bit.  out: ct_tuning[4] indexed
+ * by kind (zeros for kinds no job has), may be NULL.  The batch's captured
+ * graph is dropped (the shapes are part of it). */
+int ct_batch_tune(ct_batch* batch, int32_t flags, ct_tuning* out, void* stream);
+/* Set the shapes of one kind's batched launches (the jobs' geometries are not
+ * changed). */
+int ct_batch_set_tuning(ct_batch* batch, int32_t kind, const ct_tuning* t);
+
 /* ---- serving ---------------------------------------------------------------
  * A request loop over a batch (continuous batching): jobs are submitted with
  * their geometry, schedule parameters and measurements, wait in a FIFO queue,

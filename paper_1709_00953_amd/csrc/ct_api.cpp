@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -74,6 +75,7 @@ struct ct_geom {
     Entry* d_all = nullptr;
     unsigned long long* d_nnz = nullptr;
     Box* d_boxes = nullptr;            // [n]
+    Tune tune{};                       // launch shapes of the projectors (tuner or caller)
 };
 
 static void box_tiling(const ct_geom* g, const Box& b, int* tx, int* ty, int* tz) {
@@ -701,7 +703,7 @@ extern "C" int ct_block_back(ct_geom* g, const int32_t* rbs, int32_t n_rb, int32
         a.fused = 0;
         a.r = r;
         a.g = gout;
-        HIPCHK(launch_back(g->G, a, 1, st));
+        HIPCHK(launch_back(g->G, a, 1, g->tune.waves, st));
     }
     return CT_OK;
 }
@@ -1450,7 +1452,7 @@ static int enqueue_step(ct_solver* s, const ct_schedule* sc, int c, const float*
     b.vox_J = vox_J;
     b.xg_stride = xg_size(box.x1 - box.x0, box.y1 - box.y0, box.z1 - box.z0);
     b.partial = s->pg;
-    HIPCHK(timed(s, CT_K_BACK, st, [&] { return launch_back(g->G, b, nG, st); }));
+    HIPCHK(timed(s, CT_K_BACK, st, [&] { return launch_back(g->G, b, nG, g->tune.waves, st); }));
 
     FwdArgs f{};
     f.box = box;
@@ -1458,6 +1460,7 @@ static int enqueue_step(ct_solver* s, const ct_schedule* sc, int c, const float*
     f.n_ent = n_ent;
     f.n_chunks = n_chunks;
     f.mode = 1;
+    f.split = g->tune.split;
     f.windowed = 1;
     f.col = J;
     f.xg = s->xg;
@@ -1673,6 +1676,7 @@ struct ct_batch {
     hipGraphExec_t exec = nullptr;
     bool graph_valid = false;
     Prof prof;
+    Tune tune[4]{};                 // launch shapes per geometry kind
 };
 
 static BJob make_bjob(const BatchSlot& b) {
@@ -1839,7 +1843,9 @@ static int batch_enqueue(ct_batch* b, hipStream_t st) {
     static const int kind_of_phase[] = {CT_K_BACK, CT_K_FWD, CT_K_STEP, CT_K_FINALIZE, CT_K_RESIDUAL};
     for (const BatchLaunch& L : b->launches)
         HIPCHK(b->prof.timed(kind_of_phase[L.phase], st,
-                             [&] { return launch_batch(L.phase, L.kind, batch_args(b, &L), L.blocks, st); }));
+                             [&] {
+                                 return launch_batch(L.phase, L.kind, batch_args(b, &L), L.blocks, b->tune[L.kind], st);
+                             }));
     HIPCHK(launch_batch_advance(batch_args(b, nullptr), st));
     return CT_OK;
 }
@@ -1974,6 +1980,235 @@ extern "C" int ct_batch_epoch(ct_batch* b, int32_t flags, int32_t* ran, void* st
     }
     for (BatchSlot& j : b->jobs)
         if (j.next < j.n_epochs) ++j.next;
+    return CT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launch shapes and their tuner
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kShapes = 3;
+constexpr int kShapeVal[kShapes] = {1, 2, 4};
+constexpr int kTuneReps = 3;
+
+struct TuneTable {
+    double ms[kShapes][kShapes];    // [pieces per chord][waves per tile]; < 0: not a candidate
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneTable> g_tune_cache;
+
+int shape_index(int v) {
+    for (int i = 0; i < kShapes; ++i)
+        if (kShapeVal[i] == v) return i;
+    return -1;
+}
+}  // namespace
+
+static int check_shape(int dims, int split, int waves) {
+    if (shape_index(split) < 0) return fail(CT_EINVAL, "fwd_split must be 1, 2 or 4 (got %d)", split);
+    if (shape_index(waves) < 0) return fail(CT_EINVAL, "back_waves must be 1, 2 or 4 (got %d)", waves);
+    if (dims == 3 && waves != 4) return fail(CT_EINVAL, "the 3D back-projection tile takes 4 waves");
+    return CT_OK;
+}
+
+// size class: kind, voxels per column block and rays per row block rounded to
+// powers of two, GPU architecture
+static std::string tune_key(const ct_geom* g) {
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, g->device) != hipSuccess) prop.gcnArchName[0] = '\0';
+    const double vox = (double)g->N / std::max(1, g->n), rays = (double)g->M / std::max(1, g->m);
+    char buf[320];
+    snprintf(buf, sizeof buf, "%d/%ld/%ld/%s", g->d.kind, std::lround(std::log2(std::max(1.0, vox))),
+             std::lround(std::log2(std::max(1.0, rays))), prop.gcnArchName);
+    return buf;
+}
+
+// Time every shape as kTuneReps epochs (after one untimed) of a scratch solver
+// on the schedule's first epoch.
+static int tune_measure(ct_geom* g, const ct_schedule* sc, TuneTable* t, hipStream_t st) {
+    if (sc->ecp.size() < 2) return fail(CT_EINVAL, "the schedule has no epoch");
+    const ct_solver_params p{CT_SYNC_COLUMN};
+    size_t wsb = 0;
+    int rc = ct_solver_workspace_bytes(g, &p, &wsb);
+    if (rc) return rc;
+    void* ws = nullptr;
+    float *y = nullptr, *x = nullptr;
+    ct_solver* s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const Tune keep = g->tune;
+    hipError_t e = hipMalloc(&ws, wsb);
+    if (e == hipSuccess) e = hipMalloc((void**)&y, (size_t)g->M * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void**)&x, (size_t)g->N * sizeof(float));
+    if (e == hipSuccess) e = hipMemsetAsync(y, 0, (size_t)g->M * sizeof(float), st);
+    if (e == hipSuccess) e = hipMemsetAsync(x, 0, (size_t)g->N * sizeof(float), st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) rc = fail(CT_EDEVICE, "tuner scratch: %s", hipGetErrorString(e));
+    if (!rc) rc = ct_solver_create(g, &p, ws, wsb, &s);
+    if (!rc) rc = ct_solver_reset(s, y, nullptr, st);
+    for (int i = 0; i < kShapes && !rc; ++i) {
+        for (int j = 0; j < kShapes && !rc; ++j) {
+            t->ms[i][j] = -1.0;
+            if (g->dims == 3 && kShapeVal[j] != 4) continue;
+            g->tune.split = kShapeVal[i];
+            g->tune.waves = kShapeVal[j];
+            rc = ct_block_epoch(s, sc, 0, y, x, st);
+            if (!rc && (e = hipEventRecord(e0, st)) != hipSuccess) rc = fail(CT_EDEVICE, "%s", hipGetErrorString(e));
+            for (int r = 0; r < kTuneReps && !rc; ++r) rc = ct_block_epoch(s, sc, 0, y, x, st);
+            if (!rc && (e = hipEventRecord(e1, st)) != hipSuccess) rc = fail(CT_EDEVICE, "%s", hipGetErrorString(e));
+            if (!rc && (e = hipEventSynchronize(e1)) != hipSuccess) rc = fail(CT_EDEVICE, "%s", hipGetErrorString(e));
+            float ms = 0.f;
+            if (!rc && (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) rc = fail(CT_EDEVICE, "%s", hipGetErrorString(e));
+            if (!rc) t->ms[i][j] = (double)ms / kTuneReps;
+        }
+    }
+    g->tune = keep;
+    if (s) ct_solver_destroy(s);
+    (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (x) (void)hipFree(x);
+    if (y) (void)hipFree(y);
+    if (ws) (void)hipFree(ws);
+    return rc;
+}
+
+// The table of a geometry's size class: from the cache, or timed (and cached).
+static int tune_table(ct_geom* g, const ct_schedule* sc, bool refresh, TuneTable* t, bool* cached,
+                      hipStream_t st) {
+    const std::string key = tune_key(g);
+    if (!refresh) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *t = it->second;
+            *cached = true;
+            return CT_OK;
+        }
+    }
+    int rc = tune_measure(g, sc, t, st);
+    if (rc) return rc;
+    *cached = false;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = *t;
+    return CT_OK;
+}
+
+static void tune_pick(const double (&ms)[kShapes][kShapes], int* bi, int* bj) {
+    *bi = shape_index(kSplit);
+    *bj = shape_index(4);
+    for (int i = 0; i < kShapes; ++i)
+        for (int j = 0; j < kShapes; ++j)
+            if (ms[i][j] >= 0 && (ms[*bi][*bj] < 0 || ms[i][j] < ms[*bi][*bj])) {
+                *bi = i;
+                *bj = j;
+            }
+}
+
+extern "C" int ct_geom_set_tuning(ct_geom* g, const ct_tuning* t) {
+    if (!g || !t) return fail(CT_EINVAL, "NULL argument");
+    int rc = check_shape(g->dims, t->fwd_split, t->back_waves);
+    if (rc) return rc;
+    g->tune.split = t->fwd_split;
+    g->tune.waves = t->back_waves;
+    return CT_OK;
+}
+
+extern "C" int ct_geom_get_tuning(const ct_geom* g, ct_tuning* t) {
+    if (!g || !t) return fail(CT_EINVAL, "NULL argument");
+    std::memset(t, 0, sizeof *t);
+    t->fwd_split = g->tune.split;
+    t->back_waves = g->tune.waves;
+    return CT_OK;
+}
+
+extern "C" int ct_geom_tune(ct_geom* g, const ct_schedule* sc, int32_t flags, ct_tuning* out, void* stream) {
+    if (!g || !sc) return fail(CT_EINVAL, "NULL argument");
+    if (flags & ~CT_TUNE_REFRESH) return fail(CT_EINVAL, "unknown flags 0x%x", flags);
+    if (sc->geom != g) return fail(CT_EINVAL, "schedule was built for another geometry");
+    int rc = check_device(g);
+    if (rc) return rc;
+    TuneTable t{};
+    bool cached = false;
+    if ((rc = tune_table(g, sc, (flags & CT_TUNE_REFRESH) != 0, &t, &cached, (hipStream_t)stream))) return rc;
+    int bi, bj;
+    tune_pick(t.ms, &bi, &bj);
+    g->tune.split = kShapeVal[bi];
+    g->tune.waves = kShapeVal[bj];
+    if (out) {
+        std::memset(out, 0, sizeof *out);
+        out->fwd_split = g->tune.split;
+        out->back_waves = g->tune.waves;
+        out->ms = t.ms[bi][bj];
+        out->ms_default = t.ms[shape_index(kSplit)][shape_index(4)];
+        out->cached = cached ? 1 : 0;
+        if (!cached)
+            for (int i = 0; i < kShapes; ++i)
+                for (int j = 0; j < kShapes; ++j) out->trials += t.ms[i][j] >= 0 ? 1 : 0;
+    }
+    return CT_OK;
+}
+
+extern "C" int ct_batch_tune(ct_batch* b, int32_t flags, ct_tuning* out, void* stream) {
+    if (!b) return fail(CT_EINVAL, "NULL argument");
+    if (flags & ~CT_TUNE_REFRESH) return fail(CT_EINVAL, "unknown flags 0x%x", flags);
+    if (out) std::memset(out, 0, 4 * sizeof *out);
+    double tot[4][kShapes][kShapes] = {};
+    bool have[4] = {false, false, false, false};
+    int trials[4] = {0, 0, 0, 0}, all_cached[4] = {1, 1, 1, 1};
+    std::vector<std::string> refreshed;
+    for (const BatchSlot& j : b->jobs) {
+        ct_geom* g = j.job.solver->geom;
+        const ct_schedule* sc = j.job.sched;
+        int rc = check_device(g);
+        if (rc) return rc;
+        const std::string key = tune_key(g);
+        const bool refresh = (flags & CT_TUNE_REFRESH) &&
+                             std::find(refreshed.begin(), refreshed.end(), key) == refreshed.end();
+        TuneTable t{};
+        bool cached = false;
+        if ((rc = tune_table(g, sc, refresh, &t, &cached, (hipStream_t)stream))) return rc;
+        if (refresh) refreshed.push_back(key);
+        const int k = g->d.kind;
+        for (int i = 0; i < kShapes; ++i)
+            for (int q = 0; q < kShapes; ++q) {
+                if (!have[k]) tot[k][i][q] = t.ms[i][q];
+                else if (t.ms[i][q] < 0 || tot[k][i][q] < 0) tot[k][i][q] = -1.0;
+                else tot[k][i][q] += t.ms[i][q];
+                if (!cached && t.ms[i][q] >= 0) ++trials[k];
+            }
+        if (!cached) all_cached[k] = 0;
+        have[k] = true;
+    }
+    for (int k = 0; k < 4; ++k) {
+        if (!have[k]) continue;
+        int bi, bj;
+        tune_pick(tot[k], &bi, &bj);
+        b->tune[k].split = kShapeVal[bi];
+        b->tune[k].waves = kShapeVal[bj];
+        if (out) {
+            out[k].fwd_split = kShapeVal[bi];
+            out[k].back_waves = kShapeVal[bj];
+            out[k].ms = tot[k][bi][bj];
+            out[k].ms_default = tot[k][shape_index(kSplit)][shape_index(4)];
+            out[k].trials = trials[k];
+            out[k].cached = all_cached[k];
+        }
+    }
+    for (BatchSlot& j : b->jobs) j.job.solver->geom->tune = b->tune[j.job.solver->geom->d.kind];
+    batch_drop_graph(b);
+    return CT_OK;
+}
+
+extern "C" int ct_batch_set_tuning(ct_batch* b, int32_t kind, const ct_tuning* t) {
+    if (!b || !t) return fail(CT_EINVAL, "NULL argument");
+    if (kind < 0 || kind > 3) return fail(CT_EINVAL, "unknown kind %d", kind);
+    int rc = check_shape(kind == CT_CONE3D_FLAT ? 3 : 2, t->fwd_split, t->back_waves);
+    if (rc) return rc;
+    b->tune[kind].split = t->fwd_split;
+    b->tune[kind].waves = t->back_waves;
+    batch_drop_graph(b);
     return CT_OK;
 }
 

@@ -130,6 +130,7 @@ struct FwdCore {
     unsigned long long* nnz;      // count: [m][n]
     int32_t n_cols, col;          // count: column count and this column
     double tau;                   // count threshold
+    int32_t split = kSplit;       // fused: pieces per chord (waves per 64 rays): 1, 2 or 4
 };
 struct FwdArgs : FwdCore {
     static constexpr bool kInl = true;
@@ -278,7 +279,13 @@ enum { kPhBack = 0, kPhFwd = 1, kPhStep = 2, kPhFin = 3, kPhRes = 4 };
 int fail(int code, const char* fmt, ...);
 
 hipError_t launch_fwd(const DGeom& G, const FwdArgs& a, hipStream_t st);
-hipError_t launch_back(const DGeom& G, const BackArgs& a, int n_groups, hipStream_t st);
+// Launch-shape choices of the projectors (picked by the tuner, or set):
+// pieces per chord of the fused forward and waves per 2D back-projection tile.
+struct Tune {
+    int32_t split = kSplit;
+    int32_t waves = 4;
+};
+hipError_t launch_back(const DGeom& G, const BackArgs& a, int n_groups, int waves, hipStream_t st);
 hipError_t launch_step(const StepArgs& s, int n_groups, hipStream_t st);
 hipError_t launch_finalize(const DGeom& G, const FinArgs& f, int vox_blocks, hipStream_t st);
 hipError_t launch_residual(const DGeom& G, const ResArgs& a, int n_chunks, hipStream_t st);
@@ -286,7 +293,7 @@ hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
 // Batched phase launch: `kind` selects the projector instantiation (back and
 // forward phases); `blocks` is prefix[n_jobs].
-hipError_t launch_batch(int phase, int kind, const BatchArgs& b, int blocks, hipStream_t st);
+hipError_t launch_batch(int phase, int kind, const BatchArgs& b, int blocks, const Tune& t, hipStream_t st);
 hipError_t launch_batch_advance(const BatchArgs& b, hipStream_t st);
 hipError_t launch_sum_pairs(const double* part, int nblk, double* out, hipStream_t st);
 hipError_t launch_resnorm(const float* y, const float* p, int64_t n, double* part, int nblk,

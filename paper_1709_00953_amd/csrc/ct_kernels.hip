@@ -171,7 +171,7 @@ __device__ __forceinline__ double strided_sum256(const double* p, int lo, int hi
 }
 
 // Forward work-group `bid` of a launch (chunk bid of the entries' rays).
-template <int KIND, int MODE, class FA>
+template <int KIND, int MODE, class FA, int KS = kSplit>
 __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int bid) {
     constexpr int DIMS = (KIND == kCone) ? 3 : 2;
     constexpr bool DIVERGENT = (KIND != kPar2D);
@@ -179,7 +179,7 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
     // the count mode needs whole segment lengths, so it walks each ray in one
     // piece, and in float64: it decides length > tau, and a float32 walk gives
     // a touch of a voxel corner (length 0) lengths of about 1e-7 of the chord
-    constexpr int K = (MODE == 2) ? 1 : kSplit;
+    constexpr int K = (MODE == 2) ? 1 : KS;
     using WT = typename std::conditional<MODE == 2, double, float>::type;
     __shared__ float pacc[K][kChunk], pacc2[K][kChunk];
 
@@ -429,9 +429,9 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
     }
 }
 
-template <int KIND, int MODE>
+template <int KIND, int MODE, int KS = kSplit>
 __global__ __launch_bounds__(256) void k_fwd(DGeom G, FwdCore a) {
-    fwd_body<KIND, MODE>(G, a, blockIdx.x);
+    fwd_body<KIND, MODE, FwdCore, KS>(G, a, blockIdx.x);
 }
 
 template <int KIND>
@@ -542,11 +542,12 @@ __device__ __forceinline__ void view_params(const DGeom& G, const Tile& tl, doub
     P.W = (float)fmin(W, 1e9) + 2e-3f + 1e-6f * fabsf((float)bc);
 }
 
-// Back-projection work-group for tile `tile` (of n_tiles) of group gi.
-template <int KIND, class BA>
+// Back-projection work-group for tile `tile` (of n_tiles) of group gi: NW
+// waves, each over every NW-th view of the group (NW is a tuning choice).
+template <int KIND, class BA, int NW = 4>
 __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const int gi, const int tile,
                                            const int n_tiles) {
-    __shared__ ViewP vp[4][64];
+    __shared__ ViewP vp[NW][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wu = __builtin_amdgcn_readfirstlane(w);
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
@@ -576,9 +577,9 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
     }
 
     float acc = 0.f;
-    for (int base = 0; base < nt; base += 256) {
-        // lane `lane` of wave `w` prepares the view with flat index base + 4 lane + w
-        const int f = base + 4 * lane + w;
+    for (int base = 0; base < nt; base += 64 * NW) {
+        // lane `lane` of wave `w` prepares the view with flat index base + NW lane + w
+        const int f = base + NW * lane + w;
         if (f < nt) {
             int e = e0, off = f;
             for (;;) {
@@ -594,7 +595,7 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
             }
         }
         __syncthreads();
-        const int nb = min(64, (nt - base - wu + 3) / 4);
+        const int nb = min(64, (nt - base - wu + NW - 1) / NW);
         if (valid) {
             for (int j = 0; j < nb; ++j) {
                 const ViewP& P = vp[wu][j];
@@ -637,11 +638,17 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
     }
 
     // the four waves' partial sums, added in a fixed order
-    // the view parameters are dead here: their LDS holds the partial sums
-    float* red = reinterpret_cast<float*>(&vp[0][0]);
-    red[w * 64 + lane] = acc;
-    __syncthreads();
-    const float gsum = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
+    // the waves' partial sums in a fixed order; the view parameters are dead
+    // here and their LDS holds them
+    float gsum = acc;
+    if constexpr (NW > 1) {
+        float* red = reinterpret_cast<float*>(&vp[0][0]);
+        red[w * 64 + lane] = acc;
+        __syncthreads();
+        gsum = red[lane];
+#pragma unroll
+        for (int k = 1; k < NW; ++k) gsum += red[64 * k + lane];
+    }
     const int nxJ = a.box.x1 - a.box.x0;
     if (a.fused) {
         if (w == 0) {
@@ -662,11 +669,12 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
     }
 }
 
-// 20 KB of LDS and at most 64 VGPRs: eight work-groups per CU, so a launch of
-// 2048 tiles (four groups of a 128 x 256 block) is resident in one round
-template <int KIND, class BA>
-__global__ __launch_bounds__(256, 8) void k_back2(DGeom G, BA a) {
-    back2_body<KIND>(G, a, blockIdx.y, blockIdx.x, gridDim.x);
+// At most 64 VGPRs (eight waves per SIMD); with four waves, 20 KB of LDS:
+// eight work-groups per CU, so a launch of 2048 tiles (four groups of a
+// 128 x 256 block) is resident in one round
+template <int KIND, class BA, int NW>
+__global__ __launch_bounds__(64 * NW, 8) void k_back2(DGeom G, BA a) {
+    back2_body<KIND, BA, NW>(G, a, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // ----------------------------------------------------------------------------
@@ -1170,9 +1178,10 @@ __device__ __forceinline__ int box_vox(const Box& b) {
     return (b.x1 - b.x0) * (b.y1 - b.y0) * (b.z1 - b.z0);
 }
 
-// occupancy as the single-job kernels: eight waves per SIMD in 2D, four in 3D
-template <int KIND>
-__global__ __launch_bounds__(256, KIND == kCone ? 4 : 8) void kb_back(BatchArgs B) {
+// occupancy as the single-job kernels: eight waves per SIMD in 2D, four in 3D;
+// NW waves per 2D tile (the 3D tile always takes four)
+template <int KIND, int NW>
+__global__ __launch_bounds__(64 * NW, KIND == kCone ? 4 : 8) void kb_back(BatchArgs B) {
     const int k = batch_job(B, blockIdx.x);
     const int L = blockIdx.x - B.prefix[k];
     const BJob J = cld(B.jobs, k);
@@ -1196,10 +1205,10 @@ __global__ __launch_bounds__(256, KIND == kCone ? 4 : 8) void kb_back(BatchArgs 
     a.xg_stride = xg_size(a.box.x1 - a.box.x0, a.box.y1 - a.box.y0, a.box.z1 - a.box.z0);
     a.partial = J.pg;
     if constexpr (KIND == kCone) back3_body(G, a, gi, tile, nt);
-    else back2_body<KIND>(G, a, gi, tile, nt);
+    else back2_body<KIND, BackCore, NW>(G, a, gi, tile, nt);
 }
 
-template <int KIND>
+template <int KIND, int KS>
 __global__ __launch_bounds__(256) void kb_fwd(BatchArgs B) {
     const int k = batch_job(B, blockIdx.x);
     const int L = blockIdx.x - B.prefix[k];
@@ -1222,7 +1231,7 @@ __global__ __launch_bounds__(256) void kb_fwd(BatchArgs B) {
     a.out = J.z + (size_t)sr.col * (size_t)J.M;
     a.q = J.q;
     a.partial = J.pq;
-    fwd_body<KIND, 1>(G, a, L);
+    fwd_body<KIND, 1, FwdCore, KS>(G, a, L);
 }
 
 __global__ __launch_bounds__(256) void kb_step(BatchArgs B) {
@@ -1365,15 +1374,15 @@ __global__ __launch_bounds__(256) void k_sum_pairs(const double* part, int nblk,
 // ----------------------------------------------------------------------------
 // host-side launchers (internal linkage for the API file)
 // ----------------------------------------------------------------------------
-template <int MODE>
+template <int MODE, int KS = kSplit>
 static hipError_t launch_fwd_mode(const DGeom& G, const FwdArgs& a, hipStream_t st) {
-    dim3 grid(a.n_chunks), block(MODE == 2 ? kChunk : kChunk * kSplit);
+    dim3 grid(a.n_chunks), block(MODE == 2 ? kChunk : kChunk * KS);
     const FwdCore c = a;
     switch (G.kind) {
-        case kPar2D: hipLaunchKernelGGL((k_fwd<kPar2D, MODE>), grid, block, 0, st, G, c); break;
-        case kFanFlat: hipLaunchKernelGGL((k_fwd<kFanFlat, MODE>), grid, block, 0, st, G, c); break;
-        case kFanCurved: hipLaunchKernelGGL((k_fwd<kFanCurved, MODE>), grid, block, 0, st, G, c); break;
-        default: hipLaunchKernelGGL((k_fwd<kCone, MODE>), grid, block, 0, st, G, c); break;
+        case kPar2D: hipLaunchKernelGGL((k_fwd<kPar2D, MODE, KS>), grid, block, 0, st, G, c); break;
+        case kFanFlat: hipLaunchKernelGGL((k_fwd<kFanFlat, MODE, KS>), grid, block, 0, st, G, c); break;
+        case kFanCurved: hipLaunchKernelGGL((k_fwd<kFanCurved, MODE, KS>), grid, block, 0, st, G, c); break;
+        default: hipLaunchKernelGGL((k_fwd<kCone, MODE, KS>), grid, block, 0, st, G, c); break;
     }
     return hipGetLastError();
 }
@@ -1396,31 +1405,49 @@ hipError_t launch_fwd(const DGeom& G, const FwdArgs& a, hipStream_t st) {
         return launch_fwd_inline(G, a, st);
     }
     if (a.mode == 0) return launch_fwd_mode<0>(G, a, st);
-    if (a.mode == 1) return launch_fwd_mode<1>(G, a, st);
+    if (a.mode == 1) {
+        // pieces per chord: a tuning choice of the fused step
+        if (a.split == 1) return launch_fwd_mode<1, 1>(G, a, st);
+        if (a.split == 2) return launch_fwd_mode<1, 2>(G, a, st);
+        if (a.split == 4) return launch_fwd_mode<1, 4>(G, a, st);
+        return hipErrorInvalidValue;
+    }
     return launch_fwd_mode<2>(G, a, st);
 }
 
-hipError_t launch_back(const DGeom& G, const BackArgs& a, int n_groups, hipStream_t st) {
+template <class BA, int NW>
+static void launch_back2(const DGeom& G, const BA& a, dim3 grid, hipStream_t st) {
+    const dim3 block(64 * NW);
+    switch (G.kind) {
+        case kPar2D: hipLaunchKernelGGL((k_back2<kPar2D, BA, NW>), grid, block, 0, st, G, a); break;
+        case kFanFlat: hipLaunchKernelGGL((k_back2<kFanFlat, BA, NW>), grid, block, 0, st, G, a); break;
+        default: hipLaunchKernelGGL((k_back2<kFanCurved, BA, NW>), grid, block, 0, st, G, a); break;
+    }
+}
+
+template <class BA>
+static hipError_t launch_back_as(const DGeom& G, const BA& a, int n_groups, int waves, hipStream_t st) {
     const int nt = a.tiles_x * a.tiles_y * a.tiles_z;
     if (nt <= 0 || n_groups <= 0) return hipSuccess;
-    dim3 grid(nt, n_groups), block(256);
-    if (!a.ent) {
-        switch (G.kind) {
-            case kPar2D: hipLaunchKernelGGL((k_back2<kPar2D, BackArgs>), grid, block, 0, st, G, a); break;
-            case kFanFlat: hipLaunchKernelGGL((k_back2<kFanFlat, BackArgs>), grid, block, 0, st, G, a); break;
-            case kFanCurved: hipLaunchKernelGGL((k_back2<kFanCurved, BackArgs>), grid, block, 0, st, G, a); break;
-            default: hipLaunchKernelGGL(k_back3<BackArgs>, grid, block, 0, st, G, a); break;
-        }
-        return hipGetLastError();
-    }
-    const BackCore c = a;
-    switch (G.kind) {
-        case kPar2D: hipLaunchKernelGGL((k_back2<kPar2D, BackCore>), grid, block, 0, st, G, c); break;
-        case kFanFlat: hipLaunchKernelGGL((k_back2<kFanFlat, BackCore>), grid, block, 0, st, G, c); break;
-        case kFanCurved: hipLaunchKernelGGL((k_back2<kFanCurved, BackCore>), grid, block, 0, st, G, c); break;
-        default: hipLaunchKernelGGL(k_back3<BackCore>, grid, block, 0, st, G, c); break;
+    const dim3 grid(nt, n_groups);
+    if (G.kind == kCone) {
+        hipLaunchKernelGGL(k_back3<BA>, grid, dim3(256), 0, st, G, a);
+    } else if (waves == 1) {
+        launch_back2<BA, 1>(G, a, grid, st);
+    } else if (waves == 2) {
+        launch_back2<BA, 2>(G, a, grid, st);
+    } else if (waves == 4) {
+        launch_back2<BA, 4>(G, a, grid, st);
+    } else {
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_back(const DGeom& G, const BackArgs& a, int n_groups, int waves, hipStream_t st) {
+    if (!a.ent) return launch_back_as<BackArgs>(G, a, n_groups, waves, st);
+    const BackCore c = a;
+    return launch_back_as<BackCore>(G, c, n_groups, waves, st);
 }
 
 hipError_t launch_step(const StepArgs& s, int n_groups, hipStream_t st) {
@@ -1443,22 +1470,37 @@ hipError_t launch_residual(const DGeom& G, const ResArgs& a, int n_chunks, hipSt
 }
 
 template <int KIND>
-static hipError_t launch_batch_kind(int phase, const BatchArgs& b, int blocks, hipStream_t st) {
-    if (phase == kPhBack) hipLaunchKernelGGL(kb_back<KIND>, dim3(blocks), dim3(256), 0, st, b);
-    else hipLaunchKernelGGL(kb_fwd<KIND>, dim3(blocks), dim3(kChunk * kSplit), 0, st, b);
+static hipError_t launch_batch_kind(int phase, const BatchArgs& b, int blocks, const Tune& t,
+                                    hipStream_t st) {
+    const dim3 grid(blocks);
+    if (phase == kPhBack) {
+        if constexpr (KIND == kCone) {
+            hipLaunchKernelGGL((kb_back<KIND, 4>), grid, dim3(256), 0, st, b);
+        } else {
+            if (t.waves == 1) hipLaunchKernelGGL((kb_back<KIND, 1>), grid, dim3(64), 0, st, b);
+            else if (t.waves == 2) hipLaunchKernelGGL((kb_back<KIND, 2>), grid, dim3(128), 0, st, b);
+            else if (t.waves == 4) hipLaunchKernelGGL((kb_back<KIND, 4>), grid, dim3(256), 0, st, b);
+            else return hipErrorInvalidValue;
+        }
+    } else {
+        if (t.split == 1) hipLaunchKernelGGL((kb_fwd<KIND, 1>), grid, dim3(kChunk), 0, st, b);
+        else if (t.split == 2) hipLaunchKernelGGL((kb_fwd<KIND, 2>), grid, dim3(2 * kChunk), 0, st, b);
+        else if (t.split == 4) hipLaunchKernelGGL((kb_fwd<KIND, 4>), grid, dim3(4 * kChunk), 0, st, b);
+        else return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_batch(int phase, int kind, const BatchArgs& b, int blocks, hipStream_t st) {
+hipError_t launch_batch(int phase, int kind, const BatchArgs& b, int blocks, const Tune& t, hipStream_t st) {
     if (blocks <= 0) return hipSuccess;
     switch (phase) {
         case kPhBack:
         case kPhFwd:
             switch (kind) {
-                case kPar2D: return launch_batch_kind<kPar2D>(phase, b, blocks, st);
-                case kFanFlat: return launch_batch_kind<kFanFlat>(phase, b, blocks, st);
-                case kFanCurved: return launch_batch_kind<kFanCurved>(phase, b, blocks, st);
-                default: return launch_batch_kind<kCone>(phase, b, blocks, st);
+                case kPar2D: return launch_batch_kind<kPar2D>(phase, b, blocks, t, st);
+                case kFanFlat: return launch_batch_kind<kFanFlat>(phase, b, blocks, t, st);
+                case kFanCurved: return launch_batch_kind<kFanCurved>(phase, b, blocks, t, st);
+                default: return launch_batch_kind<kCone>(phase, b, blocks, t, st);
             }
         case kPhStep: hipLaunchKernelGGL(kb_step, dim3(blocks), dim3(256), 0, st, b); break;
         case kPhFin: hipLaunchKernelGGL(kb_finalize, dim3(blocks), dim3(256), 0, st, b); break;

@@ -23,6 +23,7 @@ CT_ACCUMULATE = 1
 CT_SAMPLE_DENSITY, CT_SAMPLE_UNIFORM, CT_SAMPLE_MIXED = 0, 1, 2
 CT_SYNC_COLUMN, CT_SYNC_EPOCH = 0, 1
 CT_BATCH_GRAPH = 1
+CT_TUNE_REFRESH = 1
 
 EXPORTS = (
     "ct_geom_create", "ct_geom_destroy", "ct_geom_get_info", "ct_geom_block_nnz",
@@ -34,6 +35,7 @@ EXPORTS = (
     "ct_solver_profile", "ct_solver_profile_read",
     "ct_batch_create", "ct_batch_destroy", "ct_batch_add", "ct_batch_remove", "ct_batch_epoch",
     "ct_batch_job_epoch", "ct_batch_profile", "ct_batch_profile_read",
+    "ct_geom_set_tuning", "ct_geom_get_tuning", "ct_geom_tune", "ct_batch_tune", "ct_batch_set_tuning",
     "ct_server_create", "ct_server_destroy", "ct_server_submit", "ct_server_tick", "ct_server_poll",
     "ct_server_result", "ct_job_footprint",
     "ct_last_error",
@@ -110,6 +112,11 @@ class ct_server_stats(ctypes.Structure):
                 ("updates", i64), ("bytes_in_use", i64), ("budget", i64), ("now", f64)]
 
 
+class ct_tuning(ctypes.Structure):
+    _fields_ = [("fwd_split", i32), ("back_waves", i32), ("ms", f64), ("ms_default", f64),
+                ("trials", i32), ("cached", i32)]
+
+
 class ct_solve_params(ctypes.Structure):
     _fields_ = [("sched", ct_sched_params), ("solver", ct_solver_params), ("tau", f64),
                 ("rel_tol", f64), ("check_every", i32)]
@@ -169,6 +176,11 @@ def lib():
             "ct_batch_job_epoch": [P, i32, ctypes.POINTER(i32)],
             "ct_batch_profile": [P, i32],
             "ct_batch_profile_read": [P, ctypes.POINTER(ct_kernel_times)],
+            "ct_geom_set_tuning": [P, ctypes.POINTER(ct_tuning)],
+            "ct_geom_get_tuning": [P, ctypes.POINTER(ct_tuning)],
+            "ct_geom_tune": [P, P, i32, ctypes.POINTER(ct_tuning), P],
+            "ct_batch_tune": [P, i32, P, P],
+            "ct_batch_set_tuning": [P, i32, ctypes.POINTER(ct_tuning)],
             "ct_job_footprint": [ctypes.POINTER(ct_geom_desc), ctypes.POINTER(ct_solver_params),
                                  ctypes.POINTER(ctypes.c_size_t)],
             "ct_last_error": [],
@@ -531,6 +543,45 @@ def ct_batch_profile_read(batch: Batch) -> dict:
     t = ct_kernel_times()
     _check(lib().ct_batch_profile_read(batch.handle, ctypes.byref(t)))
     return {name: (float(t.ms[k]), int(t.launches[k])) for k, name in enumerate(KERNEL_NAMES)}
+
+
+# ----------------------------------------------------------------------------
+# launch shapes and their tuner
+# ----------------------------------------------------------------------------
+def _tuning_dict(t: ct_tuning) -> dict:
+    return {"fwd_split": int(t.fwd_split), "back_waves": int(t.back_waves), "ms": float(t.ms),
+            "ms_default": float(t.ms_default), "trials": int(t.trials), "cached": bool(t.cached)}
+
+
+def ct_geom_set_tuning(geom: Geom, fwd_split: int, back_waves: int):
+    t = ct_tuning(int(fwd_split), int(back_waves), 0.0, 0.0, 0, 0)
+    _check(lib().ct_geom_set_tuning(geom.handle, ctypes.byref(t)))
+
+
+def ct_geom_get_tuning(geom: Geom) -> dict:
+    t = ct_tuning()
+    _check(lib().ct_geom_get_tuning(geom.handle, ctypes.byref(t)))
+    return _tuning_dict(t)
+
+
+def ct_geom_tune(geom: Geom, sched: Schedule, refresh: bool = False, stream=None) -> dict:
+    t = ct_tuning()
+    _check(lib().ct_geom_tune(geom.handle, sched.handle, CT_TUNE_REFRESH if refresh else 0,
+                              ctypes.byref(t), _stream(stream)))
+    return _tuning_dict(t)
+
+
+def ct_batch_tune(batch: Batch, refresh: bool = False, stream=None) -> list:
+    """Per geometry kind (index = kind), the chosen shapes (None for kinds no
+    job has)."""
+    out = (ct_tuning * 4)()
+    _check(lib().ct_batch_tune(batch.handle, CT_TUNE_REFRESH if refresh else 0, out, _stream(stream)))
+    return [(_tuning_dict(out[k]) if out[k].fwd_split else None) for k in range(4)]
+
+
+def ct_batch_set_tuning(batch: Batch, kind: int, fwd_split: int, back_waves: int):
+    t = ct_tuning(int(fwd_split), int(back_waves), 0.0, 0.0, 0, 0)
+    _check(lib().ct_batch_set_tuning(batch.handle, int(kind), ctypes.byref(t)))
 
 
 # ----------------------------------------------------------------------------

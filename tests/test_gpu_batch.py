@@ -91,18 +91,33 @@ def _make_jobs(ct, specs):
     return jobs
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_batch_matches_alone(ct, graph):
+@pytest.mark.parametrize("graph,shapes", [(False, None), (True, None), (True, "tuned"), (False, "forced")])
+def test_batch_matches_alone(ct, graph, shapes):
+    """shapes: the default launch shapes; the tuner's (the jobs' geometries
+    take the batch's choice); or forced ones set on the batch and the
+    geometries alike."""
     jobs = _make_jobs(ct, JOBS)
     B = ct.ct_batch_create(len(jobs))
     ids = {}
     for j in jobs:
         sol, x = j.batched
         ids[j.name] = ct.ct_batch_add(B, sol, j.sched, j.y, x, epoch=j.first)
+    if shapes == "tuned":
+        chosen = ct.ct_batch_tune(B)
+        print(f"[batch] tuned shapes {chosen}", flush=True)
+        for j in jobs:
+            t = ct.ct_geom_get_tuning(j.G)
+            c = chosen[j.g.kind]
+            assert (t["fwd_split"], t["back_waves"]) == (c["fwd_split"], c["back_waves"])
+    elif shapes == "forced":
+        for kind in range(4):
+            ct.ct_batch_set_tuning(B, kind, 1, 4 if kind == 3 else 2)
+        for j in jobs:
+            ct.ct_geom_set_tuning(j.G, 1, 4 if j.g.kind == 3 else 2)
     done = {j.name: j.first for j in jobs}
     it = 0
     while True:
-        print(f"[batch] graph={graph} batch epoch {it}", flush=True)
+        print(f"[batch] graph={graph} shapes={shapes} batch epoch {it}", flush=True)
         ran = ct.ct_batch_epoch(B, graph=graph)
         expect = sum(1 for j in jobs if done[j.name] < j.epochs)
         assert ran == expect
@@ -196,3 +211,7 @@ def test_batch_argument_errors(ct):
         ct.ct_batch_add(B, sol, j.sched, j.y, x)
     with pytest.raises(ct.CtError):
         ct.ct_batch_create(0)
+    ct.ct_batch_set_tuning(B, 2, 1, 2)
+    for kind, split, waves in ((3, 1, 2), (4, 1, 4), (2, 3, 4), (0, 4, 8)):
+        with pytest.raises(ct.CtError):             # 3D takes 4 waves; unknown kind; bad shapes
+            ct.ct_batch_set_tuning(B, kind, split, waves)
