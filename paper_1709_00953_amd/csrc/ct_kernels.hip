@@ -161,15 +161,6 @@ __device__ __forceinline__ void ray_of(const DGeom& G, int view, int iv, int iu,
 // ----------------------------------------------------------------------------
 // K2 / K0: forward projection through box J
 // ----------------------------------------------------------------------------
-// Fixed-order float64 sum over [lo, hi) of p by 256 lanes; result in lane 0.
-__device__ __forceinline__ double strided_sum256(const double* p, int lo, int hi, double* sh) {
-    double v = 0.0;
-    for (int i = lo + (int)threadIdx.x; i < hi; i += 256) v += p[i];
-    const double t = block_sum256(v, sh);
-    __syncthreads();
-    return t;
-}
-
 // Forward work-group `bid` of a launch (chunk bid of the entries' rays).
 template <int KIND, int MODE, class FA, int KS = kSplit>
 __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int bid) {
@@ -1042,10 +1033,23 @@ __global__ __launch_bounds__(256, 4) void k_back3(DGeom G, BA a) {
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ void step_body(const StepArgs& s, const int g, const int n_groups) {
     __shared__ double sh[4];
-    const double gg = strided_sum256(s.pg, g * s.n_tiles, (g + 1) * s.n_tiles, sh);
+    // both sums' partials are read in one pass (they were written by other
+    // XCDs, so each round trip costs a memory latency); each lane still adds
+    // its elements of each sum in the same order
     const int c0 = s.ent[s.gptr[g]].chunk_prefix;
     const int c1 = (g + 1 < n_groups) ? s.ent[s.gptr[g + 1]].chunk_prefix : s.n_chunks;
-    const double qq = strided_sum256(s.pq, c0, c1, sh);
+    const int t0 = g * s.n_tiles, t1 = (g + 1) * s.n_tiles;
+    double vg = 0.0, vq = 0.0;
+    const int ng = t1 - t0, nq = c1 - c0;
+    for (int k = (int)threadIdx.x; k < max(ng, nq); k += 256) {
+        const double a = k < ng ? s.pg[t0 + k] : 0.0;
+        const double b = k < nq ? s.pq[c0 + k] : 0.0;
+        if (k < ng) vg += a;
+        if (k < nq) vq += b;
+    }
+    const double gg = block_sum256(vg, sh);
+    __syncthreads();
+    const double qq = block_sum256(vq, sh);
     if (threadIdx.x == 0) s.mu[g] = (gg > 0.0 && qq > 0.0) ? s.beta[g] * gg / qq : 0.0;
 }
 
