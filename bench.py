@@ -568,8 +568,8 @@ def run_copy(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="fan2d_512",
                     choices=["fan2d_512", "par2d_64", "cone3d_256", "fan2d_512_parallel", "paper2d_64",
                              "paper3d_128", "batch64", "serve40",
