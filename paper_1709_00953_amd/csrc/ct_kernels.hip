@@ -80,6 +80,22 @@ __device__ __forceinline__ T ldu(const T* base, unsigned i) {
 #endif
 }
 
+// Two adjacent (x, g) pairs of a J-local copy, elements i and i + 1: one
+// 16-byte load from an 8-byte aligned address.
+struct __attribute__((aligned(8))) XG2 {
+    float x0, g0, x1, g1;
+};
+__device__ __forceinline__ XG2 ld_xg2(const float2* base, unsigned i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    using GP = const __attribute__((address_space(1))) char*;
+    using GT = const __attribute__((address_space(1))) XG2*;
+    return *(GT)((GP)base + i * 8u);
+#else
+    const float2 a = base[i], b = base[i + 1];     // host pass: never executed
+    return XG2{a.x, a.y, b.x, b.y};
+#endif
+}
+
 // Entry i of a launch: inline in the kernel arguments (primitives) or in
 // device memory.  The choice is a compile-time property of the argument type
 // so that no pointer select makes the compiler copy the arguments to scratch.
@@ -182,6 +198,17 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
     const int piece = threadIdx.x / kChunk;    // which part of the chord this wave walks
     const bool active = lane < ch.cnt;
 
+    // 2D fused forward: when every ray of the chunk runs at most 45 degrees
+    // from one axis, the chunk walks slab by slab along that axis (0: x,
+    // 1: y), else (-1) segment by segment.  Uniform per wave.
+    int slab_axis = -1;
+    if constexpr (MODE == 1 && DIMS == 2) {
+        const int kk = ch.k0 + max(0, min(lane, ch.cnt - 1));
+        const Ray2F R = G.ray2f[(size_t)ch.view * G.nu + ch.u0 + kk % ch.w];
+        const unsigned long long bx = __ballot(fabs(R.dx) >= fabs(R.dy));
+        slab_axis = bx == ~0ull ? 0 : (bx == 0ull ? 1 : -1);
+    }
+
     float acc = 0.f, acc2 = 0.f;
     unsigned cnt = 0;
     int ray = 0;
@@ -254,7 +281,94 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
             }
         }
         hit = hit && (t1 > t0);
-        if (hit) {
+        bool walked = false;
+        if constexpr (MODE == 1 && DIMS == 2) {
+            if (hit && slab_axis >= 0) {
+                // Slab walk.  Along the major axis A the ray crosses one slab
+                // of voxels per step; within a slab its coordinate on the
+                // other axis B moves by at most one voxel, so it meets at
+                // most two voxels there, adjacent along B: one load of the
+                // copy whose fast axis is B fetches both.  This wave walks
+                // slabs [S0, S1) in traversal order, so the lanes of a wave
+                // read one slab row at a time.  Positions are float32 offsets
+                // from the plane of slab S0 (tau, mm along the ray) and from
+                // the voxel plane jb on B (set up in float64); a slab's length
+                // splits at the B plane between its two voxels, clamped to
+                // the slab, which also gives a single voxel all of it.
+                walked = true;
+                const int A = slab_axis, B = 1 - slab_axis;
+                const int nx = b1[0] - b0[0], ny = b1[1] - b0[1];
+                const int nA = A == 0 ? nx : ny, nB = A == 0 ? ny : nx;
+                const int Q = (nA + K - 1) / K;
+                const int S0 = __builtin_amdgcn_readfirstlane(piece) * Q, S1 = min(nA, S0 + Q);
+                const int nS = S1 - S0;                    // uniform per wave
+                if (nS > 0) {
+                    const int grp = __builtin_amdgcn_readfirstlane(en.group);
+                    const int cs = xg_copy(nx, ny, 1);
+                    const float2* xgc = uniform_ptr(a.xg + (size_t)grp * (size_t)a.xg_stride +
+                                                    (A == 0 ? (size_t)cs : (size_t)0));
+                    const double ia = h[A] * fabs(id[A]);  // mm of ray per slab
+                    const double hiA = fma((double)b1[A], h[A], org[A]);
+                    const double Cs = ((d[A] > 0.0 ? lo[A] : hiA) - o[A]) * id[A];
+                    const double tref = fma((double)S0, ia, Cs);
+                    double tlo = fmax(t0 - tref, 0.0);
+                    double thi = fmin(t1, fma((double)S1, ia, Cs)) - tref;
+                    const bool empty = !(thi > tlo);
+                    int jb = 0;
+                    float fb = 0.5f, dbf = 0.f, idb = 1e30f;
+                    if (empty) {
+                        tlo = 0.0;
+                        thi = 0.0;
+                    } else if (d[B] == 0.0) {
+                        jb = zs[B];                        // the ray stays in slab zs of B
+                    } else {
+                        const double pb = (fma(tref, d[B], o[B]) - lo[B]) * ih[B];
+                        const double fl = floor(pb);
+                        jb = (int)fl;
+                        fb = fminf((float)(pb - fl), 0x1.fffffep-1f);
+                        const double dbd = d[B] * ih[B];   // voxels of B per mm of ray
+                        dbf = (float)dbd;
+                        idb = (float)fmax(fmin(1.0 / dbd, 1e30), -1e30);
+                    }
+                    const float nfi = -fb * idb;
+                    const float ias = (float)ia, tl = (float)tlo, th = (float)thi;
+                    const bool up = d[B] >= 0.0;
+                    const int rstep = d[A] > 0.0 ? nB : -nB;
+                    // element index of (slab, jb); the padding keeps it positive
+                    int row = (d[A] > 0.0 ? S0 : nA - 1 - S0) * nB + jb + xg_pad(nx, ny, 1);
+                    float ts = tl, fs = floorf(fmaf(tl, dbf, fb)), uf = 0.f;
+                    for (int u = 0; u < nS; u += U) {
+                        int sid[U];
+                        float llo[U], lhi[U];
+#pragma unroll
+                        for (int q = 0; q < U; ++q) {
+                            // slabs past S1 get zero lengths (tau clamped to th)
+                            uf += 1.f;
+                            const float te = __builtin_amdgcn_fmed3f(uf * ias, tl, th);
+                            const float fe = floorf(fmaf(te, dbf, fb));
+                            const float lj = fminf(fs, fe);
+                            const float tc = __builtin_amdgcn_fmed3f(fmaf(lj + 1.f, idb, nfi), ts, te);
+                            const float l1 = tc - ts, l2 = te - tc;
+                            llo[q] = up ? l1 : l2;
+                            lhi[q] = up ? l2 : l1;
+                            sid[q] = row + (int)lj;
+                            row += rstep;
+                            ts = te;
+                            fs = fe;
+                        }
+#pragma unroll
+                        for (int q = 0; q < U; ++q) {
+                            const XG2 v = ld_xg2(xgc, (unsigned)sid[q]);
+                            acc = fmaf(llo[q], v.x0, acc);
+                            acc = fmaf(lhi[q], v.x1, acc);
+                            acc2 = fmaf(llo[q], v.g0, acc2);
+                            acc2 = fmaf(lhi[q], v.g1, acc2);
+                        }
+                    }
+                }
+            }
+        }
+        if (hit && !walked) {
             // this wave's piece of the chord: [t0 + p L/K, t0 + (p+1) L/K]
             const double Lc = (t1 - t0) / (double)K;
             t0 = fma((double)piece, Lc, t0);
