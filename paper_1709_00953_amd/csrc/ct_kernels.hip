@@ -330,14 +330,35 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                         dbf = (float)dbd;
                         idb = (float)fmax(fmin(1.0 / dbd, 1e30), -1e30);
                     }
+                    // the wave walks the slabs that some lane's ray overlaps: its
+                    // lanes' ranges widened by one slab (float rounding), the
+                    // union found by a uniform binary search over ballots (lanes
+                    // without overlap are neutral)
+                    int ulo = nS, uhi = 0;
+                    if (!empty) {
+                        ulo = max(0, (int)floor(tlo / ia) - 1);
+                        uhi = min(nS, (int)ceil(thi / ia) + 1);
+                    }
+                    int us = 0, ue = nS;
+                    for (int hi = nS; us < hi;) {
+                        const int mid = (us + hi) >> 1;
+                        if (__ballot(ulo <= mid)) hi = mid;
+                        else us = mid + 1;
+                    }
+                    for (int lo2 = 0; lo2 < ue;) {
+                        const int mid = (lo2 + ue) >> 1;
+                        if (__ballot(uhi > mid)) lo2 = mid + 1;
+                        else ue = mid;
+                    }
                     const float nfi = -fb * idb;
                     const float ias = (float)ia, tl = (float)tlo, th = (float)thi;
                     const bool up = d[B] >= 0.0;
                     const int rstep = d[A] > 0.0 ? nB : -nB;
-                    // element index of (slab, jb); the padding keeps it positive
-                    int row = (d[A] > 0.0 ? S0 : nA - 1 - S0) * nB + jb + xg_pad(nx, ny, 1);
-                    float ts = tl, fs = floorf(fmaf(tl, dbf, fb)), uf = 0.f;
-                    for (int u = 0; u < nS; u += U) {
+                    // element index of (slab S0 + us, jb); the padding keeps it positive
+                    int row = (d[A] > 0.0 ? S0 : nA - 1 - S0) * nB + us * rstep + jb + xg_pad(nx, ny, 1);
+                    float uf = (float)us;
+                    float ts = __builtin_amdgcn_fmed3f(uf * ias, tl, th), fs = floorf(fmaf(ts, dbf, fb));
+                    for (int u = us; u < ue; u += U) {
                         int sid[U];
                         float llo[U], lhi[U];
 #pragma unroll
