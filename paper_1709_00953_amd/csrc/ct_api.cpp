@@ -180,18 +180,39 @@ static void build_windows(ct_geom* g) {
     std::vector<int32_t> per_col(g->n, 0);
     for (int b = 0; b < g->m; ++b)
         for (int J = 0; J < g->n; ++J) {
+            // chunks of kChunk consecutive rays of a window (row-major, the
+            // last one shorter), listed by the detector row of their first
+            // ray across the row block's views: the rays of one row of
+            // neighbouring views cross the same voxel planes of a 3D box, so
+            // work-groups that run together reuse them from L2 (a 2D window
+            // is a single row, so its list keeps the view order)
+            struct Win {
+                int view, u0, v0, w, h;
+                int64_t roff;
+            };
+            std::vector<Win> wins;
             int64_t roff = 0;
-            const size_t before = g->wchunks.size();
+            int hmax = 0;
             for (int t = g->rb_tile_ptr[b]; t < g->rb_tile_ptr[b + 1]; ++t) {
                 const Tile& tl = g->tiles[t];
                 int u0, u1, v0, v1;
                 tile_window(g, tl, g->boxes[J], &u0, &u1, &v0, &v1);
-                const int64_t nr = (int64_t)(u1 - u0) * (v1 - v0);
-                for (int64_t k0 = 0; k0 < nr; k0 += kChunk)
-                    g->wchunks.push_back(Chunk{tl.view, u0, v0, u1 - u0, (int32_t)k0,
-                                               (int32_t)std::min<int64_t>(kChunk, nr - k0), (int32_t)(roff + k0), 0});
-                roff += nr;
+                if (u1 <= u0 || v1 <= v0) continue;
+                wins.push_back(Win{tl.view, u0, v0, u1 - u0, v1 - v0, roff});
+                roff += (int64_t)(u1 - u0) * (v1 - v0);
+                hmax = std::max(hmax, v1 - v0);
             }
+            const size_t before = g->wchunks.size();
+            std::vector<int64_t> next(wins.size(), 0);       // first ray of each window's next chunk
+            for (int r = 0; r < hmax; ++r)
+                for (size_t i = 0; i < wins.size(); ++i) {
+                    const Win& wn = wins[i];
+                    const int64_t nr = (int64_t)wn.w * wn.h;
+                    for (int64_t& k0 = next[i]; k0 < nr && k0 / wn.w == r; k0 += kChunk)
+                        g->wchunks.push_back(Chunk{wn.view, wn.u0, wn.v0, wn.w, (int32_t)k0,
+                                                   (int32_t)std::min<int64_t>(kChunk, nr - k0),
+                                                   (int32_t)(wn.roff + k0), 0});
+                }
             per_col[J] += (int32_t)(g->wchunks.size() - before);
             g->rbj_chunk_ptr.push_back((int32_t)g->wchunks.size());
             g->rbj_rays.push_back(roff);

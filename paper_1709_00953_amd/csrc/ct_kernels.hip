@@ -555,9 +555,22 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
     }
 }
 
+// Work-group b of n is dispatched to XCD b mod kXcd; give each XCD a
+// contiguous run of the launch's chunks (a bijection onto [0, n)), so the
+// chunks that one XCD runs together are neighbours in the chunk list.
+constexpr int kXcd = 8;
+__device__ __forceinline__ int xcd_run(const int b, const int n) {
+    const int q = n / kXcd, r = n % kXcd, x = b % kXcd, i = b / kXcd;
+    return x * q + min(x, r) + i;
+}
+
+// The 3D fused forward reads a box larger than an XCD's L2; its chunks are
+// listed row by row across views, and contiguous runs per XCD let views
+// that cross the same voxel planes share them in L2.
 template <int KIND, int MODE, int KS = kSplit>
 __global__ __launch_bounds__(256) void k_fwd(DGeom G, FwdCore a) {
-    fwd_body<KIND, MODE, FwdCore, KS>(G, a, blockIdx.x);
+    const int bid = (KIND == kCone && MODE == 1) ? xcd_run((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    fwd_body<KIND, MODE, FwdCore, KS>(G, a, bid);
 }
 
 template <int KIND>
