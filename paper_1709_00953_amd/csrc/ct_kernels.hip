@@ -584,7 +584,7 @@ __global__ __launch_bounds__(256) void k_fwd_inl(DGeom G, FwdArgs a) {
 // Clip length of the ray described by R with the voxel whose centre lies at
 // signed distance delta from it: the overlap of its two slab intervals.
 __device__ __forceinline__ float chord2(float delta, const Ray2B& R) {
-    return fmaxf(fminf(R.M, R.S - fabsf(delta * R.K)), 0.f);
+    return __builtin_amdgcn_fmed3f(R.S - fabsf(delta * R.K), 0.f, R.M);     // clamp to [0, M]
 }
 
 // Same, for rays with a zero direction component: such a ray lies in one
@@ -757,16 +757,16 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
                     }
                 } else if (blo <= bhi) {
                     // the next candidate's loads are issued before this one's
-                    // clip, so their latency overlaps the arithmetic
+                    // clip, so their latency overlaps the arithmetic; the last
+                    // candidate reloads its own bin (no branch around the loads)
                     Ray2B Rn = ldu(RB, (unsigned)blo);
                     float rn = ldu(rr, (unsigned)blo);
                     for (int b = blo; b <= bhi; ++b) {
                         const Ray2B Rb = Rn;
                         const float rv = rn;
-                        if (b < bhi) {
-                            Rn = ldu(RB, (unsigned)(b + 1));
-                            rn = ldu(rr, (unsigned)(b + 1));
-                        }
+                        const unsigned bn = (unsigned)min(b + 1, bhi);
+                        Rn = ldu(RB, bn);
+                        rn = ldu(rr, bn);
                         const float dlt = (float)fma(Rb.p, B, -Rb.q * A);
                         acc = fmaf(chord2(dlt, Rb), rv, acc);
                     }
@@ -852,6 +852,7 @@ struct ViewP3 {
     int32_t view, fu0, fu1, fv0, fv1;     // detector window [fu0, fu1) x [fv0, fv1)
     int32_t uref, vref, flags;
     int32_t sk[3];                // the source's slab per axis (rays with a zero component stay in it)
+    int32_t chh;                  // window rows per staging pass
 };
 
 constexpr int kRayC = 256;        // staged rays per pass
@@ -932,6 +933,7 @@ __device__ __forceinline__ void view_params3(const DGeom& G, const Tile& tl, con
     P.fu1 = max(u0, u1);
     P.fv0 = v0;
     P.fv1 = max(v0, v1);
+    P.chh = max(1, kRayC / max(1, min(P.fu1 - P.fu0, kRayC)));
     // plus the float32 rounding of the voxel's shadow centre and half-extent
     // (|beta| <= a few thousand bins)
     P.e2u = (float)fmin(e2u, 1e9) + 2e-3f + 2e-6f * fabsf((float)bu);
@@ -1052,6 +1054,7 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
             const bool careful = (__builtin_amdgcn_readfirstlane(P.flags) & 1) != 0;
             const int fw = fu1 - fu0, fh = fv1 - fv0;
             if (fw <= 0 || fh <= 0) continue;
+            const float* rview = uniform_ptr(a.r + (size_t)view * G.nv * G.nu);
             // this voxel's offsets and candidate window: its shadow centre
             // sdd B / A and the half-extent of its box, from the gradient at
             // its own centre, plus the remainder e2
@@ -1072,15 +1075,16 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
             const int vlo = valid ? (int)ceilf(betv - Wv) : 1, vhi = valid ? (int)floorf(betv + Wv) : 0;
             const float stu = fmaf(-dA, P.dus, (float)P.slu), stv = fmaf(-dA, P.dvs, (float)P.slv);
             // the detector window in passes of at most kRayC rays
-            const int cw = min(fw, kRayC), chh = max(1, kRayC / cw);
+            const int cw = min(fw, kRayC), chh = __builtin_amdgcn_readfirstlane(P.chh);
             for (int cv0 = fv0; cv0 < fv1; cv0 += chh) {
                 const int cv1 = min(fv1, cv0 + chh);
                 for (int cu0 = fu0; cu0 < fu1; cu0 += cw) {
                     const int cu1 = min(fu1, cu0 + cw);
                     const int pw = cu1 - cu0, np = pw * (cv1 - cv0);
                     // row of lane t in the pass: (t + 1/2) / pw lies at least 1/(2 pw)
-                    // from an integer, far beyond float32 rounding for t < 256
-                    const float ipw = 1.f / (float)pw;
+                    // from an integer, far beyond the rounding of rcp and the
+                    // product (a few 1e-7 relative) for t < 256
+                    const float ipw = __builtin_amdgcn_rcpf((float)pw);
                     __syncthreads();                    // previous pass fully read
                     if (t < np) {
                         const int row = (int)(((float)t + 0.5f) * ipw);
@@ -1104,7 +1108,7 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
                             w[k] = (zero >> k) & 1 ? INFINITY : hh[k] * fabsf(inv);
                         }
                         const float nrm = __builtin_amdgcn_sqrtf(fmaf(d[0], d[0], fmaf(d[1], d[1], d[2] * d[2])));
-                        const float rv = a.r[((size_t)view * G.nv + iv) * G.nu + iu];
+                        const float rv = ldu(rview, (unsigned)(iv * G.nu + iu));
                         rc0[t] = make_float4(al[0], al[1], al[2], w[0]);
                         rc1[t] = make_float4(be[0], be[1], be[2], w[1]);
                         rc2[t] = make_float4(w[2], nrm, rv, __int_as_float(zero));
