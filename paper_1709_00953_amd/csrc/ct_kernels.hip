@@ -1193,11 +1193,22 @@ __device__ __forceinline__ void step_body(const StepArgs& s, const int g, const 
     const int t0 = g * s.n_tiles, t1 = (g + 1) * s.n_tiles;
     double vg = 0.0, vq = 0.0;
     const int ng = t1 - t0, nq = c1 - c0;
-    for (int k = (int)threadIdx.x; k < max(ng, nq); k += 256) {
-        const double a = k < ng ? s.pg[t0 + k] : 0.0;
-        const double b = k < nq ? s.pq[c0 + k] : 0.0;
-        if (k < ng) vg += a;
-        if (k < nq) vq += b;
+    // four rounds of loads in flight at once, added in the same order
+    constexpr int R = 4;
+    for (int k0 = (int)threadIdx.x; k0 < max(ng, nq); k0 += R * 256) {
+        double a[R], b[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int k = k0 + q * 256;
+            a[q] = k < ng ? s.pg[t0 + k] : 0.0;
+            b[q] = k < nq ? s.pq[c0 + k] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int k = k0 + q * 256;
+            if (k < ng) vg += a[q];
+            if (k < nq) vq += b[q];
+        }
     }
     const double gg = block_sum256(vg, sh);
     __syncthreads();
@@ -1210,6 +1221,20 @@ __global__ __launch_bounds__(256) void k_step(StepArgs s) { step_body(s, blockId
 // ----------------------------------------------------------------------------
 // K4: finalize a column-block step
 // ----------------------------------------------------------------------------
+
+// sum_{j < n} z[j * M + ray] in ascending j, eight loads in flight at once
+__device__ __forceinline__ float col_sum(const float* z, const int64_t M, const int n, const int ray) {
+    float s = 0.f;
+    for (int j0 = 0; j0 < n; j0 += 8) {
+        float v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = j0 + q < n ? z[(size_t)(j0 + q) * M + ray] : 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (j0 + q < n) s += v[q];
+    }
+    return s;
+}
 
 __device__ __forceinline__ void fin_body(const DGeom& G, const FinArgs& f, const int bid) {
     const int ray_blocks = (f.n_chunks + 3) / 4;
@@ -1226,11 +1251,7 @@ __device__ __forceinline__ void fin_body(const DGeom& G, const FinArgs& f, const
         const float mu = (float)f.mu[en.group];
         const float zn = fmaf(mu, f.q[en.slot_prefix + ch.roff + lane], f.zJ[ray]);
         f.zJ[ray] = zn;
-        if (f.refresh) {
-            float s = 0.f;
-            for (int j = 0; j < f.n_cols; ++j) s += f.z[(size_t)j * f.M + ray];
-            f.r[ray] = f.y[ray] - s;
-        }
+        if (f.refresh) f.r[ray] = f.y[ray] - col_sum(f.z, f.M, f.n_cols, ray);
     } else {
         const int v = (bid - ray_blocks) * 256 + threadIdx.x;
         if (v >= f.vox_J) return;
@@ -1238,10 +1259,16 @@ __device__ __forceinline__ void fin_body(const DGeom& G, const FinArgs& f, const
         const int lx = v % nxJ, ly = (v / nxJ) % nyJ, lz = v / (nxJ * nyJ);
         const int nzJ = f.box.z1 - f.box.z0;
         const int li = xg_pad(nxJ, nyJ, nzJ) + v;           // copy 0 is x-fastest
+        // the groups' pairs, four loads in flight at once, added in group order
         float s = 0.f;
-        for (int g = 0; g < f.n_groups; ++g) {
-            const float2 p = f.xg[(size_t)g * f.xg_stride + li];
-            s += fmaf((float)f.mu[g], p.y, p.x);
+        for (int g0 = 0; g0 < f.n_groups; g0 += 4) {
+            float2 p[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                p[q] = g0 + q < f.n_groups ? f.xg[(size_t)(g0 + q) * f.xg_stride + li] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (g0 + q < f.n_groups) s += fmaf((float)f.mu[g0 + q], p[q].y, p[q].x);
         }
         const size_t gix = ((size_t)(f.box.z0 + lz) * f.ny + (f.box.y0 + ly)) * f.nx + f.box.x0 + lx;
         f.x[gix] = s / (float)f.n_groups;
@@ -1265,9 +1292,7 @@ __device__ __forceinline__ void res_body(const DGeom& G, const ResArgs& a, const
     if (lane >= ch.cnt) return;
     const int k = ch.k0 + lane;
     const int ray = (ch.view * G.nv + ch.v0 + k / ch.w) * G.nu + ch.u0 + k % ch.w;
-    float s = 0.f;
-    for (int j = 0; j < a.n_cols; ++j) s += a.z[(size_t)j * a.M + ray];
-    a.r[ray] = a.y[ray] - s;
+    a.r[ray] = a.y[ray] - col_sum(a.z, a.M, a.n_cols, ray);
 }
 
 __global__ __launch_bounds__(256) void k_residual(DGeom G, ResArgs a, int n_chunks) {
