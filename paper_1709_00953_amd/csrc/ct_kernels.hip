@@ -326,9 +326,8 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                         const double fl = floor(pb);
                         jb = (int)fl;
                         fb = fminf((float)(pb - fl), 0x1.fffffep-1f);
-                        const double dbd = d[B] * ih[B];   // voxels of B per mm of ray
-                        dbf = (float)dbd;
-                        idb = (float)fmax(fmin(1.0 / dbd, 1e30), -1e30);
+                        dbf = (float)(d[B] * ih[B]);       // voxels of B per mm of ray
+                        idb = (float)fmax(fmin(h[B] * id[B], 1e30), -1e30);
                     }
                     // the wave walks the slabs that some lane's ray overlaps: its
                     // lanes' ranges widened by one slab (float rounding), the
@@ -336,8 +335,9 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                     // without overlap are neutral)
                     int ulo = nS, uhi = 0;
                     if (!empty) {
-                        ulo = max(0, (int)floor(tlo / ia) - 1);
-                        uhi = min(nS, (int)ceil(thi / ia) + 1);
+                        const double iia = fabs(d[A]) * ih[A];  // slabs per mm of ray
+                        ulo = max(0, (int)floor(tlo * iia) - 1);
+                        uhi = min(nS, (int)ceil(thi * iia) + 1);
                     }
                     int us = 0, ue = nS;
                     for (int hi = nS; us < hi;) {
@@ -350,7 +350,8 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                         if (__ballot(uhi > mid)) lo2 = mid + 1;
                         else ue = mid;
                     }
-                    const float nfi = -fb * idb;
+                    // tau of the B plane above voxel lj: lj idb + nf1
+                    const float nf1 = (float)((1.0 - (double)fb) * (double)idb);
                     const float ias = (float)ia, tl = (float)tlo, th = (float)thi;
                     const bool up = d[B] >= 0.0;
                     const int rstep = d[A] > 0.0 ? nB : -nB;
@@ -358,34 +359,43 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                     int row = (d[A] > 0.0 ? S0 : nA - 1 - S0) * nB + us * rstep + jb + xg_pad(nx, ny, 1);
                     float uf = (float)us;
                     float ts = __builtin_amdgcn_fmed3f(uf * ias, tl, th), fs = floorf(fmaf(ts, dbf, fb));
-                    for (int u = us; u < ue; u += U) {
-                        int sid[U];
-                        float llo[U], lhi[U];
+                    // DIR 1: every lane's ray goes up B, so the lower voxel of a
+                    // slab is the one it starts in; DIR 2: every ray goes down;
+                    // DIR 0: chosen per lane
+                    auto walk = [&](auto dir) {
+                        constexpr int DIR = decltype(dir)::value;
+                        for (int u = us; u < ue; u += U) {
+                            int sid[U];
+                            float llo[U], lhi[U];
 #pragma unroll
-                        for (int q = 0; q < U; ++q) {
-                            // slabs past S1 get zero lengths (tau clamped to th)
-                            uf += 1.f;
-                            const float te = __builtin_amdgcn_fmed3f(uf * ias, tl, th);
-                            const float fe = floorf(fmaf(te, dbf, fb));
-                            const float lj = fminf(fs, fe);
-                            const float tc = __builtin_amdgcn_fmed3f(fmaf(lj + 1.f, idb, nfi), ts, te);
-                            const float l1 = tc - ts, l2 = te - tc;
-                            llo[q] = up ? l1 : l2;
-                            lhi[q] = up ? l2 : l1;
-                            sid[q] = row + (int)lj;
-                            row += rstep;
-                            ts = te;
-                            fs = fe;
-                        }
+                            for (int q = 0; q < U; ++q) {
+                                // slabs past S1 get zero lengths (tau clamped to th)
+                                uf += 1.f;
+                                const float te = __builtin_amdgcn_fmed3f(uf * ias, tl, th);
+                                const float fe = floorf(fmaf(te, dbf, fb));
+                                const float lj = DIR == 1 ? fs : (DIR == 2 ? fe : fminf(fs, fe));
+                                const float tc = __builtin_amdgcn_fmed3f(fmaf(lj, idb, nf1), ts, te);
+                                const float l1 = tc - ts, l2 = te - tc;
+                                llo[q] = DIR == 1 ? l1 : (DIR == 2 ? l2 : (up ? l1 : l2));
+                                lhi[q] = DIR == 1 ? l2 : (DIR == 2 ? l1 : (up ? l2 : l1));
+                                sid[q] = row + (int)lj;
+                                row += rstep;
+                                ts = te;
+                                fs = fe;
+                            }
 #pragma unroll
-                        for (int q = 0; q < U; ++q) {
-                            const XG2 v = ld_xg2(xgc, (unsigned)sid[q]);
-                            acc = fmaf(llo[q], v.x0, acc);
-                            acc = fmaf(lhi[q], v.x1, acc);
-                            acc2 = fmaf(llo[q], v.g0, acc2);
-                            acc2 = fmaf(lhi[q], v.g1, acc2);
+                            for (int q = 0; q < U; ++q) {
+                                const XG2 v = ld_xg2(xgc, (unsigned)sid[q]);
+                                acc = fmaf(llo[q], v.x0, acc);
+                                acc = fmaf(lhi[q], v.x1, acc);
+                                acc2 = fmaf(llo[q], v.g0, acc2);
+                                acc2 = fmaf(lhi[q], v.g1, acc2);
+                            }
                         }
-                    }
+                    };
+                    if (__ballot(!up) == 0ull) walk(std::integral_constant<int, 1>{});
+                    else if (__ballot(up) == 0ull) walk(std::integral_constant<int, 2>{});
+                    else walk(std::integral_constant<int, 0>{});
                 }
             }
         }
