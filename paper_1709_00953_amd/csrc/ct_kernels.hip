@@ -1183,9 +1183,12 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
     }
 }
 
-// (at most 128 VGPRs: four waves per SIMD)
+// Six work-groups per CU (the LDS limit; at most 80 VGPRs, six waves per
+// SIMD): the kernel waits on its staging loads and barriers, and two more
+// resident work-groups than at 128 VGPRs hide them (the register spills this
+// costs are in the once-per-64-views parameter set-up only)
 template <class BA>
-__global__ __launch_bounds__(256, 4) void k_back3(DGeom G, BA a) {
+__global__ __launch_bounds__(256, 6) void k_back3(DGeom G, BA a) {
     back3_body(G, a, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
@@ -1369,10 +1372,10 @@ __device__ __forceinline__ int box_vox(const Box& b) {
     return (b.x1 - b.x0) * (b.y1 - b.y0) * (b.z1 - b.z0);
 }
 
-// occupancy as the single-job kernels: eight waves per SIMD in 2D, four in 3D;
+// occupancy as the single-job kernels: eight waves per SIMD in 2D, six in 3D;
 // NW waves per 2D tile (the 3D tile always takes four)
 template <int KIND, int NW>
-__global__ __launch_bounds__(64 * NW, KIND == kCone ? 4 : 8) void kb_back(BatchArgs B) {
+__global__ __launch_bounds__(64 * NW, KIND == kCone ? 6 : 8) void kb_back(BatchArgs B) {
     const int k = batch_job(B, blockIdx.x);
     const int L = blockIdx.x - B.prefix[k];
     const BJob J = cld(B.jobs, k);
