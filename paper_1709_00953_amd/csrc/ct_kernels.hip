@@ -199,14 +199,18 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
     const bool active = lane < ch.cnt;
 
     // 2D fused forward: when every ray of the chunk runs at most 45 degrees
-    // from one axis, the chunk walks slab by slab along that axis (0: x,
-    // 1: y), else (-1) segment by segment.  Uniform per wave.
+    // from one axis and all go the same way along the other, the chunk walks
+    // slab by slab along that axis (0: x, 1: y), else (-1) segment by segment
+    // (chunks that straddle a diagonal or an axis direction).  Uniform per wave.
     int slab_axis = -1;
     if constexpr (MODE == 1 && DIMS == 2) {
         const int kk = ch.k0 + max(0, min(lane, ch.cnt - 1));
         const Ray2F R = G.ray2f[(size_t)ch.view * G.nu + ch.u0 + kk % ch.w];
         const unsigned long long bx = __ballot(fabs(R.dx) >= fabs(R.dy));
-        slab_axis = bx == ~0ull ? 0 : (bx == 0ull ? 1 : -1);
+        const int ax = bx == ~0ull ? 0 : (bx == 0ull ? 1 : -1);
+        // and every ray of the chunk goes the same way along the other axis
+        const unsigned long long bu = __ballot((ax == 0 ? R.dy : R.dx) >= 0.0);
+        slab_axis = (bu == ~0ull || bu == 0ull) ? ax : -1;
     }
 
     float acc = 0.f, acc2 = 0.f;
@@ -360,8 +364,7 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                     float uf = (float)us;
                     float ts = __builtin_amdgcn_fmed3f(uf * ias, tl, th), fs = floorf(fmaf(ts, dbf, fb));
                     // DIR 1: every lane's ray goes up B, so the lower voxel of a
-                    // slab is the one it starts in; DIR 2: every ray goes down;
-                    // DIR 0: chosen per lane
+                    // slab is the one it starts in; DIR 2: every ray goes down
                     auto walk = [&](auto dir) {
                         constexpr int DIR = decltype(dir)::value;
                         for (int u = us; u < ue; u += U) {
@@ -373,11 +376,11 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                                 uf += 1.f;
                                 const float te = __builtin_amdgcn_fmed3f(uf * ias, tl, th);
                                 const float fe = floorf(fmaf(te, dbf, fb));
-                                const float lj = DIR == 1 ? fs : (DIR == 2 ? fe : fminf(fs, fe));
+                                const float lj = DIR == 1 ? fs : fe;
                                 const float tc = __builtin_amdgcn_fmed3f(fmaf(lj, idb, nf1), ts, te);
                                 const float l1 = tc - ts, l2 = te - tc;
-                                llo[q] = DIR == 1 ? l1 : (DIR == 2 ? l2 : (up ? l1 : l2));
-                                lhi[q] = DIR == 1 ? l2 : (DIR == 2 ? l1 : (up ? l2 : l1));
+                                llo[q] = DIR == 1 ? l1 : l2;
+                                lhi[q] = DIR == 1 ? l2 : l1;
                                 sid[q] = row + (int)lj;
                                 row += rstep;
                                 ts = te;
@@ -394,8 +397,7 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                         }
                     };
                     if (__ballot(!up) == 0ull) walk(std::integral_constant<int, 1>{});
-                    else if (__ballot(up) == 0ull) walk(std::integral_constant<int, 2>{});
-                    else walk(std::integral_constant<int, 0>{});
+                    else walk(std::integral_constant<int, 2>{});
                 }
             }
         }
