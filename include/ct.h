@@ -317,7 +317,7 @@ int ct_batch_profile_read(ct_batch* batch, ct_kernel_times* out);
  * (only the order of float32 sums moves): how many pieces each chord of the
  * fused forward pass is walked in (fwd_split: 1, 2 or 4 waves per 64 rays),
  * and how many waves share the views of a 2D back-projection tile
- * (back_waves: 1, 2 or 4; the 3D tile always takes 4).  They are not steps
+ * (back_waves: 1, 2, 4, 8 or 16; the 3D tile always takes 4).  They are not steps
  * of the method: they serve the batched and served system patterns, whose
  * jobs range from small slices to large volumes.  Default: 4 and 4.
  *

@@ -2008,27 +2008,33 @@ extern "C" int ct_batch_epoch(ct_batch* b, int32_t flags, int32_t* ran, void* st
 // launch shapes and their tuner
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int kShapes = 3;
-constexpr int kShapeVal[kShapes] = {1, 2, 4};
+constexpr int kSplits = 3, kWaves = 5;
+constexpr int kSplitVal[kSplits] = {1, 2, 4};
+constexpr int kWaveVal[kWaves] = {1, 2, 4, 8, 16};
 constexpr int kTuneReps = 3;
 
 struct TuneTable {
-    double ms[kShapes][kShapes];    // [pieces per chord][waves per tile]; < 0: not a candidate
+    double ms[kSplits][kWaves];     // [pieces per chord][waves per tile]; < 0: not a candidate
 };
 
 std::mutex g_tune_mu;
 std::map<std::string, TuneTable> g_tune_cache;
 
-int shape_index(int v) {
-    for (int i = 0; i < kShapes; ++i)
-        if (kShapeVal[i] == v) return i;
+int split_index(int v) {
+    for (int i = 0; i < kSplits; ++i)
+        if (kSplitVal[i] == v) return i;
+    return -1;
+}
+int wave_index(int v) {
+    for (int i = 0; i < kWaves; ++i)
+        if (kWaveVal[i] == v) return i;
     return -1;
 }
 }  // namespace
 
 static int check_shape(int dims, int split, int waves) {
-    if (shape_index(split) < 0) return fail(CT_EINVAL, "fwd_split must be 1, 2 or 4 (got %d)", split);
-    if (shape_index(waves) < 0) return fail(CT_EINVAL, "back_waves must be 1, 2 or 4 (got %d)", waves);
+    if (split_index(split) < 0) return fail(CT_EINVAL, "fwd_split must be 1, 2 or 4 (got %d)", split);
+    if (wave_index(waves) < 0) return fail(CT_EINVAL, "back_waves must be 1, 2, 4, 8 or 16 (got %d)", waves);
     if (dims == 3 && waves != 4) return fail(CT_EINVAL, "the 3D back-projection tile takes 4 waves");
     return CT_OK;
 }
@@ -2068,12 +2074,12 @@ static int tune_measure(ct_geom* g, const ct_schedule* sc, TuneTable* t, hipStre
     if (e != hipSuccess) rc = fail(CT_EDEVICE, "tuner scratch: %s", hipGetErrorString(e));
     if (!rc) rc = ct_solver_create(g, &p, ws, wsb, &s);
     if (!rc) rc = ct_solver_reset(s, y, nullptr, st);
-    for (int i = 0; i < kShapes && !rc; ++i) {
-        for (int j = 0; j < kShapes && !rc; ++j) {
+    for (int i = 0; i < kSplits && !rc; ++i) {
+        for (int j = 0; j < kWaves && !rc; ++j) {
             t->ms[i][j] = -1.0;
-            if (g->dims == 3 && kShapeVal[j] != 4) continue;
-            g->tune.split = kShapeVal[i];
-            g->tune.waves = kShapeVal[j];
+            if (g->dims == 3 && kWaveVal[j] != 4) continue;
+            g->tune.split = kSplitVal[i];
+            g->tune.waves = kWaveVal[j];
             rc = ct_block_epoch(s, sc, 0, y, x, st);
             if (!rc && (e = hipEventRecord(e0, st)) != hipSuccess) rc = fail(CT_EDEVICE, "%s", hipGetErrorString(e));
             for (int r = 0; r < kTuneReps && !rc; ++r) rc = ct_block_epoch(s, sc, 0, y, x, st);
@@ -2116,11 +2122,11 @@ static int tune_table(ct_geom* g, const ct_schedule* sc, bool refresh, TuneTable
     return CT_OK;
 }
 
-static void tune_pick(const double (&ms)[kShapes][kShapes], int* bi, int* bj) {
-    *bi = shape_index(kSplit);
-    *bj = shape_index(4);
-    for (int i = 0; i < kShapes; ++i)
-        for (int j = 0; j < kShapes; ++j)
+static void tune_pick(const double (&ms)[kSplits][kWaves], int* bi, int* bj) {
+    *bi = split_index(kSplit);
+    *bj = wave_index(4);
+    for (int i = 0; i < kSplits; ++i)
+        for (int j = 0; j < kWaves; ++j)
             if (ms[i][j] >= 0 && (ms[*bi][*bj] < 0 || ms[i][j] < ms[*bi][*bj])) {
                 *bi = i;
                 *bj = j;
@@ -2155,18 +2161,18 @@ extern "C" int ct_geom_tune(ct_geom* g, const ct_schedule* sc, int32_t flags, ct
     if ((rc = tune_table(g, sc, (flags & CT_TUNE_REFRESH) != 0, &t, &cached, (hipStream_t)stream))) return rc;
     int bi, bj;
     tune_pick(t.ms, &bi, &bj);
-    g->tune.split = kShapeVal[bi];
-    g->tune.waves = kShapeVal[bj];
+    g->tune.split = kSplitVal[bi];
+    g->tune.waves = kWaveVal[bj];
     if (out) {
         std::memset(out, 0, sizeof *out);
         out->fwd_split = g->tune.split;
         out->back_waves = g->tune.waves;
         out->ms = t.ms[bi][bj];
-        out->ms_default = t.ms[shape_index(kSplit)][shape_index(4)];
+        out->ms_default = t.ms[split_index(kSplit)][wave_index(4)];
         out->cached = cached ? 1 : 0;
         if (!cached)
-            for (int i = 0; i < kShapes; ++i)
-                for (int j = 0; j < kShapes; ++j) out->trials += t.ms[i][j] >= 0 ? 1 : 0;
+            for (int i = 0; i < kSplits; ++i)
+                for (int j = 0; j < kWaves; ++j) out->trials += t.ms[i][j] >= 0 ? 1 : 0;
     }
     return CT_OK;
 }
@@ -2175,7 +2181,7 @@ extern "C" int ct_batch_tune(ct_batch* b, int32_t flags, ct_tuning* out, void* s
     if (!b) return fail(CT_EINVAL, "NULL argument");
     if (flags & ~CT_TUNE_REFRESH) return fail(CT_EINVAL, "unknown flags 0x%x", flags);
     if (out) std::memset(out, 0, 4 * sizeof *out);
-    double tot[4][kShapes][kShapes] = {};
+    double tot[4][kSplits][kWaves] = {};
     bool have[4] = {false, false, false, false};
     int trials[4] = {0, 0, 0, 0}, all_cached[4] = {1, 1, 1, 1};
     std::vector<std::string> refreshed;
@@ -2192,8 +2198,8 @@ extern "C" int ct_batch_tune(ct_batch* b, int32_t flags, ct_tuning* out, void* s
         if ((rc = tune_table(g, sc, refresh, &t, &cached, (hipStream_t)stream))) return rc;
         if (refresh) refreshed.push_back(key);
         const int k = g->d.kind;
-        for (int i = 0; i < kShapes; ++i)
-            for (int q = 0; q < kShapes; ++q) {
+        for (int i = 0; i < kSplits; ++i)
+            for (int q = 0; q < kWaves; ++q) {
                 if (!have[k]) tot[k][i][q] = t.ms[i][q];
                 else if (t.ms[i][q] < 0 || tot[k][i][q] < 0) tot[k][i][q] = -1.0;
                 else tot[k][i][q] += t.ms[i][q];
@@ -2206,13 +2212,13 @@ extern "C" int ct_batch_tune(ct_batch* b, int32_t flags, ct_tuning* out, void* s
         if (!have[k]) continue;
         int bi, bj;
         tune_pick(tot[k], &bi, &bj);
-        b->tune[k].split = kShapeVal[bi];
-        b->tune[k].waves = kShapeVal[bj];
+        b->tune[k].split = kSplitVal[bi];
+        b->tune[k].waves = kWaveVal[bj];
         if (out) {
-            out[k].fwd_split = kShapeVal[bi];
-            out[k].back_waves = kShapeVal[bj];
+            out[k].fwd_split = kSplitVal[bi];
+            out[k].back_waves = kWaveVal[bj];
             out[k].ms = tot[k][bi][bj];
-            out[k].ms_default = tot[k][shape_index(kSplit)][shape_index(4)];
+            out[k].ms_default = tot[k][split_index(kSplit)][wave_index(4)];
             out[k].trials = trials[k];
             out[k].cached = all_cached[k];
         }

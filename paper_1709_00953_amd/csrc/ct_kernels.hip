@@ -822,9 +822,10 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
 
 // At most 64 VGPRs (eight waves per SIMD); with four waves, 20 KB of LDS:
 // eight work-groups per CU, so a launch of 2048 tiles (four groups of a
-// 128 x 256 block) is resident in one round
+// 128 x 256 block) is resident in one round.  Eight or sixteen waves per tile
+// (up to 80 KB of LDS) spread a small launch's views over more SIMDs.
 template <int KIND, class BA, int NW>
-__global__ __launch_bounds__(64 * NW, 8) void k_back2(DGeom G, BA a) {
+__global__ __launch_bounds__(64 * NW, NW <= 4 ? 8 : 32 / NW) void k_back2(DGeom G, BA a) {
     back2_body<KIND, BA, NW>(G, a, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
@@ -1377,7 +1378,7 @@ __device__ __forceinline__ int box_vox(const Box& b) {
 // occupancy as the single-job kernels: eight waves per SIMD in 2D, six in 3D;
 // NW waves per 2D tile (the 3D tile always takes four)
 template <int KIND, int NW>
-__global__ __launch_bounds__(64 * NW, KIND == kCone ? 6 : 8) void kb_back(BatchArgs B) {
+__global__ __launch_bounds__(64 * NW, KIND == kCone ? 6 : (NW <= 4 ? 8 : 32 / NW)) void kb_back(BatchArgs B) {
     const int k = batch_job(B, blockIdx.x);
     const int L = blockIdx.x - B.prefix[k];
     const BJob J = cld(B.jobs, k);
@@ -1634,6 +1635,10 @@ static hipError_t launch_back_as(const DGeom& G, const BA& a, int n_groups, int 
         launch_back2<BA, 2>(G, a, grid, st);
     } else if (waves == 4) {
         launch_back2<BA, 4>(G, a, grid, st);
+    } else if (waves == 8) {
+        launch_back2<BA, 8>(G, a, grid, st);
+    } else if (waves == 16) {
+        launch_back2<BA, 16>(G, a, grid, st);
     } else {
         return hipErrorInvalidValue;
     }
@@ -1676,6 +1681,8 @@ static hipError_t launch_batch_kind(int phase, const BatchArgs& b, int blocks, c
             if (t.waves == 1) hipLaunchKernelGGL((kb_back<KIND, 1>), grid, dim3(64), 0, st, b);
             else if (t.waves == 2) hipLaunchKernelGGL((kb_back<KIND, 2>), grid, dim3(128), 0, st, b);
             else if (t.waves == 4) hipLaunchKernelGGL((kb_back<KIND, 4>), grid, dim3(256), 0, st, b);
+            else if (t.waves == 8) hipLaunchKernelGGL((kb_back<KIND, 8>), grid, dim3(512), 0, st, b);
+            else if (t.waves == 16) hipLaunchKernelGGL((kb_back<KIND, 16>), grid, dim3(1024), 0, st, b);
             else return hipErrorInvalidValue;
         }
     } else {

@@ -68,13 +68,13 @@ def test_geometry_validation_rejects_bad_descriptions():
 
 def test_launch_shapes_validated():
     """Launch shapes are checked before any device work: pieces per chord and
-    waves per 2D tile in {1, 2, 4}; the 3D tile takes 4 waves."""
+    waves per 2D tile in {1, 2, 4, 8, 16}; the 3D tile takes 4 waves."""
     G = ct.ct_geom_create(inputs.config_c1())
     assert ct.ct_geom_get_tuning(G)["fwd_split"] == 4 and ct.ct_geom_get_tuning(G)["back_waves"] == 4
     ct.ct_geom_set_tuning(G, 2, 1)
     t = ct.ct_geom_get_tuning(G)
     assert (t["fwd_split"], t["back_waves"]) == (2, 1)
-    for split, waves in ((3, 4), (0, 4), (4, 8), (8, 2)):
+    for split, waves in ((3, 4), (0, 4), (4, 32), (4, 3), (8, 2)):
         _err(ct.ct_geom_set_tuning, G, split, waves)
     assert ct.ct_geom_get_tuning(G)["fwd_split"] == 2          # unchanged by the rejected calls
     C = ct.ct_geom_create(inputs.config_p3())

@@ -212,6 +212,6 @@ def test_batch_argument_errors(ct):
     with pytest.raises(ct.CtError):
         ct.ct_batch_create(0)
     ct.ct_batch_set_tuning(B, 2, 1, 2)
-    for kind, split, waves in ((3, 1, 2), (4, 1, 4), (2, 3, 4), (0, 4, 8)):
+    for kind, split, waves in ((3, 1, 2), (4, 1, 4), (2, 3, 4), (0, 4, 32), (3, 2, 16)):
         with pytest.raises(ct.CtError):             # 3D takes 4 waves; unknown kind; bad shapes
             ct.ct_batch_set_tuning(B, kind, split, waves)

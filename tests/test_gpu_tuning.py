@@ -32,7 +32,7 @@ def host(t):
 
 
 def shapes(g):
-    waves = (4,) if g.is3d else (1, 2, 4)
+    waves = (4,) if g.is3d else (1, 2, 4, 8, 16)
     return [(s, w) for s in (1, 2, 4) for w in waves]
 
 
