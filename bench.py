@@ -583,7 +583,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {max(args.gpus, world)}); "
+        print(f"bench.py: the solver runs on one GPU only (asked for {max(args.gpus, world)}); "
               "sharding the column blocks across GPUs is not built.",
               file=sys.stderr)
         sys.exit(2)

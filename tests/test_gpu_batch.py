@@ -91,11 +91,13 @@ def _make_jobs(ct, specs):
     return jobs
 
 
-@pytest.mark.parametrize("graph,shapes", [(False, None), (True, None), (True, "tuned"), (False, "forced")])
+@pytest.mark.parametrize("graph,shapes", [(False, None), (True, None), (True, "tuned"), (False, "forced"),
+                                          (True, "wide")])
 def test_batch_matches_alone(ct, graph, shapes):
     """shapes: the default launch shapes; the tuner's (the jobs' geometries
     take the batch's choice); or forced ones set on the batch and the
-    geometries alike."""
+    geometries alike (one piece per chord and two waves per 2D tile, or two
+    pieces and sixteen waves)."""
     jobs = _make_jobs(ct, JOBS)
     B = ct.ct_batch_create(len(jobs))
     ids = {}
@@ -109,11 +111,12 @@ def test_batch_matches_alone(ct, graph, shapes):
             t = ct.ct_geom_get_tuning(j.G)
             c = chosen[j.g.kind]
             assert (t["fwd_split"], t["back_waves"]) == (c["fwd_split"], c["back_waves"])
-    elif shapes == "forced":
+    elif shapes in ("forced", "wide"):
+        split, waves = (1, 2) if shapes == "forced" else (2, 16)
         for kind in range(4):
-            ct.ct_batch_set_tuning(B, kind, 1, 4 if kind == 3 else 2)
+            ct.ct_batch_set_tuning(B, kind, split, 4 if kind == 3 else waves)
         for j in jobs:
-            ct.ct_geom_set_tuning(j.G, 1, 4 if j.g.kind == 3 else 2)
+            ct.ct_geom_set_tuning(j.G, split, 4 if j.g.kind == 3 else waves)
     done = {j.name: j.first for j in jobs}
     it = 0
     while True:
