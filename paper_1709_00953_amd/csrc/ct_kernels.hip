@@ -5,15 +5,15 @@
 //             consecutive lanes = consecutive detector bins, so the output
 //             writes are coalesced along the detector-major ray layout.  The
 //             ray is set up in float64 (entry into the box, no division), then
-//             walked in float32 box-local voxel coordinates, crossing
-//             parameters taken from the plane index rather than by repeated
-//             addition; four segments are formed before their four gathers so
-//             that the loads overlap.  The fused mode walks x_J and g_J
-//             together (A x and A g in one pass), emits a float64 partial of
-//             ||A g||^2 per work-group, and the last work-group to finish
-//             turns all partials into mu = beta ||g||^2 / ||A g||^2 (Eq. 11,
-//             relaxed) in a fixed order.  The count mode counts the pairs
-//             longer than tau (block densities).
+//             walked in float32 box-local coordinates, crossing parameters
+//             taken from the plane index rather than by repeated addition.
+//             The segment walk forms four segments before their four gathers
+//             so that the loads overlap; the 2D fused mode walks slab by slab
+//             along the rays' major axis where a chunk allows it (one 16-byte
+//             load per slab fetches the two voxels the ray can meet there).
+//             The fused mode walks x_J and g_J together (A x and A g in one
+//             pass) and emits a float64 partial of ||A g||^2 per work-group;
+//             the count mode counts the pairs longer than tau (densities).
 //  k_back2/3  gather back-projection (A_I^J)^T r_I (Eq. 7): one lane per
 //             voxel, which visits the bins of its shadow in every view of the
 //             group and clips each candidate ray against its own box, so no
@@ -21,10 +21,12 @@
 //             The voxel's view-frame offset and each candidate's distance from
 //             the voxel centre are formed in float64 (they cancel ~500 mm
 //             lever arms); the clip itself is float32.  In 2D a work-group is
-//             an 8 x 8 voxel tile whose four waves take every fourth view;
+//             an 8 x 8 voxel tile whose NW waves take every NW-th view;
 //             per (tile, view) one lane derives the frame offsets and a
 //             linearised shadow with a rigorous curvature margin, so a voxel's
 //             candidate bins cost two FMAs.
+//  k_step     mu = beta ||g||^2 / ||A g||^2 (Eq. 11, relaxed) of every group,
+//             from the partials in a fixed order.
 //  k_finalize z^J_{I_G} = A x + mu A g, residual r = y - sum_j z^j on the
 //             touched rays (Sec. II-C), and x_J = mean_G (x_J + mu_G g_G).
 //  k_residual r_I = y_I - sum_j z^j_I (epoch-synchronous refresh, reset).
@@ -788,9 +790,8 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
         __syncthreads();
     }
 
-    // the four waves' partial sums, added in a fixed order
-    // the waves' partial sums in a fixed order; the view parameters are dead
-    // here and their LDS holds them
+    // the waves' partial sums, added in a fixed order; the view parameters are
+    // dead here and their LDS holds them
     float gsum = acc;
     if constexpr (NW > 1) {
         float* red = reinterpret_cast<float*>(&vp[0][0]);
