@@ -28,9 +28,12 @@ enum { kPar2D = 0, kFanFlat = 1, kFanCurved = 2, kCone = 3 };
 // rays) gather adjacent pixels.  The walk forms kWalkU segments before their
 // gathers, so it can step past the box by one crossing that float32 rounding
 // places before the exit, then by up to kWalkU - 1 more to the end of the
-// batch, each by at most the largest index stride.  Each copy has xg_pad zero
-// elements before and after it, enough for those steps and one more: they
-// read finite values for segments of zero length, with no bounds check.
+// batch, each by at most the largest index stride.  The 2D slab walk runs at
+// most kWalkU - 1 slab rows past the box (one row stride each) and reads a
+// pair that starts one element before a row or ends one element after it.
+// Each copy has xg_pad zero elements before and after it, enough for those
+// steps and one more: they read finite values for segments of zero length,
+// with no bounds check.
 constexpr int kWalkU = 4;
 __host__ __device__ inline int xg_pad(int nx, int ny, int nz) {
     const int step = nz > 1 ? nx * ny : (nx > ny ? nx : ny);
