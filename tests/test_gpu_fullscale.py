@@ -1,5 +1,7 @@
 """Parity at the full sizes of the benchmark workloads (512^2 fan beam, 256^3
-cone beam), in the launch configuration the benchmark times.
+cone beam), in the launch configuration the benchmark times, and at the
+largest sizes of the batched and served workloads (1024^2 fan slices, 192^3
+cones).
 
 Projections are checked on sampled outputs the oracle computes one by one:
 sampled rays through Siddon rows of those rays, sampled voxels through the
@@ -85,18 +87,31 @@ def clip_sum(g, org, dirn, div, r, v):
     return float(L @ r.astype(np.float64))
 
 
-def test_fan512_projectors_sampled(ct):
-    g = inputs.config_c2()
+# 2D cases: the benchmark's 512^2 fan, and the largest slice of the batched
+# and served workloads (1024^2 at 0.25 mm, 1536 views of 1536 bins)
+FAN_CASES = {
+    "fan512": (inputs.config_c2, (([0, 1, 2, 3, 4, 5, 6, 7], 5), ([2], 0), ([7, 3], 6)),
+               (([2], 0), ([7, 3], 6))),
+    "slice1024": (lambda: inputs.slice_fan(1024), (([0, 1, 2, 3], 3), ([1], 0), ([3, 0], 2)),
+                  (([1], 0), ([3, 0], 2))),
+}
+
+
+@pytest.mark.parametrize("name", list(FAN_CASES))
+def test_fan_projectors_sampled(ct, name):
+    make, fwd_cases, back_cases = FAN_CASES[name]
+    g = make()
     G = ct.ct_geom_create(g)
     rng = np.random.default_rng(11)
     x = rng.uniform(0.0, 1.0, g.n_vox).astype(np.float32)
-    for rbs, J in (([0, 1, 2, 3, 4, 5, 6, 7], 5), ([2], 0), ([7, 3], 6)):
-        err = sampled_forward(ct, g, G, rbs, J, x, 3000, 12 + J)
-        print(f"[full] fan512 forward rbs={rbs} J={J}: rel {err:.2e}", flush=True)
+    for rbs, J in fwd_cases:
+        err = sampled_forward(ct, g, G, list(rbs), J, x, 3000, 12 + J)
+        print(f"[full] {name} forward rbs={rbs} J={J}: rel {err:.2e}", flush=True)
         assert err <= 1e-5
     r = rng.normal(0.0, 1.0, g.n_rays).astype(np.float32)
     org_all, dir_all, div = rays.rays(g)
-    for rbs, J in (([2], 0), ([7, 3], 6)):
+    for rbs, J in back_cases:
+        rbs = list(rbs)
         gd = torch.full((G.N,), 7.0, device="cuda")
         ct.ct_block_back(G, rbs, J, dev(r), gd)
         got = host(gd)
@@ -105,7 +120,7 @@ def test_fan512_projectors_sampled(ct):
         smp = np.sort(rng.choice(vox, size=300, replace=False))
         ref = np.array([clip_sum(g, org_all[I], dir_all[I], div, r[I], v) for v in smp])
         err = rel_l2(got[smp], ref)
-        print(f"[full] fan512 back rbs={rbs} J={J}: rel {err:.2e}", flush=True)
+        print(f"[full] {name} back rbs={rbs} J={J}: rel {err:.2e}", flush=True)
         assert err <= 1e-5
         other = np.setdiff1d(rng.choice(G.N, size=5000, replace=False), vox)
         assert np.all(got[other] == 7.0)
@@ -174,18 +189,29 @@ def cone_candidates(g, v, views):
     return np.concatenate(out)
 
 
-def test_cone256_projectors_sampled(ct):
-    g = inputs.config_c3()
+# 3D cases: the benchmark's 256^3 cone and the largest served cone (192^3,
+# 360 views of 288^2)
+CONE_CASES = {
+    "cone256": (inputs.config_c3, (([0, 1, 2], 4), ([11], 0), ([5, 9, 6], 7)), (([0, 1, 2], 4), ([5, 9, 6], 7))),
+    "cone192": (lambda: inputs.slice_cone(192), (([0, 1, 2], 3), ([11], 0), ([4, 8], 6)), (([0, 1, 2], 3), ([4, 8], 6))),
+}
+
+
+@pytest.mark.parametrize("name", list(CONE_CASES))
+def test_cone_projectors_sampled(ct, name):
+    make, fwd_cases, back_cases = CONE_CASES[name]
+    g = make()
     G = ct.ct_geom_create(g)
     rng = np.random.default_rng(21)
     x = rng.uniform(0.0, 1.0, g.n_vox).astype(np.float32)
-    for rbs, J in (([0, 1, 2], 4), ([11], 0), ([5, 9, 6], 7)):
-        err = sampled_forward(ct, g, G, rbs, J, x, 2000, 22 + J)
-        print(f"[full] cone256 forward rbs={rbs} J={J}: rel {err:.2e}", flush=True)
+    for rbs, J in fwd_cases:
+        err = sampled_forward(ct, g, G, list(rbs), J, x, 2000, 22 + J)
+        print(f"[full] {name} forward rbs={rbs} J={J}: rel {err:.2e}", flush=True)
         assert err <= 1e-5
     del x
     r = rng.normal(0.0, 1.0, g.n_rays).astype(np.float32)
-    for rbs, J in (([0, 1, 2], 4), ([5, 9, 6], 7)):
+    for rbs, J in back_cases:
+        rbs = list(rbs)
         gd = torch.full((G.N,), 7.0, device="cuda")
         ct.ct_block_back(G, rbs, J, dev(r), gd)
         got = host(gd)
@@ -198,7 +224,7 @@ def test_cone256_projectors_sampled(ct):
             org, dirn, div = rays.rays_at(g, cand)
             ref.append(clip_sum(g, org, dirn, div, r[cand], v))
         err = rel_l2(got[smp], np.array(ref))
-        print(f"[full] cone256 back rbs={rbs} J={J}: rel {err:.2e}", flush=True)
+        print(f"[full] {name} back rbs={rbs} J={J}: rel {err:.2e}", flush=True)
         assert err <= 1e-5
         other = np.setdiff1d(rng.choice(G.N, size=5000, replace=False), vox)
         assert np.all(got[other] == 7.0)
