@@ -279,3 +279,62 @@ def test_cone256_epoch_invariants(ct):
     print(f"[full] cone256 one epoch: true residual {rel:.4f}", flush=True)
     assert np.isfinite(host(x)).all()
     assert 0.0 < rel < 0.9
+
+
+# The fused forward of the solver's epoch, the kernel the benchmark times, at
+# full size: the 2D cases walk slab by slab, the 3D ones run their chunks in
+# per-XCD runs.
+FUSED_CASES = {
+    "fan512": inputs.config_c2,
+    "slice1024": lambda: inputs.slice_fan(1024),
+    "cone256": inputs.config_c3,
+    "cone192": lambda: inputs.slice_cone(192),
+}
+
+
+@pytest.mark.parametrize("name", list(FUSED_CASES))
+def test_fused_forward_sampled(ct, name):
+    """After a reset from x0, y is set to the float32 sum of the z^j in the
+    kernels' order, so the reset gives r = 0 exactly; with r refreshed once per
+    epoch every g and mu of the next epoch is then 0 (reading C7), x stays x0
+    and each visited z^J is the fused forward's A_{I_G}^J x0_J, checked on
+    sampled rays against the oracle's Siddon rows."""
+    g = FUSED_CASES[name]()
+    G = ct.ct_geom_create(g)
+    rng = np.random.default_rng(31)
+    x0 = rng.uniform(0.0, 1.0, g.n_vox).astype(np.float32)
+    xd = dev(x0)
+    sol = ct.ct_solver_create(G, ct.CT_SYNC_EPOCH)
+    ct.ct_solver_reset(sol, torch.zeros(G.M, device="cuda"), xd)
+    z, r = ct.ct_solver_state(sol)
+    zz = z.view(g.n, G.M)
+    y = zz[0].clone()
+    for j in range(1, g.n):
+        y = y + zz[j]
+    ct.ct_solver_reset(sol, y, xd)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(r).item() == 0
+    P = np.full((g.m, g.n), 1.0 / g.m)
+    sch = sampler.make_schedule(P, 1, 0.5, 1.0, 2, 1.0, 31)
+    x = xd.clone()
+    ct.ct_block_epoch(sol, ct.ct_schedule_import(G, sch), 0, y, x)
+    torch.cuda.synchronize()
+    # x_J = the mean over its groups of x0_J + 0 g: x0 up to the rounding of
+    # the mean
+    assert rel_l2(host(x).astype(np.float64), x0.astype(np.float64)) <= 1e-6
+    cols = sch.cols[sch.epoch_col_ptr[0]:sch.epoch_col_ptr[1]]
+    for k, J in enumerate(cols[:3]):
+        c = sch.epoch_col_ptr[0] + k
+        groups = range(sch.col_group_ptr[c], sch.col_group_ptr[c + 1])
+        rbs = [int(b) for q in groups for b in sch.rbs[sch.group_rb_ptr[q]:sch.group_rb_ptr[q + 1]]]
+        I = rows_of(g, rbs)
+        smp = np.sort(rng.choice(I, size=min(1500, I.size), replace=False))
+        org, dirn, div = rays.rays_at(g, smp)
+        vox = g.col_block_vox(int(J))
+        xJ = np.zeros(g.n_vox)
+        xJ[vox] = x0[vox].astype(np.float64)
+        ref = siddon.rows_for(g, org, dirn, div) @ xJ
+        got = zz[int(J)][torch.as_tensor(smp, device="cuda")].cpu().numpy().astype(np.float64)
+        err = rel_l2(got, ref)
+        print(f"[full] {name} fused forward J={int(J)} ({len(rbs)} row blocks): rel {err:.2e}", flush=True)
+        assert err <= 1e-5
