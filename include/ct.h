@@ -219,8 +219,12 @@ int ct_solver_reset(ct_solver* solver, const float* y, const float* x, void* str
 /* One epoch `epoch` of the schedule, updating x (device, [N]) in place. */
 int ct_block_epoch(ct_solver* solver, const ct_schedule* sched, int32_t epoch, const float* y,
                    float* x, void* stream);
-/* Device pointers into the solver workspace (for inspection and tests):
- * z [n][M], r [M]. */
+/* Device pointers into the solver workspace: z [n][M], r [M].  Between
+ * epochs a solver's whole state is x, z and r: every other workspace buffer
+ * is written within each step before it is read, or holds zeros.  Copying
+ * x, z and r out after an epoch and back into a solver of the same geometry
+ * and sync mode (after its ct_solver_reset) checkpoints the run; the resumed
+ * epochs repeat the uninterrupted run's bit for bit. */
 int ct_solver_state(const ct_solver* solver, float** z, float** r);
 /* ||y - A x||_2 / ||y||_2 with a full forward projection (reading C16);
  * synchronous on `stream`. */

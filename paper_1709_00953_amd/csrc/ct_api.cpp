@@ -575,6 +575,12 @@ static int geom_ensure_device(ct_geom* g) {
     G.wchunks = (const Chunk*)(base + L.off_wch);
     G.rbj_chunk_ptr = (const int32_t*)(base + L.off_rbj);
     G.n_cols = g->n;
+    G.mixed_boxes = 0;
+    for (const Box& b : g->boxes) {
+        const Box& b0 = g->boxes[0];
+        if (b.x1 - b.x0 != b0.x1 - b0.x0 || b.y1 - b.y0 != b0.y1 - b0.y0 || b.z1 - b.z0 != b0.z1 - b0.z0)
+            G.mixed_boxes = 1;
+    }
     g->d_all = (Entry*)(base + L.off_all);
     g->d_nnz = (unsigned long long*)(base + L.off_nnz);
     g->d_boxes = (Box*)(base + L.off_boxes);

@@ -33,7 +33,10 @@ enum { kPar2D = 0, kFanFlat = 1, kFanCurved = 2, kCone = 3 };
 // pair that starts one element before a row or ends one element after it.
 // Each copy has xg_pad zero elements before and after it, enough for those
 // steps and one more: they read finite values for segments of zero length,
-// with no bounds check.
+// with no bounds check.  Where column blocks differ in size, the step's
+// finalize clears the copies after reading them: a block of another size
+// lays its copies out differently, so this step's pairs could otherwise lie
+// in the padding of a later step's.
 constexpr int kWalkU = 4;
 __host__ __device__ inline int xg_pad(int nx, int ny, int nz) {
     const int step = nz > 1 ? nx * ny : (nx > ny ? nx : ny);
@@ -107,6 +110,7 @@ struct DGeom {
     const Chunk* wchunks;         // row block x column block windows
     const int32_t* rbj_chunk_ptr; // [m*n+1], index rb*n + J
     int32_t n_cols;
+    int32_t mixed_boxes;          // column blocks differ in size (their (x, g) copies differ in layout)
 };
 
 struct Box {
@@ -197,7 +201,7 @@ struct FinArgs {
     int32_t vox_J;
     int32_t xg_stride;
     int32_t n_groups;
-    const float2* xg;
+    float2* xg;             // read; cleared after the read where column blocks differ in size
     float* x;
     int32_t nx, ny;
 };

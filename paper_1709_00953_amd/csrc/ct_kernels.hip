@@ -1289,6 +1289,20 @@ __device__ __forceinline__ void fin_body(const DGeom& G, const FinArgs& f, const
         }
         const size_t gix = ((size_t)(f.box.z0 + lz) * f.ny + (f.box.y0 + ly)) * f.nx + f.box.x0 + lx;
         f.x[gix] = s / (float)f.n_groups;
+        if (G.mixed_boxes) {
+            // Column blocks of unequal sizes lay their (x, g) copies out
+            // differently, so this step's pairs could lie in the padding of a
+            // later step's copies.  The forward walks read padding only for
+            // segments that are zero up to float32 rounding; clearing both
+            // copies here keeps the whole buffer zero between steps, so that
+            // each step is a function of x, z and r alone.
+            const int li1 = xg_copy(nxJ, nyJ, nzJ) + xg_pad(nxJ, nyJ, nzJ) + (lz * nxJ + lx) * nyJ + ly;
+            for (int g = 0; g < f.n_groups; ++g) {
+                float2* slot = f.xg + (size_t)g * f.xg_stride;
+                slot[li] = make_float2(0.f, 0.f);
+                slot[li1] = make_float2(0.f, 0.f);
+            }
+        }
     }
 }
 

@@ -218,6 +218,50 @@ def test_epochs_are_bitwise_reproducible(ct):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("name,sync", [("fan_curved", "column"), ("cone", "epoch")])
+def test_checkpoint_resume_is_bitwise(ct, name, sync):
+    """A solver carries x, z and r from one epoch to the next and nothing
+    else, so saving them after epoch k and restoring them into a fresh solver
+    (through ct_solver_state's pointers) continues bit for bit like an
+    uninterrupted run."""
+    g, S = system(name)
+    G = ct.ct_geom_create(g)
+    _, y = phantom_y(g, S, 78)
+    sch = sampler.make_schedule(sampler.density(S.nnz_table(tau_for(g))), 5, 0.5, 1.0, 2, 1.0, 78)
+    sc = ct.ct_schedule_import(G, sch)
+    mode = ct.CT_SYNC_COLUMN if sync == "column" else ct.CT_SYNC_EPOCH
+    yd = dev(y)
+
+    def run(sol, x, e0, e1):
+        for e in range(e0, e1):
+            ct.ct_block_epoch(sol, sc, e, yd, x)
+
+    ref = ct.ct_solver_create(G, mode)
+    x_ref = torch.zeros(G.N, device="cuda")
+    ct.ct_solver_reset(ref, yd)
+    run(ref, x_ref, 0, 5)
+    z_ref, r_ref = ct.ct_solver_state(ref)
+
+    a = ct.ct_solver_create(G, mode)
+    xa = torch.zeros(G.N, device="cuda")
+    ct.ct_solver_reset(a, yd)
+    run(a, xa, 0, 2)
+    za, ra = ct.ct_solver_state(a)
+    # the checkpoint, on the host (float32 -> float64 -> float32 is exact)
+    saved = tuple(host(t).astype(np.float32) for t in (xa, za, ra))
+    del a, za, ra
+
+    b = ct.ct_solver_create(G, mode)
+    ct.ct_solver_reset(b, yd)
+    zb, rb = ct.ct_solver_state(b)
+    zb.copy_(torch.as_tensor(saved[1], device="cuda"))
+    rb.copy_(torch.as_tensor(saved[2], device="cuda"))
+    xb = dev(saved[0])
+    run(b, xb, 2, 5)
+    torch.cuda.synchronize()
+    assert torch.equal(xb, x_ref) and torch.equal(zb, z_ref) and torch.equal(rb, r_ref)
+
+
 def test_solve_counts_updates_and_converges(ct):
     g, S = system("c1_par2d")
     G = ct.ct_geom_create(g)
