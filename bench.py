@@ -53,7 +53,7 @@ PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 TRAFFIC_KIB = {
     ("fan2d_512", "back"): {"fetch": 11456.0, "write": 2112.0,
                             "profile": "profiles/fan2d_512_back_projection_hbm_traffic.md"},
-    ("cone3d_256", "back"): {"fetch": 373023.0, "write": 853686.0,
+    ("cone3d_256", "back"): {"fetch": 378970.0, "write": 886904.0,
                              "profile": "profiles/cone3d_256_counters.md"},
 }
 SERVE_FAN = (256, 384, 512, 768, 1024)

@@ -967,9 +967,10 @@ __device__ __forceinline__ void view_params3(const DGeom& G, const Tile& tl, con
     P.dvs = (float)(G.pv * isdd);
 }
 
-// Clip length of a staged ray with the voxel at offsets (du, dv); for a zero
-// direction component (careful views only) the ray stays in the source's slab
-// of that axis, so the voxel (indices vi) meets it only in that slab.
+// Clipped parameter extent of a staged ray in the voxel at offsets (du, dv)
+// (times the ray's |d| it is the intersection length); for a zero direction
+// component (careful views only) the ray stays in the source's slab of that
+// axis, so the voxel (indices vi) meets it only in that slab.
 __device__ __forceinline__ float clip3(float du, float dv, const float4& q0, const float4& q1,
                                        const float4& q2, const ViewP3& P, const int vi[3],
                                        bool careful) {
@@ -995,7 +996,12 @@ __device__ __forceinline__ float clip3(float du, float dv, const float4& q0, con
             }
         }
     }
-    return fmaxf(hi - lo, 0.f) * q2.y;
+    return fmaxf(hi - lo, 0.f);
+}
+
+// float4 at byte offset `b` of an LDS array
+__device__ __forceinline__ float4 lds_f4(const float4* base, int b) {
+    return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(base) + b);
 }
 
 template <class BA>
@@ -1125,7 +1131,8 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
                         const float rv = ldu(rview, (unsigned)(iv * G.nu + iu));
                         rc0[t] = make_float4(al[0], al[1], al[2], w[0]);
                         rc1[t] = make_float4(be[0], be[1], be[2], w[1]);
-                        rc2[t] = make_float4(w[2], nrm, rv, __int_as_float(zero));
+                        // |d| r: the length scale and the residual in one factor
+                        rc2[t] = make_float4(w[2], nrm * rv, 0.f, __int_as_float(zero));
                     }
                     __syncthreads();
                     const int ua = max(ulo, cu0), ub = min(uhi, cu1 - 1);
@@ -1138,27 +1145,27 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
                                       fmaf(-dA, fmaf((float)(ua - P.uref), P.dus, P.usr), dBu);
                     const float dv0 = (float)fma((double)(va - P.vref), P.slv, P.D0v) +
                                       fmaf(-dA, fmaf((float)(va - P.vref), P.dvs, P.vsr), dBv);
-                    // the rectangle row by row in one flat loop: the offsets
-                    // (exact small integers) are kept as floats and the LDS
-                    // index jumps to the next row at the end of one; one copy
-                    // of the loop per kind of view (a uniform branch)
-                    const int li0 = (va - cv0) * pw + (ua - cu0);
-                    const int li_end = li0 + (vb - va + 1) * pw;     // where the last wrap lands
-                    const int jump = pw - nu_w + 1;
+                    // the rectangle row by row in one flat loop: the column
+                    // offset (an exact small integer) is kept as a float, dv
+                    // steps by stv at the end of a row, and the LDS byte
+                    // offset jumps to the next row there; one copy of the
+                    // loop per kind of view (a uniform branch)
+                    const int lb0 = ((va - cv0) * pw + (ua - cu0)) * 16;
+                    const int lb_end = lb0 + (vb - va + 1) * pw * 16;   // where the last wrap lands
+                    const int jump = (pw - nu_w + 1) * 16;
                     const float last = (float)(nu_w - 1);
                     auto candidates = [&](auto careful_c) {
-                        float kuf = 0.f, kvf = 0.f;
-                        int li = li0;
+                        float kuf = 0.f, dv = dv0;
+                        int lb = lb0;
                         do {
                             const float du = fmaf(kuf, stu, du0);
-                            const float dv = fmaf(kvf, stv, dv0);
-                            const float4 q0 = rc0[li], q1 = rc1[li], q2 = rc2[li];
-                            acc = fmaf(clip3(du, dv, q0, q1, q2, P, vi, decltype(careful_c)::value), q2.z, acc);
+                            const float4 q0 = lds_f4(rc0, lb), q1 = lds_f4(rc1, lb), q2 = lds_f4(rc2, lb);
+                            acc = fmaf(clip3(du, dv, q0, q1, q2, P, vi, decltype(careful_c)::value), q2.y, acc);
                             const bool wrap = kuf == last;
                             kuf = wrap ? 0.f : kuf + 1.f;
-                            kvf = wrap ? kvf + 1.f : kvf;
-                            li += wrap ? jump : 1;
-                        } while (li != li_end);
+                            dv = wrap ? dv + stv : dv;
+                            lb += wrap ? jump : 16;
+                        } while (lb != lb_end);
                     };
                     if (careful) candidates(std::true_type{});
                     else candidates(std::false_type{});
