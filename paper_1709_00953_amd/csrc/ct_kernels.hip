@@ -623,6 +623,25 @@ struct ViewP {
     int32_t view, u0, u1, flags;
 };
 
+// Curved fan, views with no axis-parallel ray whose candidates stay within
+// 2e-2 rad of a reference bin kr near the tile's shadow (flag bit 1): the
+// view's frame turned to that bin's ray, stored over (Ac, Bc, ax, ay) of the
+// ViewP.  With (p, q) the reference ray's direction terms (its Ray2B), a
+// point (A, B) of the view frame lies at lateral offset X = p B - q A and
+// depth R = p A + q B from it, both affine in the voxel offsets; the ray of
+// bin b, turned from it by e = pu (b - kr) (the bins are equi-angular), passes
+// the point at signed distance X cos e - R sin e.  For |e| <= 2e-2 the cubic
+// sine and quadratic cosine are exact to 3e-11 and 7e-9 (times distances
+// below a metre and a tile), so the distance needs no float64 product per
+// candidate, and a candidate reads only K, S, M of its bin and r.
+struct FanC {
+    float Xx, Xy, Yx, Yy;         // X and R per voxel step along x and y
+    float Xc, Rc;                 // X and R at the tile centre
+    int32_t kr;                   // reference bin
+    float pu;                     // bin pitch (rad)
+};
+static_assert(sizeof(FanC) <= 4 * sizeof(double), "FanC overlays Ac, Bc, ax, ay");
+
 template <int KIND>
 __device__ __forceinline__ void view_params(const DGeom& G, const Tile& tl, double cx, double cy,
                                             double dt, ViewP& P) {
@@ -693,6 +712,27 @@ __device__ __forceinline__ void view_params(const DGeom& G, const Tile& tl, doub
     P.bxs = (float)bxs;
     P.bys = (float)bys;
     P.W = (float)fmin(W, 1e9) + 2e-3f + 1e-6f * fabsf((float)bc);
+    if constexpr (KIND == kFanCurved) {
+        // candidates lie within W + 4 (|bxs| + |bys|) bins of bc (voxel
+        // offsets at most 4 from the tile centre)
+        const int kr = min(max((int)floor(bc + 0.5), 0), G.nu - 1);
+        const double emax = G.pu * (fabs(bc - kr) + W + 4.0 * (fabs(bxs) + fabs(bys)) + 1.0);
+        if (!(P.flags & 1) && emax <= 2e-2) {
+            const Ray2B& Rr = G.ray2b[(size_t)tl.view * G.nu + kr];
+            const double p = Rr.p, q = Rr.q;
+            FanC f;
+            f.Xx = (float)(p * P.bx - q * P.ax);
+            f.Xy = (float)(p * P.by - q * P.ay);
+            f.Yx = (float)(p * P.ax + q * P.bx);
+            f.Yy = (float)(p * P.ay + q * P.by);
+            f.Xc = (float)(p * P.Bc - q * P.Ac);
+            f.Rc = (float)(p * P.Ac + q * P.Bc);
+            f.kr = kr;
+            f.pu = (float)G.pu;
+            __builtin_memcpy(&P.Ac, &f, sizeof f);
+            P.flags |= 2;
+        }
+    }
 }
 
 // Back-projection work-group for tile `tile` (of n_tiles) of group gi: NW
@@ -756,13 +796,37 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
                 const int u0 = __builtin_amdgcn_readfirstlane(P.u0);
                 const int u1 = __builtin_amdgcn_readfirstlane(P.u1);
                 const int vflags = __builtin_amdgcn_readfirstlane(P.flags);
-                const double A = fma(lyd, P.ay, fma(lxd, P.ax, P.Ac));
-                const double B = fma(lyd, P.by, fma(lxd, P.bx, P.Bc));
                 const float beta = fmaf(lyf, P.bys, fmaf(lxf, P.bxs, P.bc));
                 const int blo = max((int)ceilf(beta - P.W), u0);
                 const int bhi = min((int)floorf(beta + P.W), u1 - 1);
                 const Ray2B* RB = G.ray2b + (size_t)view * G.nu;
                 const float* rr = a.r + (size_t)view * G.nu;
+                if (KIND == kFanCurved && (vflags & 2)) {
+                    if (blo <= bhi) {
+                        FanC f;
+                        __builtin_memcpy(&f, &P.Ac, sizeof f);
+                        const float Xs = f.Xc + fmaf(lyf, f.Xy, lxf * f.Xx);
+                        const float Rs = f.Rc + fmaf(lyf, f.Yy, lxf * f.Yx);
+                        // K, S, M (and the unused slab) of bin b: the second
+                        // half of its Ray2B
+                        const float4* KS = reinterpret_cast<const float4*>(RB);
+                        float ef = (float)(blo - f.kr);      // b - kr, an exact small integer
+                        for (int b = blo; b <= bhi; ++b) {
+                            const float4 k = ldu(KS, 2u * (unsigned)b + 1u);
+                            const float rv = ldu(rr, (unsigned)b);
+                            const float e = ef * f.pu;
+                            const float e2 = e * e;
+                            const float sn = e * fmaf(e2, -1.f / 6.f, 1.f);
+                            const float cs = fmaf(e2, -0.5f, 1.f);
+                            const float dlt = fmaf(cs, Xs, -sn * Rs);
+                            acc = fmaf(__builtin_amdgcn_fmed3f(k.y - fabsf(dlt * k.x), 0.f, k.z), rv, acc);
+                            ef += 1.f;
+                        }
+                    }
+                    continue;
+                }
+                const double A = fma(lyd, P.ay, fma(lxd, P.ax, P.Ac));
+                const double B = fma(lyd, P.by, fma(lxd, P.bx, P.Bc));
                 if (vflags & 1) {
                     for (int b = blo; b <= bhi; ++b) {
                         const Ray2B Rb = ldu(RB, (unsigned)b);
