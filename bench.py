@@ -51,7 +51,7 @@ BATCH_SIZES = (128, 256, 384, 512, 768, 1024)
 # An entry holds only for the kernel version the counters were taken on.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 TRAFFIC_KIB = {
-    ("fan2d_512", "back"): {"fetch": 11456.0, "write": 2112.0,
+    ("fan2d_512", "back"): {"fetch": 12565.0, "write": 6208.0,
                             "profile": "profiles/fan2d_512_back_projection_hbm_traffic.md"},
     ("cone3d_256", "back"): {"fetch": 378970.0, "write": 886904.0,
                              "profile": "profiles/cone3d_256_counters.md"},
