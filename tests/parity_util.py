@@ -36,6 +36,14 @@ def geom_fan_flat():
                         pu_flat=3.2)
 
 
+# Fine pixels on a curved fan (0.5 mm voxels, 1e-3 rad bins, source at
+# 500 mm): every view's candidate bins lie within 2e-2 rad of a bin near the
+# tile's shadow, so the back-projection forms its ray distances in float32
+# in that bin's frame; the coarser fans here keep the float64 form.
+def geom_fan_fine():
+    return inputs.fan2d(64, 0.5, 120, 96, 1e-3, 500.0, 1000.0, m=6, bx=3, by=2)
+
+
 def geom_cone():
     return inputs.cone3d(40, 3.2, 120, 60, 6.4, 500.0, 1000.0, m=6, bz=3, bxy=2)
 
@@ -62,7 +70,8 @@ def geom_cone_axis():
     return inputs.cone3d(24, 1.0, 8, 41, 1.0, 100.0, 200.0, m=4, bz=2, bxy=2)
 
 
-GEOMS = {"c1_par2d": geom_c1, "fan_curved": geom_fan_curved, "fan_flat": geom_fan_flat,
+GEOMS = {"c1_par2d": geom_c1, "fan_curved": geom_fan_curved, "fan_fine": geom_fan_fine,
+         "fan_flat": geom_fan_flat,
          "cone": geom_cone, "par_axis": geom_par_axis, "fan_axis": geom_fan_axis,
          "fan_flat_axis": geom_fan_flat_axis, "cone_axis": geom_cone_axis}
 

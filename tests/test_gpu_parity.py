@@ -173,6 +173,7 @@ def _run_pair(ct, name, epochs, alpha, gamma, s, b, seed, sync="column",
     ("fan_flat", 12, 0.6, 1.0, 2, 2.0, 2100, "epoch", sampler.DENSITY),
     ("cone", 10, 1.0, 1.0, 3, 1.0, 3000, "column", sampler.DENSITY),
     ("fan_curved", 15, 0.5, 1.0, 2, 1.0, 2002, "column", "area"),
+    ("fan_fine", 12, 0.5, 1.0, 2, 1.0, 2003, "column", sampler.DENSITY),
     ("cone", 6, 0.5, 1.0, 2, 1.0, 3001, "column", "area"),
 ])
 def test_epoch_parity(ct, case):
