@@ -32,6 +32,7 @@ JOBS = [
     ("slice32", lambda: inputs.slice_fan(32), "column", "density", 1.0, 2, 1.0, 5, 0),
     ("slice48", lambda: inputs.slice_fan(48), "epoch", "uniform", 0.5, 1, 0.5, 4, 0),
     ("slice80", lambda: inputs.slice_fan(80), "column", "density", 1.0, 2, 1.0, 6, 2),
+    ("fan_fine", GEOMS["fan_fine"], "column", "density", 0.5, 2, 1.0, 4, 0),
 ]
 
 
