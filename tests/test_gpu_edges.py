@@ -48,7 +48,7 @@ def run_epochs(ct, g, y, sch, E, x0=None, sync="column"):
     return host(xd), host(z), host(r)
 
 
-@pytest.mark.parametrize("name", ["c1_par2d", "fan_curved", "fan_flat", "cone"])
+@pytest.mark.parametrize("name", ["c1_par2d", "fan_curved", "fan_fine", "fan_flat", "cone"])
 def test_zero_data_stays_zero(ct, name):
     g, S = system(name)
     P = sampler.density(S.nnz_table(tau_for(g)))

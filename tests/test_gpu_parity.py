@@ -219,7 +219,7 @@ def test_epochs_are_bitwise_reproducible(ct):
     assert np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("name,sync", [("fan_curved", "column"), ("cone", "epoch")])
+@pytest.mark.parametrize("name,sync", [("fan_curved", "column"), ("fan_fine", "column"), ("cone", "epoch")])
 def test_checkpoint_resume_is_bitwise(ct, name, sync):
     """A solver carries x, z and r from one epoch to the next and nothing
     else, so saving them after epoch k and restoring them into a fresh solver
