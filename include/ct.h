@@ -145,8 +145,13 @@ int ct_block_back(ct_geom* geom, const int32_t* row_blocks, int32_t n_rb, int32_
  * ceil(gamma n) are used; for each, ceil(alpha m) successive draws without
  * replacement of row blocks with weight P(I,J) (zero weight never drawn),
  * cut into consecutive groups of group_size; beta_G = b sum_{I in G} P(I,J).
- * Uniform sampling gives every row block weight 1; mixed sampling uses
- * P_I + theta (P_max - P_I) with theta = min(1, epoch*theta_step) (Sec. III-F).
+ * Uniform sampling gives every row block weight 1.  Mixed sampling
+ * (Sec. III-D) gives row block I the weight P_I + theta (P_max - P_I), with
+ * theta = min(1, epoch*theta_step) and P_max the largest P(., J) among the
+ * row blocks of I's projection: row blocks whose tiles cover the same set of
+ * views are the sub-detector areas of one projection.  A sub-area that J's
+ * shadow misses gets theta P_max; a projection J does not reach keeps weight
+ * 0.  beta always uses P.
  * Random numbers: SplitMix64 as a counter-based generator,
  * u64 = mix(seed + (ctr+1) * 0x9E3779B97F4A7C15), ctr = epoch*2^32 + k. */
 enum { CT_SAMPLE_DENSITY = 0, CT_SAMPLE_UNIFORM = 1, CT_SAMPLE_MIXED = 2 };
@@ -204,7 +209,10 @@ typedef struct ct_solver_params {
 
 typedef struct ct_solver ct_solver;
 
-/* Device workspace (bytes, 256-aligned) a solver needs for this geometry. */
+/* Device workspace (bytes, 256-aligned) a solver needs for this geometry:
+ * the partial projections z^j of every column block (Alg. 4), the residual
+ * r, and the per-group buffers of one column-block step (the group
+ * gradients g_J, A g and the float64 partial sums of Eq. 11). */
 int ct_solver_workspace_bytes(const ct_geom* geom, const ct_solver_params* params,
                               size_t* bytes);
 /* workspace: caller-owned device buffer of at least that many bytes, kept
@@ -263,13 +271,24 @@ typedef struct ct_solve_stats {
     int32_t epochs_run;
     double rel_residual;        /* last checked true relative residual    */
     int64_t ray_voxel_updates;  /* 2 * sum over groups of nnz(A_{I_G}^J)  */
+    double* r_norm;             /* in: host array of params->sched.epochs
+                                   doubles, or NULL; out: ||r||_2 of the
+                                   tracked residual after each epoch run   */
 } ct_solve_stats;
 
-/* x (device, [N]) starts from zero.  Allocates its workspace with
- * hipMalloc.  Returns CT_NOT_CONVERGED if the cap was reached before
- * rel_tol (with check_every > 0).  Synchronous. */
+/* The whole iteration of Alg. 4-6: the density table (Sec. II-C), the
+ * schedule drawn from it (Alg. 5/6), then epochs from x = 0, z^j = 0, r = y
+ * until the cap or, every check_every epochs, until the true relative
+ * residual ||y - A x|| / ||y|| (reading C16: the tracked r of Sec. II-B is an
+ * approximation) is <= rel_tol.  x: device [N], overwritten.  workspace:
+ * caller-owned device memory of ct_solver_workspace_bytes(geom,
+ * &params->solver) bytes, 256-byte aligned, not retained after the call.
+ * The schedule's device tables and, on first use, the geometry's are
+ * allocated by the library.  stats may be NULL.  Returns CT_NOT_CONVERGED if
+ * the cap was reached before rel_tol (with check_every > 0), CT_EINVAL for a
+ * bad argument or a short workspace (nothing enqueued).  Synchronous. */
 int ct_solve(ct_geom* geom, const ct_solve_params* params, const float* y, float* x,
-             ct_solve_stats* stats, void* stream);
+             void* workspace, size_t ws_bytes, ct_solve_stats* stats, void* stream);
 
 /* ---- batched epochs --------------------------------------------------------
  * Many independent jobs (each its own geometry, solver, schedule, y and x)

@@ -12,8 +12,14 @@ The schedule depends only on the density table, the parameters and the seed
       consecutive groups of s (the last one may be shorter).
 * C5  a group's relaxation is beta_G = b * sum_{I in G} P(I,J).
 * C6  P(I,J) = nnz(A_I^J) / sum_I' nnz(A_I'^J).
-* Mixed sampling (Sec. III-F): weight P_I + theta (P_max - P_I) for the row
-  blocks with P_I > 0, theta = min(1, epoch * theta_step).
+* Mixed sampling (Sec. III-D): row block I of projection p gets the weight
+  P_I + theta (P_max(p) - P_I), where P_max(p) is the largest P among the
+  row blocks of the same projection (the sub-detector areas of one view, or
+  of one set of views) and theta = min(1, epoch * theta_step).  A row block
+  with P_I = 0 in a projection with P_max(p) > 0 has weight theta P_max(p),
+  so at theta = 1 every sub-area of a projection is equally likely (the
+  caption of the sampling-comparison figure); a projection that J does not
+  reach at all keeps weight 0.  beta still uses P (C5).
 
 Random numbers come from SplitMix64 (Steele, Lea and Flood, 2014) used as a
 counter-based generator: the k-th output for key ``seed`` is
@@ -101,11 +107,54 @@ class Schedule:
             yield int(self.cols[c]), groups
 
 
+def projection_of(row_blocks) -> np.ndarray:
+    """Projection of every row block, for mixed sampling (Sec. III-D).
+
+    Row blocks whose tiles cover the same set of views are sub-detector
+    areas of one projection.  Returns, per row block, the index of the first
+    row block with the same set of views.
+    """
+    first = {}
+    out = np.zeros(len(row_blocks), dtype=np.int32)
+    for I, tiles in enumerate(row_blocks):
+        key = tuple(sorted(set(int(t[0]) for t in np.asarray(tiles).reshape(-1, 5))))
+        out[I] = first.setdefault(key, I)
+    return out
+
+
+def draw_weights(P: np.ndarray, J: int, theta: float, sampling: int, proj=None) -> List[float]:
+    """Weight of every row block in the draws for column block J: P(I,J)
+    (importance sampling, Sec. II-C), 1 (uniform), or the mixed weight
+    P_I + theta (P_max(p) - P_I) of Sec. III-D, P_max(p) the largest P(., J)
+    in I's projection p (0 for a projection J does not reach)."""
+    m = P.shape[0]
+    if sampling == UNIFORM:
+        return [1.0] * m
+    if sampling == MIXED:
+        pmax = {}
+        for I in range(m):
+            pmax[proj[I]] = max(pmax.get(proj[I], 0.0), float(P[I, J]))
+        return [(float(P[I, J]) + theta * (pmax[proj[I]] - float(P[I, J]))) if pmax[proj[I]] > 0
+                else 0.0 for I in range(m)]
+    return [float(P[I, J]) for I in range(m)]
+
+
 def make_schedule(P: np.ndarray, epochs: int, alpha: float, gamma: float, s: int, b: float,
-                  seed: int, sampling: int = DENSITY, theta_step: float = 0.0) -> Schedule:
-    """Draw the whole schedule (Alg. 5 with s = 1, Alg. 6 in general)."""
+                  seed: int, sampling: int = DENSITY, theta_step: float = 0.0,
+                  proj=None) -> Schedule:
+    """Draw the whole schedule (Alg. 5 with s = 1, Alg. 6 in general).
+
+    ``proj`` (mixed sampling only): the projection of every row block, as
+    ``projection_of`` gives it.
+    """
     P = np.asarray(P, dtype=np.float64)
     m, n = P.shape
+    if sampling == MIXED:
+        if proj is None:
+            raise ValueError("mixed sampling needs the projection of every row block")
+        proj = [int(p) for p in np.asarray(proj).reshape(-1)]
+        if len(proj) != m:
+            raise ValueError("proj has the wrong length")
     ecp, cols, cgp, grp, rbs, beta = [0], [], [0], [0], [], []
     for e in range(epochs):
         k = 0
@@ -123,15 +172,7 @@ def make_schedule(P: np.ndarray, epochs: int, alpha: float, gamma: float, s: int
             perm[i], perm[j] = perm[j], perm[i]
         theta = min(1.0, e * theta_step)
         for J in perm[:count_of(gamma, n)]:
-            if sampling == UNIFORM:
-                w = [1.0] * m
-            elif sampling == MIXED:
-                pos = [P[I, J] for I in range(m) if P[I, J] > 0]
-                pmax = max(pos) if pos else 0.0
-                w = [(P[I, J] + theta * (pmax - P[I, J])) if P[I, J] > 0 else 0.0
-                     for I in range(m)]
-            else:
-                w = [P[I, J] for I in range(m)]
+            w = draw_weights(P, J, theta, sampling, proj)
             avail = [I for I in range(m) if w[I] > 0]
             K = min(count_of(alpha, m), len(avail))
             draws: List[int] = []

@@ -1111,6 +1111,21 @@ static int sched_draw(const ct_geom* g, const ct_sched_params* p, const std::vec
     const uint64_t seed = p->seed;
     std::vector<int> perm(n), avail;
     std::vector<double> w(m);
+    // mixed sampling (Sec. III-D): row blocks whose tiles cover the same set
+    // of views are sub-detector areas of one projection; proj[I] is the first
+    // row block with I's set of views, and P_max is taken within it
+    std::vector<int> proj(m);
+    std::vector<double> pmax(m);
+    if (p->sampling == CT_SAMPLE_MIXED) {
+        std::map<std::vector<int32_t>, int> first;
+        for (int I = 0; I < m; ++I) {
+            std::vector<int32_t> vs;
+            for (int t = g->rb_tile_ptr[I]; t < g->rb_tile_ptr[I + 1]; ++t) vs.push_back(g->tiles[t].view);
+            std::sort(vs.begin(), vs.end());
+            vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
+            proj[I] = first.emplace(std::move(vs), I).first->second;
+        }
+    }
     for (int e = 0; e < p->epochs; ++e) {
         uint64_t k = 0;
         const uint64_t base = (uint64_t)e << 32;
@@ -1123,13 +1138,17 @@ static int sched_draw(const ct_geom* g, const ct_sched_params* p, const std::vec
         const int ncol = count_of(p->gamma, n);
         for (int ci = 0; ci < ncol; ++ci) {
             const int J = perm[ci];
-            double pmax = 0.0;
-            for (int I = 0; I < m; ++I) pmax = std::max(pmax, P[(size_t)I * n + J]);
+            if (p->sampling == CT_SAMPLE_MIXED) {
+                for (int I = 0; I < m; ++I) pmax[I] = 0.0;
+                for (int I = 0; I < m; ++I) pmax[proj[I]] = std::max(pmax[proj[I]], P[(size_t)I * n + J]);
+            }
             for (int I = 0; I < m; ++I) {
                 const double pij = P[(size_t)I * n + J];
                 if (p->sampling == CT_SAMPLE_UNIFORM) w[I] = 1.0;
-                else if (p->sampling == CT_SAMPLE_MIXED) w[I] = pij > 0 ? pij + theta * (pmax - pij) : 0.0;
-                else w[I] = pij;
+                else if (p->sampling == CT_SAMPLE_MIXED) {
+                    const double pm = pmax[proj[I]];
+                    w[I] = pm > 0 ? pij + theta * (pm - pij) : 0.0;
+                } else w[I] = pij;
             }
             avail.clear();
             for (int I = 0; I < m; ++I)
@@ -1605,27 +1624,25 @@ extern "C" int ct_true_residual(ct_solver* s, const float* y, const float* x, do
 // ---------------------------------------------------------------------------
 // whole solve
 // ---------------------------------------------------------------------------
-extern "C" int ct_solve(ct_geom* g, const ct_solve_params* p, const float* y, float* x, ct_solve_stats* st_out,
-                        void* stream) {
-    if (!g || !p || !y || !x) return fail(CT_EINVAL, "NULL argument");
+extern "C" int ct_solve(ct_geom* g, const ct_solve_params* p, const float* y, float* x, void* ws,
+                        size_t ws_bytes, ct_solve_stats* st_out, void* stream) {
+    if (!g || !p || !y || !x || !ws) return fail(CT_EINVAL, "NULL argument");
     if (p->check_every < 0) return fail(CT_EINVAL, "check_every < 0");
     if (!(p->tau >= 0)) return fail(CT_EINVAL, "tau < 0");
-    int rc = check_device(g);
+    int rc = sched_check_params(&p->sched);
     if (rc) return rc;
+    size_t bytes = 0;
+    if ((rc = ct_solver_workspace_bytes(g, &p->solver, &bytes))) return rc;
+    if (ws_bytes < bytes) return fail(CT_EINVAL, "workspace too small (%zu < %zu)", ws_bytes, bytes);
+    if (((uintptr_t)ws & 255) != 0) return fail(CT_EINVAL, "workspace must be 256-byte aligned");
+    if ((rc = check_device(g))) return rc;
     hipStream_t st = (hipStream_t)stream;
     std::vector<int64_t> nnz((size_t)g->m * g->n);
     if ((rc = ct_geom_block_nnz(g, p->tau, nnz.data(), stream))) return rc;
     ct_schedule* sc = nullptr;
     if ((rc = ct_schedule_create(g, &p->sched, nnz.data(), &sc))) return rc;
-    size_t bytes = 0;
-    ct_solver_workspace_bytes(g, &p->solver, &bytes);
-    void* ws = nullptr;
-    if (hipMalloc(&ws, bytes) != hipSuccess) {
-        ct_schedule_destroy(sc);
-        return fail(CT_ENOMEM, "hipMalloc(%zu) for the solver workspace failed", bytes);
-    }
     ct_solver* s = nullptr;
-    rc = ct_solver_create(g, &p->solver, ws, bytes, &s);
+    rc = ct_solver_create(g, &p->solver, ws, ws_bytes, &s);
     int64_t updates = 0;
     int run = 0;
     double rel = -1.0;
@@ -1636,6 +1653,20 @@ extern "C" int ct_solve(ct_geom* g, const ct_solve_params* p, const float* y, fl
         rc = ct_block_epoch(s, sc, e, y, x, stream);
         if (rc) break;
         run = e + 1;
+        if (st_out && st_out->r_norm) {
+            // ||r||^2 of the tracked residual: the second sum of the norm
+            // kernel, sum r^2, with the first taken against r itself
+            const int nblk = (int)std::min<int64_t>(kResBlocks, (g->M + 255) / 256);
+            double ab[2] = {0.0, 0.0};
+            if (launch_resnorm(s->r, s->r, g->M, s->part, nblk, st) != hipSuccess ||
+                launch_sum_pairs(s->part, nblk, s->part + 2 * kResBlocks, st) != hipSuccess ||
+                hipMemcpyAsync(ab, s->part + 2 * kResBlocks, sizeof ab, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                rc = fail(CT_EDEVICE, "residual norm of epoch %d", e);
+                break;
+            }
+            st_out->r_norm[e] = std::sqrt(ab[1]);
+        }
         for (int c = sc->ecp[e]; c < sc->ecp[e + 1]; ++c) {
             const int J = sc->cols[c];
             for (int k = sc->grp[sc->cgp[c]]; k < sc->grp[sc->cgp[c + 1]]; ++k)
@@ -1656,7 +1687,6 @@ extern "C" int ct_solve(ct_geom* g, const ct_solve_params* p, const float* y, fl
         st_out->ray_voxel_updates = updates;
     }
     ct_solver_destroy(s);
-    (void)hipFree(ws);
     ct_schedule_destroy(sc);
     if (rc) return rc;
     if (p->check_every > 0 && !converged) return CT_NOT_CONVERGED;

@@ -123,7 +123,8 @@ class ct_solve_params(ctypes.Structure):
 
 
 class ct_solve_stats(ctypes.Structure):
-    _fields_ = [("epochs_run", i32), ("rel_residual", f64), ("ray_voxel_updates", i64)]
+    _fields_ = [("epochs_run", i32), ("rel_residual", f64), ("ray_voxel_updates", i64),
+                ("r_norm", P)]
 
 
 _lib = None
@@ -165,7 +166,8 @@ def lib():
             "ct_server_tick": [P, P, ctypes.POINTER(ct_server_stats)],
             "ct_server_poll": [P, ctypes.POINTER(ct_server_done), i32, ctypes.POINTER(i32)],
             "ct_server_result": [P, i32, P],
-            "ct_solve": [P, ctypes.POINTER(ct_solve_params), P, P, ctypes.POINTER(ct_solve_stats), P],
+            "ct_solve": [P, ctypes.POINTER(ct_solve_params), P, P, P, ctypes.c_size_t,
+                         ctypes.POINTER(ct_solve_stats), P],
             "ct_solver_profile": [P, i32],
             "ct_solver_profile_read": [P, ctypes.POINTER(ct_kernel_times)],
             "ct_batch_create": [i32, ctypes.POINTER(P)],
@@ -473,14 +475,26 @@ def ct_solver_profile_read(solver: Solver) -> dict:
 
 
 def ct_solve(geom: Geom, params: ct_sched_params, y, x, sync=CT_SYNC_COLUMN, tau=0.0,
-             rel_tol=0.0, check_every=0, stream=None):
+             rel_tol=0.0, check_every=0, workspace=None, stream=None):
+    """Whole solve; the workspace is a caller tensor (allocated here if not
+    given).  Returns (status, stats) with the per-epoch ||r|| in stats."""
+    import torch
     sp = ct_solve_params(params, ct_solver_params(sync), float(tau), float(rel_tol), int(check_every))
+    nbytes = ct_solver_workspace_bytes(geom, sync)
+    if workspace is None:
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    base = workspace.data_ptr()
+    off = (-base) % 256
+    rn = np.zeros(max(1, params.epochs), dtype=np.float64)
     st = ct_solve_stats()
+    st.r_norm = rn.ctypes.data_as(P)
     rc = _check(lib().ct_solve(geom.handle, ctypes.byref(sp), _dev(y, geom.M, "y"),
-                               _dev(x, geom.N, "x"), ctypes.byref(st), _stream(stream)),
+                               _dev(x, geom.N, "x"), P(base + off), workspace.numel() - off,
+                               ctypes.byref(st), _stream(stream)),
                 allow=(CT_OK, CT_NOT_CONVERGED))
     return rc, {"epochs_run": st.epochs_run, "rel_residual": st.rel_residual,
-                "ray_voxel_updates": st.ray_voxel_updates}
+                "ray_voxel_updates": st.ray_voxel_updates,
+                "r_norm": rn[:st.epochs_run].copy()}
 
 
 # ----------------------------------------------------------------------------

@@ -130,7 +130,7 @@ def _circular_views(thetas, sid, sdd, third_axis=False):
 
 
 def sphere_views(n_views, radius, sdd, seed):
-    """Random source positions on a sphere (the paper's 3D trajectory, Sec. III-G).
+    """Random source positions on a sphere (the paper's 3D trajectory, Sec. III-E).
 
     Detector plane perpendicular to the source-centre line, centre at distance
     ``sdd`` from the source on the far side of the rotation centre.
@@ -224,12 +224,12 @@ def fan2d(n=512, pitch=0.5, n_views=720, nu=768, dgamma=1e-3, sid=500.0, sdd=100
 
 
 def cone3d(n=256, pitch=0.5, n_views=360, nd=384, pd=1.0, sid=500.0, sdd=1000.0,
-           m=12, bz=8, bxy=1, span_deg=360.0):
+           m=12, bz=8, bxy=1, span_deg=360.0, u_split=1, v_split=1):
     th = np.deg2rad(span_deg) * np.arange(n_views) / n_views
     half = n * pitch / 2
     return Geometry(CONE3D_FLAT, n, n, n, pitch, pitch, pitch, -half, -half, -half,
                     nd, nd, pd, pd, _circular_views(th, sid, sdd, third_axis=True),
-                    angle_group_blocks(n_views, m, nd, nd),
+                    angle_group_blocks(n_views, m, nd, nd, u_split=u_split, v_split=v_split),
                     box_blocks(n, n, n, bxy, bxy, bz))
 
 
@@ -275,7 +275,7 @@ def config_paper2d():
 
 
 def config_paper3d(n=128, nd=202, n_views=720, seed=5300):
-    """The paper's 3D setting (Sec. III-G): n^3 voxels over a 32^3 volume, a
+    """The paper's 3D setting (Sec. III-E): n^3 voxels over a 32^3 volume, a
     square detector of side 101 (nd x nd pixels), 720 source positions drawn
     at random on a sphere of radius 66, detector plane perpendicular at
     distance 132; every projection one row block (no detector split) x

@@ -95,16 +95,22 @@ def test_primitive_argument_errors_enqueue_nothing():
 
 @pytest.mark.parametrize("samp", [sampler.DENSITY, sampler.UNIFORM, sampler.MIXED])
 @pytest.mark.parametrize("alpha,gamma,s", [(0.5, 1.0, 1), (1.0, 0.5, 3), (0.3, 0.75, 2)])
-def test_library_sampler_equals_oracle_sampler(samp, alpha, gamma, s):
-    g = inputs.fan2d(128, 2.0, 60, 64, 4e-3, 500.0, 1000.0, m=10, bx=3, by=2)
+@pytest.mark.parametrize("u_split", [1, 2, 3])
+def test_library_sampler_equals_oracle_sampler(samp, alpha, gamma, s, u_split):
+    """u_split > 1: every view group's detector is cut into sub-areas, so
+    mixed sampling takes P_max over the sub-areas of one projection."""
+    g = inputs.fan2d(128, 2.0, 60, 64, 4e-3, 500.0, 1000.0, m=10 // u_split, bx=3, by=2,
+                     u_split=u_split)
     G = ct.ct_geom_create(g)
     rng = np.random.default_rng(101)
     nnz = rng.integers(0, 5000, size=(G.m, G.n))
     nnz[3, :] = 0
     nnz[:, 4] = 0
+    nnz[0, 1] = 0                       # a sub-area J misses in a projection it reaches
     params = ct.sched_params(9, alpha, gamma, s, 2.5, samp, 0.125, seed=987654321)
     ex = ct.ct_schedule_export(ct.ct_schedule_create(G, params, nnz))
-    o = sampler.make_schedule(sampler.density(nnz), 9, alpha, gamma, s, 2.5, 987654321, samp, 0.125)
+    o = sampler.make_schedule(sampler.density(nnz), 9, alpha, gamma, s, 2.5, 987654321, samp, 0.125,
+                              proj=sampler.projection_of(g.row_blocks))
     for k in ("epoch_col_ptr", "cols", "col_group_ptr", "group_rb_ptr", "rbs"):
         assert np.array_equal(ex[k], getattr(o, k)), k
     assert np.array_equal(ex["beta"], o.beta)          # bitwise: same FP64 formula and order

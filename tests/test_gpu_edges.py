@@ -9,7 +9,7 @@ import pytest
 
 from oracle import csgd, sampler, siddon
 from paper_1709_00953_amd import inputs
-from tests.parity_util import rel_l2, system, tau_for
+from tests.parity_util import max_rel, rel_l2, system, tau_for
 
 pytestmark = pytest.mark.gpu
 
@@ -114,6 +114,7 @@ def test_tiny_geometries(ct, name):
             got = host(yd)
             if np.linalg.norm(ref) > 0:
                 assert rel_l2(got[rows], ref) <= 1e-5, (I, J)
+                assert max_rel(got[rows], ref) <= 1e-5, (I, J)
             else:
                 assert np.all(got[rows] == 0), (I, J)
             gd = torch.full((G.N,), -3.0, device="cuda")
@@ -122,6 +123,7 @@ def test_tiny_geometries(ct, name):
             gb = host(gd)[S.vox[J]]
             if np.linalg.norm(refb) > 0:
                 assert rel_l2(gb, refb) <= 1e-5, (I, J)
+                assert max_rel(gb, refb) <= 1e-5, (I, J)
             else:
                 assert np.all(gb == 0), (I, J)
     nnz = S.nnz_table(tau_for(g))

@@ -11,7 +11,7 @@ import pytest
 
 from oracle import area, csgd, rays, sampler, siddon
 from paper_1709_00953_amd import inputs
-from tests.parity_util import rel_l2, tau_for
+from tests.parity_util import max_rel, rel_l2, tau_for
 
 pytestmark = pytest.mark.gpu
 
@@ -57,6 +57,7 @@ def test_paper_projectors(ct, name):
         ref = csgd.block_fwd(S, rbs, J, x.astype(np.float64))
         if np.linalg.norm(ref) > 0:
             assert rel_l2(y[rows], ref) <= 1e-5, (rbs[:4], J)
+            assert max_rel(y[rows], ref) <= 1e-5, (rbs[:4], J)
         other = np.setdiff1d(np.arange(G.M), rows)
         assert np.all(y[other] == 7.0)
         gd = torch.full((G.N,), 7.0, device="cuda")
@@ -66,6 +67,7 @@ def test_paper_projectors(ct, name):
         vox = S.vox[J]
         if np.linalg.norm(refb) > 0:
             assert rel_l2(gv[vox], refb) <= 1e-5, (rbs[:4], J)
+            assert max_rel(gv[vox], refb) <= 1e-5, (rbs[:4], J)
 
 
 def _epochs(ct, name, E, alpha, s, b, seed, P=None):
@@ -140,6 +142,7 @@ def test_paper3d_fullsize_sampled(ct):
     err = rel_l2(got[smp], A_s @ xJ)
     print(f"[paper3d] forward sampled: {err:.2e}", flush=True)
     assert err <= 1e-5
+    assert max_rel(got[smp], A_s @ xJ) <= 1e-5
     r = rng.normal(0.0, 1.0, g.n_rays).astype(np.float32)
     gd = torch.full((G.N,), 7.0, device="cuda")
     ct.ct_block_back(G, rbs, J, dev(r), gd)
@@ -154,3 +157,4 @@ def test_paper3d_fullsize_sampled(ct):
     err = rel_l2(gv[vsmp], np.array(ref))
     print(f"[paper3d] back sampled: {err:.2e}", flush=True)
     assert err <= 1e-5
+    assert max_rel(gv[vsmp], np.array(ref)) <= 1e-5

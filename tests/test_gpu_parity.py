@@ -9,7 +9,7 @@ import pytest
 
 from oracle import csgd, sampler
 from paper_1709_00953_amd import inputs
-from tests.parity_util import GEOMS, phantom_y, rel_l2, system, tau_for
+from tests.parity_util import GEOMS, max_rel, phantom_y, rel_l2, system, tau_for
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +47,7 @@ def test_block_fwd_parity(ct, name):
     rng = np.random.default_rng(1)
     x = rng.uniform(0.0, 1.0, g.n_vox).astype(np.float32)
     xd = dev(x)
-    worst = 0.0
+    worst = worst_el = 0.0
     for rbs, J in _pairs(g):
         print(f"[fwd] {name} rbs={rbs} J={J}", flush=True)
         yd = torch.full((G.M,), 7.0, device="cuda")
@@ -59,10 +59,12 @@ def test_block_fwd_parity(ct, name):
             assert np.all(y[rows] == 0)
         else:
             worst = max(worst, rel_l2(y[rows], ref))
+            worst_el = max(worst_el, max_rel(y[rows], ref))
         other = np.ones(G.M, bool)
         other[rows] = False
         assert np.all(y[other] == 7.0), "wrote outside the row blocks"
     assert worst <= 1e-5, worst
+    assert worst_el <= 1e-5, worst_el
 
 
 @pytest.mark.parametrize("name", list(GEOMS))
@@ -72,7 +74,7 @@ def test_block_back_parity(ct, name):
     rng = np.random.default_rng(2)
     r = rng.normal(0.0, 1.0, g.n_rays).astype(np.float32)
     rd = dev(r)
-    worst = 0.0
+    worst = worst_el = 0.0
     for rbs, J in _pairs(g):
         print(f"[back] {name} rbs={rbs} J={J}", flush=True)
         gd = torch.full((G.N,), -3.0, device="cuda")
@@ -84,10 +86,12 @@ def test_block_back_parity(ct, name):
             assert np.all(gv[vox] == 0)
         else:
             worst = max(worst, rel_l2(gv[vox], ref))
+            worst_el = max(worst_el, max_rel(gv[vox], ref))
         other = np.ones(G.N, bool)
         other[vox] = False
         assert np.all(gv[other] == -3.0), "wrote outside the column block"
     assert worst <= 1e-5, worst
+    assert worst_el <= 1e-5, worst_el
 
 
 @pytest.mark.parametrize("name", ["c1_par2d", "cone"])
@@ -141,7 +145,7 @@ def test_block_density_table(ct, name):
 
 
 def _run_pair(ct, name, epochs, alpha, gamma, s, b, seed, sync="column",
-              sampling=sampler.DENSITY, noise=0.01):
+              sampling=sampler.DENSITY, noise=0.01, theta_step=1.0 / 40):
     g, S = system(name)
     G = ct.ct_geom_create(g)
     x_true, y = phantom_y(g, S, seed, noise)
@@ -150,7 +154,8 @@ def _run_pair(ct, name, epochs, alpha, gamma, s, b, seed, sync="column",
         P, sampling = area.area_density(g), sampler.DENSITY
     else:
         P = sampler.density(S.nnz_table(tau_for(g)))
-    sch = sampler.make_schedule(P, epochs, alpha, gamma, s, b, seed, sampling, 1.0 / 40)
+    sch = sampler.make_schedule(P, epochs, alpha, gamma, s, b, seed, sampling, theta_step,
+                                proj=sampler.projection_of(g.row_blocks))
     ref = csgd.run(S, y.astype(np.float64), sch, sync=sync)
     sc = ct.ct_schedule_import(G, sch)
     sol = ct.ct_solver_create(G, ct.CT_SYNC_COLUMN if sync == "column" else ct.CT_SYNC_EPOCH)
@@ -175,11 +180,17 @@ def _run_pair(ct, name, epochs, alpha, gamma, s, b, seed, sync="column",
     ("fan_curved", 15, 0.5, 1.0, 2, 1.0, 2002, "column", "area"),
     ("fan_fine", 12, 0.5, 1.0, 2, 1.0, 2003, "column", sampler.DENSITY),
     ("cone", 6, 0.5, 1.0, 2, 1.0, 3001, "column", "area"),
+    # detector split into sub-areas: mixed sampling's P_max per projection,
+    # theta reaching 1 within the run
+    ("fan_split", 10, 0.5, 1.0, 2, 1.0, 2004, "column", sampler.MIXED, 0.125),
+    ("cone_split", 6, 0.5, 1.0, 3, 1.0, 3002, "epoch", sampler.MIXED, 0.25),
 ])
 def test_epoch_parity(ct, case):
-    name, E, a, gm, s, b, seed, sync, samp = case
+    name, E, a, gm, s, b, seed, sync, samp = case[:9]
+    th = case[9] if len(case) > 9 else 1.0 / 40
     print(f"[epochs] {case}", flush=True)
-    g, S, ref, x, z, r, x_true = _run_pair(ct, name, E, a, gm, s, b, seed, sync, samp)
+    g, S, ref, x, z, r, x_true = _run_pair(ct, name, E, a, gm, s, b, seed, sync, samp,
+                                           theta_step=th)
     err = rel_l2(x, ref.x)
     assert err <= 1e-4, err
     assert rel_l2(z, ref.z) <= 1e-4

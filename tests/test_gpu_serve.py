@@ -115,3 +115,46 @@ def test_server_rejects_job_over_budget(ct):
         ct.ct_server_submit(srv, g, ct.sched_params(5), y)
     with pytest.raises(ct.CtError):
         ct.ct_server_result(srv, 0)
+
+
+def test_served_jobs_match_oracle(ct):
+    """A served fan slice and a served cone against the FP64 oracle: the
+    oracle runs the schedule the server draws (same sampler, same density
+    table) for the epochs the job ran, on the same float32 y; x within 1e-4
+    and the retiring residual within the residual bound of the stopping
+    tests."""
+    from oracle import csgd, sampler, siddon
+    from tests.parity_util import rel_l2
+
+    specs = [("fan32", inputs.slice_fan(32), 1.0, 4, 1.0, 30, ct.CT_SYNC_COLUMN),
+             ("cone16", inputs.slice_cone(16), 1.0, 3, 2.0, 10, ct.CT_SYNC_COLUMN),
+             ("fan40e", inputs.slice_fan(40), 0.5, 1, 0.5, 16, ct.CT_SYNC_EPOCH)]
+    tau = 1e-5 * min(g.vx for _, g, *_ in specs)
+    srv = ct.ct_server_create(capacity=4, rel_tol=1e-3, check_every=4, tau=tau, graph=True)
+    jobs = {}
+    for k, (name, g, alpha, s, b, cap, sync) in enumerate(specs):
+        S = csgd.BlockSystem(siddon.system_matrix(g), g)
+        seed = inputs.seed_for(5, 50 + k)
+        y = (S.A @ inputs.phantom_for(g, seed)).astype(np.float32)
+        params = ct.sched_params(cap, alpha, 1.0, s, b, seed=seed)
+        jid = ct.ct_server_submit(srv, g, params, y, sync=sync)
+        jobs[jid] = (name, g, S, y, alpha, s, b, seed, sync)
+    done, ticks = [], 0
+    while len(done) < len(jobs):
+        ct.ct_server_tick(srv)
+        done += ct.ct_server_poll(srv)
+        ticks += 1
+        assert ticks < 400
+    for d in done:
+        name, g, S, y, alpha, s, b, seed, sync = jobs[d["id"]]
+        x = ct.ct_server_result(srv, d["id"]).astype(np.float64)
+        P = sampler.density(S.nnz_table(tau))
+        sch = sampler.make_schedule(P, d["epochs"], alpha, 1.0, s, b, seed)
+        ref = csgd.run(S, y.astype(np.float64), sch,
+                       sync="column" if sync == ct.CT_SYNC_COLUMN else "epoch")
+        err = rel_l2(x, ref.x)
+        rho = csgd.true_rel_residual(S, y.astype(np.float64), ref.x)
+        print(f"[serve-oracle] {name}: status {d['status']} epochs {d['epochs']} x rel {err:.2e} "
+              f"rho {d['rel_residual']:.4e} oracle {rho:.4e}", flush=True)
+        assert err <= 1e-4, name
+        assert abs(d["rel_residual"] - rho) <= 1e-4 * max(rho, 1.0)

@@ -206,6 +206,90 @@ def test_residual_update_identity():
     np.testing.assert_allclose(y[rows] - st.z[:, rows].sum(axis=0), lhs, rtol=1e-12, atol=1e-12)
 
 
+def _stacked(S, G, J):
+    """A_{I_G}^J as a dense array cut straight from the full A: the rows of
+    the group's row blocks stacked in group order, the columns of J."""
+    rows = np.concatenate([S.geom.row_block_rays(I) for I in G])
+    return S.A.toarray()[rows][:, S.geom.col_block_vox(J)], rows
+
+
+def test_group_step_orthogonality_and_identity():
+    """Alg. 6 with a group of three row blocks (given out of order): the step
+    is the exact line search of Eq. 10-11 on the stacked system, so with
+    beta = 1 the new residual of the group's rows is orthogonal to A_G g;
+    and the partial projections it records satisfy Eq. 13 on the stack,
+    y_G - A_G x^{n+1} = r_G^n - mu A_G^J g."""
+    g, S = _system("par2d")
+    assert g.m == 3
+    rng = np.random.default_rng(29)
+    x0 = rng.uniform(0, 1, g.n_vox)
+    y = S.A @ rng.uniform(0, 1, g.n_vox) + rng.normal(0, 0.1, g.n_rays)
+    G, J = [2, 0, 1], 1
+    AG, rows = _stacked(S, G, J)
+    for beta in (1.0, 0.6):
+        st = csgd.State(S, y, x0=x0)
+        r0 = st.r[rows].copy()
+        xnew, mu, _ = csgd.step_group(st, G, J, beta)
+        gvec = AG.T @ r0
+        q = AG @ gvec
+        x1 = x0.copy()
+        x1[S.vox[J]] = xnew
+        lhs = y[rows] - S.A[rows] @ x1
+        np.testing.assert_allclose(lhs, r0 - mu * q, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(y[rows] - st.z[:, rows].sum(axis=0), lhs, rtol=1e-12, atol=1e-12)
+        if beta == 1.0:
+            assert mu > 0
+            assert abs(q @ lhs) <= 1e-12 * np.linalg.norm(q) * np.linalg.norm(r0)
+
+
+def _epoch_schedule(cols_groups, beta=0.8):
+    """A one-epoch schedule from [(J, [G, ...]), ...]."""
+    ecp, cols, cgp, grp, rbs, bet = [0], [], [0], [0], [], []
+    for J, groups in cols_groups:
+        for G in groups:
+            rbs.extend(G)
+            grp.append(len(rbs))
+            bet.append(beta)
+        cols.append(J)
+        cgp.append(len(grp) - 1)
+    ecp.append(len(cols))
+    i32 = lambda a: np.asarray(a, dtype=np.int32)
+    return sampler.Schedule(i32(ecp), i32(cols), i32(cgp), i32(grp), i32(rbs), np.asarray(bet))
+
+
+def test_epoch_sync_reads_the_epoch_start_residual():
+    """The simultaneous reading (Sec. II-B): every column block of an epoch
+    reads the epoch-start r, so the epoch does not depend on the order of
+    its column blocks (the per-column refresh does); afterwards
+    r = y - sum_j z^j on every row, and with one column block per epoch the
+    two readings coincide."""
+    g, S = _system("par2d")
+    rng = np.random.default_rng(31)
+    x0 = rng.uniform(0, 1, g.n_vox)
+    y = S.A @ rng.uniform(0, 1, g.n_vox) + rng.normal(0, 0.1, g.n_rays)
+    steps = [(2, [[0], [2]]), (0, [[1, 2]]), (3, [[1]])]
+    a = _epoch_schedule(steps)
+    b = _epoch_schedule(steps[::-1])
+    out = {}
+    for sync in ("epoch", "column"):
+        sa = csgd.run(S, y, a, sync=sync, x0=x0)
+        sb = csgd.run(S, y, b, sync=sync, x0=x0)
+        out[sync] = (sa, sb)
+        for st in (sa, sb):
+            np.testing.assert_allclose(st.r, y - st.z.sum(axis=0), rtol=1e-12, atol=1e-12)
+    sa, sb = out["epoch"]
+    np.testing.assert_allclose(sa.x, sb.x, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(sa.z, sb.z, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(sa.r, sb.r, rtol=1e-12, atol=1e-12)
+    ca, cb = out["column"]
+    assert np.max(np.abs(ca.x - cb.x)) > 1e-6        # the per-column refresh is order dependent
+    assert np.max(np.abs(ca.x - sa.x)) > 1e-6
+    # one column block: nothing to read stale, the readings agree
+    one = _epoch_schedule([(2, [[0], [2]])])
+    np.testing.assert_allclose(csgd.run(S, y, one, sync="epoch", x0=x0).x,
+                               csgd.run(S, y, one, sync="column", x0=x0).x, rtol=1e-13, atol=1e-14)
+
+
 def test_one_block_is_relaxed_steepest_descent():
     g = inputs.par2d(12, 1.0, 16, 180.0, 18, 0.8, m=1, bx=1, by=1)
     S = csgd.BlockSystem(siddon.system_matrix(g), g)
@@ -309,14 +393,65 @@ def test_draw_counts_groups_and_beta():
                 assert b == pytest.approx(2.0 * sum(P[I, J] for I in G), rel=1e-15)
 
 
-def test_mixed_sampling_reaches_uniform_and_uniform_mode():
-    P = np.array([[0.7], [0.2], [0.1], [0.0]])
-    s = sampler.make_schedule(P, 6000, 0.25, 1.0, 1, 1.0, 43, sampler.MIXED, theta_step=1.0)
-    first = s.rbs[s.group_rb_ptr[s.col_group_ptr[:-1]]][1:]      # epochs >= 1: theta = 1
-    counts = np.bincount(first, minlength=4)
-    assert counts[3] == 0
-    _, p = scipy.stats.chisquare(counts[:3])
+def test_mixed_weights_hand_computed():
+    """Sec. III-D: weight P_I + theta (P_max - P_I), P_max over the sub-areas
+    of I's projection; a sub-area J misses gets theta P_max, a projection J
+    does not reach keeps 0.  Values worked out by hand."""
+    P = np.array([[0.3], [0.1], [0.6], [0.0], [0.0], [0.0]])
+    proj = [0, 0, 2, 2, 4, 4]
+    w = lambda th: sampler.draw_weights(P, 0, th, sampler.MIXED, proj)
+    assert w(0.0) == [0.3, 0.1, 0.6, 0.0, 0.0, 0.0]
+    np.testing.assert_allclose(w(0.5), [0.3, 0.2, 0.6, 0.3, 0.0, 0.0], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(w(1.0), [0.3, 0.3, 0.6, 0.6, 0.0, 0.0], rtol=0, atol=1e-15)
+    # every row block its own projection: mixed sampling is importance sampling
+    assert sampler.draw_weights(P, 0, 0.7, sampler.MIXED, list(range(6))) == \
+        [0.3, 0.1, 0.6, 0.0, 0.0, 0.0]
+    with pytest.raises(ValueError):
+        sampler.make_schedule(P, 1, 1.0, 1.0, 1, 1.0, 1, sampler.MIXED, 0.5)
+
+
+def test_mixed_first_draw_frequencies_at_half_theta():
+    """Draw frequencies follow the mixed weights at theta = 0.5 (epoch 1 of
+    theta_step 0.5): 3000 identical columns give 3000 first draws."""
+    n = 3000
+    P = np.tile(np.array([[0.3], [0.1], [0.6], [0.0], [0.0], [0.0]]), (1, n))
+    s = sampler.make_schedule(P, 2, 1.0 / 6, 1.0, 1, 1.0, 53, sampler.MIXED, theta_step=0.5,
+                              proj=[0, 0, 2, 2, 4, 4])
+    c0, c1 = s.col_group_ptr[s.epoch_col_ptr[1]], s.col_group_ptr[s.epoch_col_ptr[2]]
+    first = s.rbs[s.group_rb_ptr[c0:c1]]
+    counts = np.bincount(first, minlength=6)
+    assert counts[4] == 0 and counts[5] == 0 and counts[3] > 0
+    expect = np.array([0.3, 0.2, 0.6, 0.3]) / 1.4 * n
+    _, p = scipy.stats.chisquare(counts[:4], expect)
     assert p > 1e-3
+    # beta keeps P: a drawn sub-area with P = 0 has beta 0
+    b = s.beta[c0:c1]
+    assert np.all(b[first == 3] == 0.0) and np.all(b[first == 2] == 0.6)
+
+
+def test_mixed_weights_on_the_papers_2d_setting():
+    """The paper's 2D layout (one row block per (view, detector half)): both
+    halves of a view are one projection; at theta = 1 they weigh the same
+    (the larger P of the two), at theta = 0.5 the smaller moves half way."""
+    from oracle import area
+    g = inputs.config_paper2d()
+    proj = sampler.projection_of(g.row_blocks)
+    assert np.array_equal(proj, np.repeat(np.arange(0, 720, 2), 2))
+    P = area.area_density(g)
+    zero_halves = 0
+    for J in range(g.n):
+        w1 = np.array(sampler.draw_weights(P, J, 1.0, sampler.MIXED, proj)).reshape(360, 2)
+        wh = np.array(sampler.draw_weights(P, J, 0.5, sampler.MIXED, proj)).reshape(360, 2)
+        Pv = P[:, J].reshape(360, 2)
+        pmax = Pv.max(axis=1, keepdims=True)
+        np.testing.assert_allclose(w1, np.repeat(pmax, 2, axis=1), rtol=1e-15, atol=0)
+        np.testing.assert_allclose(wh, Pv + 0.5 * (pmax - Pv), rtol=0, atol=1e-16)
+        zero_halves += int(np.count_nonzero((Pv == 0) & (pmax > 0)))
+    assert zero_halves > 100          # J's shadow misses one half in many views
+
+
+def test_uniform_mode_draws_every_row_block():
+    P = np.array([[0.7], [0.2], [0.1], [0.0]])
     u = sampler.make_schedule(P, 4000, 0.25, 1.0, 1, 1.0, 47, sampler.UNIFORM)
     cu = np.bincount(u.rbs, minlength=4)
     assert cu[3] > 0
