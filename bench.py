@@ -1,29 +1,32 @@
 #!/usr/bin/env python3
 """Throughput of the block-iterative CT solver on one MI355X.
 
-Default workload (fan2d_512): a step is one epoch of Alg. 6 on the 2D
-fan-beam case: 512 x 512 image at 0.5 mm, 720 views over 360 degrees,
-768-bin curved detector (1e-3 rad), source 500 mm / detector 1000 mm from
-the source, 12-ellipse seeded phantom, 1% Gaussian noise; 8 view groups x 8
-image tiles, row blocks drawn with probability proportional to nnz(A_I^J),
-alpha = 0.5, group size 1.  Each epoch runs, per column block, the gather
-back-projection, the fused forward projection, the step, and the
-finalize/residual kernels.
+Default workload (cone3d_256, the largest single-GPU case): a step is one
+epoch of Alg. 6 on the 3D cone-beam case: 256^3 volume at 0.5 mm, 360 views
+of 384 x 384 bins at 1 mm over 360 degrees on a circular orbit, source 500 mm
+/ detector 1000 mm from the source, 20-ellipsoid seeded phantom, Poisson
+noise at 1e5 photons per ray; 12 view groups x 8 z-slabs, alpha = 1, groups
+of s = 3 row blocks (4 groups per column block).  Each epoch runs, per column
+block, the gather back-projection, the fused forward projection, the step,
+and the finalize/residual kernels.
 
-Other workloads (--workload): par2d_64 (the small parallel-beam case),
-cone3d_256 (256^3 cone beam, 360 views of 384^2, 12 view groups x 8 z-slabs,
-4 groups of 3, Poisson noise at 1e5 photons), batch64 (64 fan slices of
-uneven sizes, all jobs advanced by shared launches, against the same jobs
-solved one at a time), serve40 (a Poisson stream of mixed fan and cone jobs
-at 40 jobs/s served for a fixed wall-clock window by the continuous-batching
-server, against the same stream served one job at a time).
+Other workloads (--workload): fan2d_512 (2D fan beam, 512^2, 720 views, 768
+curved bins, 8 x 8 blocks), par2d_64 (the small parallel-beam case),
+batch64 (64 fan slices of uneven sizes, all jobs advanced by shared
+launches, against the same jobs solved one at a time), serve40 (a Poisson
+stream of mixed fan and cone jobs served by the continuous-batching server,
+against the same stream served one job at a time).
 
 Printed as one JSON line.  value = ray-voxel updates per second over the
 timed epochs (2 nnz(A_{I_G}^J) per group update, from the exact density
-table), inputs resident in HBM.  The roofline figure is the dominant kernel's
-algorithmic work over its average launch time, measured with a HIP event pair
-around every kernel in a replay of as many epochs right after the timed ones
-(the events themselves add gaps, so they stay out of the timed epochs).
+table), inputs resident in HBM.  The roofline object is the dominant
+kernel's gather-equivalent byte rate: 4 B per ray-voxel pair plus 4 B per
+output element per launch (what a matrix-stored projector would stream),
+over its average launch time measured with a HIP event pair around every
+kernel in a replay of as many epochs right after the timed ones (the events
+add gaps, so they stay out of the timed epochs), against the 8 TB/s HBM
+peak.  Measured DRAM bytes and VALU instructions from rocprofv3 counters of
+the same kernel version are given beside it.
 """
 from __future__ import annotations
 
@@ -41,20 +44,18 @@ if ROOT not in sys.path:
 
 # roofline constants (MI355X)
 HBM_PEAK_GBS = 8000.0
-VALU_PEAK_TFLOPS = 78.6          # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
-FLOPS_PER_UPDATE = 5.0           # select next crossing, segment length, advance, multiply-add
-GATHER_BYTES_PER_UPDATE = 4.0    # what an explicit-A SpMV would stream per nonzero
+GATHER_BYTES = 4.0               # per ray-voxel pair and per output element
+N_SIMD, CLOCK_HZ = 1024, 2.4e9   # 256 CUs x 4 SIMDs; a wave64 VALU instruction issues over 4 cycles
 BATCH_SIZES = (128, 256, 384, 512, 768, 1024)
-# HBM traffic of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs (KiB per dispatch), scaled by what the same counters read
-# for a plain 256 MiB device copy (workload copy256): fetch x 2.0, write x 1.0.
-# An entry holds only for the kernel version the counters were taken on.
+# Counters of the dominant kernels, per dispatch, from rocprofv3 runs of the
+# kernel version they name (FETCH_SIZE and WRITE_SIZE in KiB, each from its
+# own pass, scaled by what the same counters read for a plain 256 MiB device
+# copy: fetch x 2.0, write x 1.0; SQ_INSTS_VALU in wave instructions).  An
+# entry holds only for the kernel version it was taken on.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
-TRAFFIC_KIB = {
-    ("fan2d_512", "back"): {"fetch": 12565.0, "write": 6208.0,
+COUNTERS = {
+    ("fan2d_512", "back"): {"fetch": 12565.0, "write": 6208.0, "valu": None,
                             "profile": "profiles/fan2d_512_back_projection_hbm_traffic.md"},
-    ("cone3d_256", "back"): {"fetch": 378970.0, "write": 886904.0,
-                             "profile": "profiles/cone3d_256_counters.md"},
 }
 SERVE_FAN = (256, 384, 512, 768, 1024)
 SERVE_CONE = (64, 96, 128, 160, 192)
@@ -85,8 +86,7 @@ def single_workload(name):
                 "SDD 230, 720 row blocks (view x detector half) x 4 quadrants, alpha 0.5, s 100, b 2")
     if name == "paper3d_128":
         return (inputs.config_paper3d(), dict(alpha=0.5, gamma=1.0, s=90, b=1.0, seed=6200,
-                                              noise=0.01,
-                                              cpu_geom=lambda: inputs.config_paper3d(24, 40, 360)),
+                                              noise=0.01),
                 "paper 3D setting: cone3d_flat 128^3 over 32^3, 720 random views on a sphere of "
                 "radius 66, 202^2 bins over 101^2, SDD 132, 720 row blocks (views) x 8 blocks, "
                 "alpha 0.5, s 90, b 1")
@@ -151,34 +151,107 @@ def cpu_baseline(g, y, ex, budget_s=15.0, note=""):
             "seconds": t_run}
 
 
-def roofline_of(kt, prof_updates, workload=None):
-    """Roofline object of the dominant kernel from per-class (ms, launches)."""
+def projector_outputs(ex, g, epochs):
+    """Output elements written by the projector launches of the given epochs:
+    the back-projection writes g_J once per group of a column step (|J| per
+    group), the fused forward A x and A g for every ray of a group's row
+    blocks."""
+    vox = [int((b[1] - b[0]) * (b[3] - b[2]) * (b[5] - b[4])) for b in g.col_blocks]
+    rays = [int(sum((t[2] - t[1]) * (t[4] - t[3]) for t in rb)) for rb in g.row_blocks]
+    back = fwd = 0
+    for e in epochs:
+        for c in range(ex["epoch_col_ptr"][e], ex["epoch_col_ptr"][e + 1]):
+            J = ex["cols"][c]
+            for G in range(ex["col_group_ptr"][c], ex["col_group_ptr"][c + 1]):
+                back += vox[J]
+                for k in range(ex["group_rb_ptr"][G], ex["group_rb_ptr"][G + 1]):
+                    fwd += 2 * rays[ex["rbs"][k]]
+    return {"back": back, "fwd": fwd}
+
+
+def cpu_baseline_matrix_free(g, y_np, ex, budget_s=15.0):
+    """The FP64 oracle's matrix-free group step (rows of A regenerated by its
+    Siddon row generator for every product, as a whole A of this size does
+    not fit in memory), as it is, on a bounded sample of the same workload:
+    the first group update of the schedule (J, its first group, beta; epoch
+    start x = 0, r = y) on the rays of the group's first V views, V chosen so
+    the run takes about ``budget_s``.  Run on the row generator's OpenMP
+    threads (OMP_NUM_THREADS, else the affinity mask), then on one thread for
+    one view."""
+    from oracle import csgd, siddon
+    c = ex["epoch_col_ptr"][0]
+    J = int(ex["cols"][c])
+    G0 = ex["col_group_ptr"][c]
+    rbs = [int(t) for t in ex["rbs"][ex["group_rb_ptr"][G0]:ex["group_rb_ptr"][G0 + 1]]]
+    beta = float(ex["beta"][G0])
+    rows = np.concatenate([g.row_block_rays(I) for I in rbs])
+    per_view = g.nu * g.nv
+    x0 = np.zeros(g.n_vox)
+    y64 = np.asarray(y_np, dtype=np.float64)
+    aff = len(os.sched_getaffinity(0))
+    want = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or aff
+
+    def timed(nv, threads):
+        used = siddon.set_threads(threads)
+        t = time.perf_counter()
+        _, _, _, nnz = csgd.step_group_matrix_free(g, rows[:nv * per_view], J, x0, y64, beta)
+        return time.perf_counter() - t, nnz, used
+
+    t1, _, _ = timed(1, want)                       # calibration: one view
+    nv = int(max(1, min(len(rows) // per_view, budget_s / max(t1, 1e-3))))
+    t_all, nnz_all, used = timed(nv, want)
+    t_one, nnz_one, _ = timed(1, 1)
+    siddon.set_threads(want)
+    return {"value": 2 * nnz_all / t_all, "unit": "ray-voxel updates/s", "cores": used,
+            "kind": "oracle",
+            "sample": (f"matrix-free FP64 oracle group step on the same geometry, y and schedule: "
+                       f"column block {J}, its first group (row blocks {rbs}, beta {beta:.4g}), "
+                       f"x = 0, r = y, restricted to the rays of the group's first {nv} of "
+                       f"{len(rows) // per_view} views ({nv * per_view} rays, {nnz_all} pairs in J); "
+                       f"A's rows regenerated by the C Siddon generator for g = A^T r and again "
+                       f"for A g and A x_J; {2 * nnz_all} updates in {t_all:.2f} s on {used} "
+                       f"OpenMP threads (affinity mask: {aff} CPUs)"),
+            "seconds": t_all,
+            "one_thread": {"value": 2 * nnz_one / t_one, "cores": 1, "seconds": t_one,
+                           "sample": f"the same step on the group's first view ({per_view} rays, "
+                                     f"{nnz_one} pairs in J) on one thread"}}
+
+
+def roofline_of(kt, prof_updates, outputs, workload=None):
+    """Roofline object of the dominant kernel from per-class (ms, launches).
+
+    Projectors: algorithmic bytes per launch = 4 B x (ray-voxel pairs +
+    output elements), the stream an explicit-A sparse product of the same
+    block would need; achieved = those bytes / the average launch time."""
     dom = max(kt, key=lambda k: kt[k][0])
     dom_ms, dom_n = kt[dom]
     avg_ms = dom_ms / max(dom_n, 1)
-    if dom in ("back", "fwd"):
-        units = prof_updates / 2                # ray-voxel pairs handled by one projector
-        per_launch = units / dom_n
-        achieved = per_launch * FLOPS_PER_UPDATE / (avg_ms * 1e-3) / 1e12
-        tr = TRAFFIC_KIB.get((workload, dom))
-        traffic = (None if tr is None else
-                   (tr["fetch"] * PMC_FETCH_SCALE + tr["write"] * PMC_WRITE_SCALE) * 1024.0)
-        roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": VALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 5),
-                "traffic": traffic, "kernel": dom, "avg_launch_ms": round(avg_ms, 5),
-                "launches": dom_n, "units_per_launch": per_launch,
-                "flops_per_unit": FLOPS_PER_UPDATE}
-        if tr is not None:
-            roof["traffic_note"] = (f"HBM bytes per launch (FETCH_SIZE x {PMC_FETCH_SCALE} + "
-                                    f"WRITE_SIZE x {PMC_WRITE_SCALE}), {tr['profile']}")
-        gbytes = per_launch * GATHER_BYTES_PER_UPDATE / (avg_ms * 1e-3) / 1e9
-        gather = {"achieved": round(gbytes, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(gbytes / HBM_PEAK_GBS, 5)}
-    else:
-        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    if dom not in ("back", "fwd"):
+        return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": None, "traffic": None, "kernel": dom}
-        gather = None
-    return roof, gather
+    pairs = prof_updates / 2 / dom_n            # ray-voxel pairs handled by one launch
+    outs = outputs[dom] / dom_n
+    alg = GATHER_BYTES * (pairs + outs)
+    gbs = alg / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom,
+            "avg_launch_ms": round(avg_ms, 5), "launches": dom_n,
+            "pairs_per_launch": pairs, "outputs_per_launch": outs,
+            "algorithmic_bytes_per_launch": alg,
+            "model": "4 B per ray-voxel pair + 4 B per output element (gather-equivalent)"}
+    c = COUNTERS.get((workload, dom))
+    if c is not None:
+        roof["traffic"] = (c["fetch"] * PMC_FETCH_SCALE + c["write"] * PMC_WRITE_SCALE) * 1024.0
+        roof["traffic_note"] = (f"measured HBM bytes per launch (FETCH_SIZE x {PMC_FETCH_SCALE} + "
+                                f"WRITE_SIZE x {PMC_WRITE_SCALE}), {c['profile']}")
+        if c.get("valu"):
+            roof["valu"] = {"wave_instructions_per_launch": c["valu"],
+                            "lane_instructions_per_pair": round(c["valu"] * 64 / pairs, 2),
+                            "busy_frac": round(c["valu"] * 4 / (N_SIMD * CLOCK_HZ) /
+                                               (avg_ms * 1e-3), 4),
+                            "note": "SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz) over the "
+                                    "launch time: the fraction of the VALU issue ceiling used"}
+    return roof
 
 
 def make_y(ct, inputs, G, g, cfg, seed):
@@ -265,7 +338,8 @@ def run_single(args):
 
     timed_updates = sum(upd[args.warmup:E])
     out = base_record(args, timed_updates / (ms * 1e-3), ms, args.steps)
-    roof, gather = roofline_of(kt, prof_updates, args.workload)
+    roof = roofline_of(kt, prof_updates, projector_outputs(ex, g, range(E, E + args.steps)),
+                       args.workload)
     out["config"] = {"workload": desc, "epoch_updates": upd[args.warmup], "b": cfg["b"],
                      "rel_residual_after": rel, "setup_s": round(t_setup, 3),
                      "launch_shape": {"fwd_split": shape["fwd_split"], "back_waves": shape["back_waves"],
@@ -273,24 +347,15 @@ def run_single(args):
                                       "default_ms_per_epoch": round(shape["ms_default"], 4)},
                      "tune_s": round(t_tune, 3)}
     out["roofline"] = roof
-    out["gather_equivalent_hbm"] = gather
     out["kernels_ms"] = {k: round(v[0], 4) for k, v in kt.items()}
     out["kernels_note"] = "per-kernel HIP-event times from the same number of epochs run right after the timed ones"
     out["kernels_launches"] = {k: v[1] for k, v in kt.items()}
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         if g.is3d:
-            # the explicit FP64 A of the full volume does not fit; time the
-            # oracle on the same geometry at parity scale instead
-            gs = cfg["cpu_geom"]() if "cpu_geom" in cfg else inputs.config_p3()
-            Gs = ct.ct_geom_create(gs)
-            ys_np, _ = make_y(ct, inputs, Gs, gs, cfg, cfg["seed"])
-            nnzs = ct.ct_geom_block_nnz(Gs, 1e-5 * min(gs.vx, gs.vy))
-            exs = ct.ct_schedule_export(ct.ct_schedule_create(Gs, params, nnzs))
-            out["cpu_baseline"] = cpu_baseline(
-                gs, ys_np, exs, args.cpu_budget,
-                note=f"parity-scale version of the cone geometry ({gs.nx}^3, {gs.n_views} views of "
-                     f"{gs.nu}^2): ")
+            # the explicit FP64 A of the full volume does not fit in memory:
+            # the oracle's matrix-free mode on the same geometry, y, schedule
+            out["cpu_baseline"] = cpu_baseline_matrix_free(g, y_np, ex, args.cpu_budget)
         else:
             out["cpu_baseline"] = cpu_baseline(g, y_np, ex, args.cpu_budget)
     return out
@@ -395,7 +460,12 @@ def run_batch(args):
     for e in range(E):
         ct.ct_batch_epoch(B2)
     kt = ct.ct_batch_profile_read(B2)
-    roof, gather = roofline_of(kt, total_updates)
+    outs = {"back": 0, "fwd": 0}
+    for j in jobs:
+        o = projector_outputs(j["ex"], j["g"], range(E))
+        outs["back"] += o["back"]
+        outs["fwd"] += o["fwd"]
+    roof = roofline_of(kt, total_updates, outs)
 
     out = base_record(args, total_updates / (ms_batch * 1e-3), ms_batch, E)
     out["config"] = {
@@ -415,7 +485,6 @@ def run_batch(args):
     out["mean_rel_residual"] = float(np.mean(res_batch))
     out["identical_to_plain"] = bool(same)
     out["roofline"] = roof
-    out["gather_equivalent_hbm"] = gather
     out["kernels_ms"] = {k: round(v[0], 4) for k, v in kt.items()}
     out["kernels_launches"] = {k: v[1] for k, v in kt.items()}
     out["kernels_note"] = "batched launches timed with HIP events in a replay of the same epochs"
@@ -570,7 +639,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="fan2d_512",
+    ap.add_argument("--workload", default="cone3d_256",
                     choices=["fan2d_512", "par2d_64", "cone3d_256", "fan2d_512_parallel", "paper2d_64",
                              "paper3d_128", "batch64", "serve40",
                              "copy256"])

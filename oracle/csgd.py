@@ -103,6 +103,54 @@ def step_group(st: State, G, J: int, beta: float):
     return xnew, mu, rows
 
 
+def step_group_matrix_free(geom, rows: np.ndarray, J: int, x: np.ndarray, r: np.ndarray,
+                           beta: float, chunk: int = 1 << 17):
+    """The basic computation block of ``step_group`` without a stored A
+    (matrix-free mode, for geometries whose A does not fit in memory).
+
+    The rows of A for the rays ``rows`` (global ray indices of the group's
+    row blocks, in order) are generated chunk by chunk by the same Siddon
+    row generator, cut to the columns of block J and dropped after use; A
+    is generated twice, once for g = (A_{I_G}^J)^T r_{I_G} (Eq. 7) and once
+    for q = A g and a = A x_J, as the step size (Eq. 11) needs all of g
+    first.  z^J_{I_G} = A x_J + mu A g, which is A (x_J + mu g) of
+    ``step_group`` up to rounding.  Returns (x_J + mu g, mu, z rows, nnz of
+    the block).  Pinned against ``step_group`` on small geometries."""
+    from . import rays as _rays
+    from . import siddon as _siddon
+    rows = np.asarray(rows, dtype=np.int64)
+    vox = geom.col_block_vox(J)
+    loc = np.full(geom.n_vox, -1, dtype=np.int64)
+    loc[vox] = np.arange(len(vox))
+
+    def blocks():
+        for a in range(0, len(rows), chunk):
+            idx = rows[a:a + chunk]
+            org, dirn, div = _rays.rays_at(geom, idx)
+            A = _siddon.rows_for(geom, org, dirn, div)
+            c = loc[A.indices]
+            keep = c >= 0
+            rid = np.repeat(np.arange(len(idx)), np.diff(A.indptr))
+            AJ = sp.csr_matrix((A.data[keep], (rid[keep], c[keep])), shape=(len(idx), len(vox)))
+            yield a, idx, AJ
+
+    g = np.zeros(len(vox))
+    nnz = 0
+    for _, idx, AJ in blocks():
+        g += AJ.T @ np.asarray(r, dtype=np.float64)[idx]
+        nnz += AJ.nnz
+    xJ = np.asarray(x, dtype=np.float64)[vox]
+    q = np.zeros(len(rows))
+    ax = np.zeros(len(rows))
+    for a, idx, AJ in blocks():
+        q[a:a + len(idx)] = AJ @ g
+        ax[a:a + len(idx)] = AJ @ xJ
+    gg = float(g @ g)
+    qq = float(q @ q)
+    mu = beta * gg / qq if (gg > 0.0 and qq > 0.0) else 0.0
+    return xJ + mu * g, mu, ax + mu * q, nnz
+
+
 def refresh(st: State, rows: np.ndarray):
     """r_It = y_It - sum_j z^j_It (sum over j ascending)."""
     acc = np.zeros(len(rows))

@@ -177,3 +177,9 @@ int siddon_fill(int dims, const int64_t* n, const double* lo, const double* h,
     }
     return err;
 }
+
+/* Thread count of the OpenMP ray loops above (a timing knob only: every ray
+ * is computed the same way whatever the count). */
+#include <omp.h>
+void siddon_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+int siddon_max_threads(void) { return omp_get_max_threads(); }

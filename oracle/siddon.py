@@ -46,8 +46,20 @@ def _load():
         lib.siddon_count.argtypes = [ctypes.c_int, P, P, P, ctypes.c_int64, P, P, ctypes.c_int, P]
         lib.siddon_fill.argtypes = [ctypes.c_int, P, P, P, ctypes.c_int64, P, P, ctypes.c_int,
                                     P, P, P]
+        lib.siddon_set_threads.argtypes = [ctypes.c_int]
+        lib.siddon_set_threads.restype = None
+        lib.siddon_max_threads.argtypes = []
+        lib.siddon_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads of the row generator's OpenMP loops (timing only); returns the
+    count now in effect."""
+    lib = _load()
+    lib.siddon_set_threads(int(n))
+    return int(lib.siddon_max_threads())
 
 
 def _vol(geom):

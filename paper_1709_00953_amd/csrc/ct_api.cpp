@@ -67,6 +67,7 @@ struct ct_geom {
     std::vector<Entry> all_entries;
     int32_t max_rb_rays = 0, max_cb_vox = 0, max_tiles = 0, total_chunks = 0, max_xg = 0;
     int32_t max_step_wchunks = 0;      // windowed chunks of all row blocks, worst column block
+    int32_t vertical = 0;              // cone with detector columns along z (kConeV)
     int device = -1;
     void* dmem = nullptr;               // device tables, uploaded on first use
     size_t dbytes = 0;
@@ -84,6 +85,12 @@ static void box_tiling(const ct_geom* g, const Box& b, int* tx, int* ty, int* tz
         *tx = (nxJ + kTile2 - 1) / kTile2;
         *ty = (nyJ + kTile2 - 1) / kTile2;
         *tz = 1;
+    } else if (g->vertical) {
+        int TZ, CX, CY;
+        col_tile_shape(nzJ, TZ, CX, CY);
+        *tx = (nxJ + CX - 1) / CX;
+        *ty = (nyJ + CY - 1) / CY;
+        *tz = (nzJ + TZ - 1) / TZ;
     } else {
         *tx = (nxJ + kTile3x - 1) / kTile3x;
         *ty = (nyJ + kTile3y - 1) / kTile3y;
@@ -291,6 +298,18 @@ static int build_host(ct_geom* g, const ct_geom_desc* d) {
         }
     }
 
+    // cone views whose detector columns run along z (e_v = +-z, e_u and the
+    // source-detector axis in the xy plane): the voxel-column back-projection
+    g->vertical = 0;
+    if (g->dims == 3) {
+        bool vert = true;
+        for (int k = 0; k < d->n_views && vert; ++k) {
+            const double* V = &g->views[(size_t)k * 12];
+            vert = V[9] == 0.0 && V[10] == 0.0 && std::fabs(V[11]) == 1.0 && V[8] == 0.0 && V[5] == V[2];
+        }
+        g->vertical = vert ? 1 : 0;
+    }
+
     // row blocks: tiles, coverage
     std::vector<uint8_t> cover((size_t)M, 0);
     g->rb_tile_ptr.assign(1, 0);
@@ -377,13 +396,14 @@ static int build_host(ct_geom* g, const ct_geom_desc* d) {
 
 // 2D per-ray constants and per-view zero-direction flags.
 static void build_frames(const ct_geom* g, std::vector<Ray2F>& rayf, std::vector<Ray2B>& rayb,
-                         std::vector<int32_t>& flags) {
+                         std::vector<Ray2K>& rayk, std::vector<int32_t>& flags) {
     const ct_geom_desc& d = g->d;
     flags.assign(d.n_views, 0);
     const double hx = 0.5 * d.vx, hy = 0.5 * d.vy;
     if (g->dims == 2) {
         rayf.assign((size_t)d.n_views * d.nu, Ray2F{});
         rayb.assign((size_t)d.n_views * d.nu, Ray2B{});
+        rayk.assign((size_t)d.n_views * d.nu, Ray2K{});
     }
     for (int k = 0; k < d.n_views; ++k) {
         const double* W = &g->v64[(size_t)k * kViewStride];
@@ -426,23 +446,26 @@ static void build_frames(const ct_geom* g, std::vector<Ray2F>& rayf, std::vector
                 auto slab = [](double o, double org, double ih) {
                     return (float)std::fmin(std::fmax(std::floor((o - org) * ih), -1e7), 1e7);
                 };
+                Ray2K& Q = rayk[(size_t)k * d.nu + iu];
                 if (dx == 0.0) {
-                    R.K = (float)dy;
-                    R.S = (float)(2.0 * hy / std::fabs(dy));
+                    R.K = (float)(2.0 * hy / std::fabs(dy));
                     R.M = -1.f;
-                    R.slab = slab(o0, d.ox, 1.0 / d.vx);
+                    R.hs = slab(o0, d.ox, 1.0 / d.vx);
                     flags[k] |= 1;
                 } else if (dy == 0.0) {
-                    R.K = (float)(-dx);
-                    R.S = (float)(2.0 * hx / std::fabs(dx));
+                    R.K = (float)(2.0 * hx / std::fabs(dx));
                     R.M = -2.f;
-                    R.slab = slab(o1, d.oy, 1.0 / d.vy);
+                    R.hs = slab(o1, d.oy, 1.0 / d.vy);
                     flags[k] |= 1;
                 } else {
-                    const double wx = hx / std::fabs(dx), wy = hy / std::fabs(dy);
-                    R.K = (float)(-dy / dx - dx / dy);
-                    R.S = (float)(wx + wy);
-                    R.M = (float)std::min(2.0 * wx, 2.0 * wy);
+                    const double adx = std::fabs(dx), ady = std::fabs(dy);
+                    const double K = 1.0 / (adx * ady);
+                    R.hs = hx * ady + hy * adx;
+                    R.K = (float)K;
+                    R.M = (float)std::min(2.0 * hx / adx, 2.0 * hy / ady);
+                    Q.K = R.K;
+                    Q.S = (float)(R.hs * K);
+                    Q.M = R.M;
                 }
             }
         } else {
@@ -467,10 +490,39 @@ static void build_frames(const ct_geom* g, std::vector<Ray2F>& rayf, std::vector
 }
 
 struct DevLayout {
-    size_t off_view, off_rayf, off_rayb, off_flags, off_tiles, off_rbt, off_troff, off_chunks, off_rbc, off_wch,
+    size_t off_view, off_rayf, off_rayb, off_rayk, off_cdxy, off_cdz, off_cisv, off_flags, off_tiles, off_rbt, off_troff, off_chunks, off_rbc, off_wch,
         off_rbj, off_all,
         off_nnz, off_boxes, total;
 };
+
+// Per-view tables of a vertical cone (see DGeom): the x, y components of a
+// ray depend on its detector column only, the z component on its row only.
+// Same operations as the kernels' float64 ray vector D = v e_v + u e_u + sdd n
+// (with e_v,x = e_v,y = e_u,z = n_z = 0 the other terms are exact zeros).
+static void build_columns(const ct_geom* g, std::vector<float2>& dxy, std::vector<float>& dz,
+                          std::vector<double>& isv) {
+    const ct_geom_desc& d = g->d;
+    dxy.assign((size_t)d.n_views * d.nu, float2{});
+    dz.assign((size_t)d.n_views * d.nv, 0.f);
+    isv.assign((size_t)d.n_views * d.nv, 0.0);
+    for (int k = 0; k < d.n_views; ++k) {
+        const double* W = &g->v64[(size_t)k * kViewStride];
+        const double sdd = W[15], is = W[16];
+        for (int iu = 0; iu < d.nu; ++iu) {
+            const double u = ((double)iu - 0.5 * (double)(d.nu - 1)) * d.pu;
+            float2& q = dxy[(size_t)k * d.nu + iu];
+            q.x = (float)(std::fma(u, W[6], sdd * W[12]) * is);
+            q.y = (float)(std::fma(u, W[7], sdd * W[13]) * is);
+        }
+        for (int iv = 0; iv < d.nv; ++iv) {
+            const double v = ((double)iv - 0.5 * (double)(d.nv - 1)) * d.pv;
+            const double Dz = v * W[11];
+            const float f = (float)(Dz * is);
+            dz[(size_t)k * d.nv + iv] = f;
+            isv[(size_t)k * d.nv + iv] = std::fabs(f) <= kAxisEpsF ? 0.0 : sdd / Dz;
+        }
+    }
+}
 
 static DevLayout dev_layout(const ct_geom* g) {
     DevLayout L{};
@@ -483,6 +535,10 @@ static DevLayout dev_layout(const ct_geom* g) {
     L.off_view = take((size_t)g->d.n_views * kViewStride * sizeof(double));
     L.off_rayf = take(g->dims == 2 ? (size_t)g->d.n_views * g->d.nu * sizeof(Ray2F) : 0);
     L.off_rayb = take(g->dims == 2 ? (size_t)g->d.n_views * g->d.nu * sizeof(Ray2B) : 0);
+    L.off_rayk = take(g->dims == 2 ? (size_t)g->d.n_views * g->d.nu * sizeof(Ray2K) : 0);
+    L.off_cdxy = take(g->vertical ? (size_t)g->d.n_views * g->d.nu * sizeof(float2) : 0);
+    L.off_cdz = take(g->vertical ? (size_t)g->d.n_views * g->d.nv * sizeof(float) : 0);
+    L.off_cisv = take(g->vertical ? (size_t)g->d.n_views * g->d.nv * sizeof(double) : 0);
     L.off_flags = take((size_t)g->d.n_views * sizeof(int32_t));
     L.off_tiles = take(g->tiles.size() * sizeof(Tile));
     L.off_rbt = take((g->m + 1) * sizeof(int32_t));
@@ -511,8 +567,9 @@ static int geom_ensure_device(ct_geom* g) {
     const std::vector<double>& v64 = g->v64;
     std::vector<Ray2F> rayf;
     std::vector<Ray2B> rayb;
+    std::vector<Ray2K> rayk;
     std::vector<int32_t> flags;
-    build_frames(g, rayf, rayb, flags);
+    build_frames(g, rayf, rayb, rayk, flags);
     DevLayout L = dev_layout(g);
     void* mem = nullptr;
     if (hipMalloc(&mem, L.total) != hipSuccess)
@@ -526,6 +583,14 @@ static int geom_ensure_device(ct_geom* g) {
     if (e == hipSuccess) e = up(L.off_view, v64.data(), v64.size() * sizeof(double));
     if (e == hipSuccess) e = up(L.off_rayf, rayf.data(), rayf.size() * sizeof(Ray2F));
     if (e == hipSuccess) e = up(L.off_rayb, rayb.data(), rayb.size() * sizeof(Ray2B));
+    if (e == hipSuccess) e = up(L.off_rayk, rayk.data(), rayk.size() * sizeof(Ray2K));
+    std::vector<float2> cdxy;
+    std::vector<float> cdz;
+    std::vector<double> cisv;
+    if (g->vertical) build_columns(g, cdxy, cdz, cisv);
+    if (e == hipSuccess) e = up(L.off_cdxy, cdxy.data(), cdxy.size() * sizeof(float2));
+    if (e == hipSuccess) e = up(L.off_cdz, cdz.data(), cdz.size() * sizeof(float));
+    if (e == hipSuccess) e = up(L.off_cisv, cisv.data(), cisv.size() * sizeof(double));
     if (e == hipSuccess) e = up(L.off_flags, flags.data(), flags.size() * sizeof(int32_t));
     if (e == hipSuccess) e = up(L.off_tiles, g->tiles.data(), g->tiles.size() * sizeof(Tile));
     if (e == hipSuccess) e = up(L.off_rbt, g->rb_tile_ptr.data(), g->rb_tile_ptr.size() * sizeof(int32_t));
@@ -566,6 +631,10 @@ static int geom_ensure_device(ct_geom* g) {
     G.view64 = (const double*)(base + L.off_view);
     G.ray2f = g->dims == 2 ? (const Ray2F*)(base + L.off_rayf) : nullptr;
     G.ray2b = g->dims == 2 ? (const Ray2B*)(base + L.off_rayb) : nullptr;
+    G.ray2k = g->dims == 2 ? (const Ray2K*)(base + L.off_rayk) : nullptr;
+    G.cdxy = g->vertical ? (const float2*)(base + L.off_cdxy) : nullptr;
+    G.cdz = g->vertical ? (const float*)(base + L.off_cdz) : nullptr;
+    G.cisv = g->vertical ? (const double*)(base + L.off_cisv) : nullptr;
     G.view_flags = (const int32_t*)(base + L.off_flags);
     G.tiles = (const Tile*)(base + L.off_tiles);
     G.rb_tile_ptr = (const int32_t*)(base + L.off_rbt);
@@ -575,6 +644,7 @@ static int geom_ensure_device(ct_geom* g) {
     G.wchunks = (const Chunk*)(base + L.off_wch);
     G.rbj_chunk_ptr = (const int32_t*)(base + L.off_rbj);
     G.n_cols = g->n;
+    G.vertical = g->vertical;
     G.mixed_boxes = 0;
     for (const Box& b : g->boxes) {
         const Box& b0 = g->boxes[0];
@@ -1733,8 +1803,12 @@ struct ct_batch {
     hipGraphExec_t exec = nullptr;
     bool graph_valid = false;
     Prof prof;
-    Tune tune[4]{};                 // launch shapes per geometry kind
+    Tune tune[5]{};                 // launch shapes per launch kind (the four kinds and kConeV)
 };
+
+// Launch kind of a geometry's projectors: its kind, or kConeV for a cone
+// whose detector columns run along z (voxel-column back-projection).
+static int launch_kind(const ct_geom* g) { return g->vertical ? kConeV : g->d.kind; }
 
 static BJob make_bjob(const BatchSlot& b) {
     const ct_solver* s = b.job.solver;
@@ -1814,7 +1888,7 @@ static int batch_rebuild(ct_batch* b, hipStream_t st) {
         const ct_schedule* sc = j.job.sched;
         for (size_t e = 0; e + 1 < sc->ecp.size(); ++e) cmax = std::max(cmax, sc->ecp[e + 1] - sc->ecp[e]);
         any_epoch_sync = any_epoch_sync || j.job.solver->p.sync == CT_SYNC_EPOCH;
-        const int k = j.job.solver->geom->d.kind;
+        const int k = launch_kind(j.job.solver->geom);
         if (std::find(kinds.begin(), kinds.end(), k) == kinds.end()) kinds.push_back(k);
     }
     std::sort(kinds.begin(), kinds.end());
@@ -1828,7 +1902,7 @@ static int batch_rebuild(ct_batch* b, hipStream_t st) {
         int acc = 0;
         pre.push_back(0);
         for (const BatchSlot& j : b->jobs) {
-            const bool mine = (phase != kPhBack && phase != kPhFwd) || j.job.solver->geom->d.kind == kind;
+            const bool mine = (phase != kPhBack && phase != kPhFwd) || launch_kind(j.job.solver->geom) == kind;
             acc += mine ? phase_work(j, phase, c) : 0;
             pre.push_back(acc);
         }
@@ -1901,7 +1975,8 @@ static int batch_enqueue(ct_batch* b, hipStream_t st) {
     for (const BatchLaunch& L : b->launches)
         HIPCHK(b->prof.timed(kind_of_phase[L.phase], st,
                              [&] {
-                                 return launch_batch(L.phase, L.kind, batch_args(b, &L), L.blocks, b->tune[L.kind], st);
+                                 return launch_batch(L.phase, L.kind, batch_args(b, &L), L.blocks,
+                                                     b->tune[L.kind == kConeV ? (int)CT_CONE3D_FLAT : L.kind], st);
                              }));
     HIPCHK(launch_batch_advance(batch_args(b, nullptr), st));
     return CT_OK;

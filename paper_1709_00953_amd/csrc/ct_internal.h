@@ -20,7 +20,30 @@ constexpr int kViewStride = 24;
 // endpoints would cancel), while the exact-zero half-open membership test can.
 constexpr double kAxisEps = 1e-12;
 constexpr float kAxisEpsF = 1e-12f;
+// 3D back-projection: views whose detector window holds a ray with a direction
+// component (in units of the ray vector over the source-detector distance)
+// below this take the float64 candidate path (clip3_precise)
+constexpr double kNearAxis = 0.02;
 enum { kPar2D = 0, kFanFlat = 1, kFanCurved = 2, kCone = 3 };
+// Launch kind of a cone geometry whose every view has its detector columns
+// parallel to the z axis (e_v = +-z, e_u and the source-detector axis in the
+// xy plane): its back-projection takes the voxel-column kernel.
+constexpr int kConeV = 4;
+
+// Voxel-column tile of that kernel: 256 lanes = NC columns x TZ voxels in z
+// (z fastest), the columns CX x CY.  TZ is the largest power of two up to 32
+// whose tiles waste at most 1/8 of the lanes over the box's nz voxels
+// (at least 1).
+__host__ __device__ inline void col_tile_shape(int nz, int& tz, int& cx, int& cy) {
+    int t = 32;
+    while (t > 1 && ((nz + t - 1) / t) * t - nz > nz / 8) t >>= 1;
+    tz = t;
+    const int nc = 256 / t;                  // 8 .. 256 columns
+    int lg = 0;
+    while ((1 << lg) < nc) ++lg;
+    cx = 1 << ((lg + 1) / 2);
+    cy = nc / cx;
+}
 
 // J-local (x, g) pairs of a group are stored twice: copy 0 x-fastest
 // ([z][y][x]) and copy 1 y-fastest ([z][x][y]).  The forward pass reads the
@@ -78,17 +101,25 @@ struct Ray2F {
     double dx, dy, idx, idy;
 };
 // Back-projection: delta = p*B - q*A is the signed distance of the ray from a
-// voxel centre whose view-frame coordinates are (A, B).  Along the ray the
-// voxel's x slab is [delta kx - wx, delta kx + wx] and its y slab
-// [delta ky - wy, delta ky + wy] (kx = -dy/dx, ky = dx/dy, wx = hx/|dx|,
-// wy = hy/|dy|), so the clip length is
-//   max(0, min(2 wx, 2 wy, wx + wy - |delta (kx - ky)|))
-// stored as K = kx - ky, S = wx + wy, M = min(2 wx, 2 wy).  A zero direction
-// component is marked by M = -1 (dx = 0) or M = -2 (dy = 0); then S is the
-// full chord and slab the index of the one x (or y) slab the ray lies in.
+// voxel centre whose view-frame coordinates are (A, B).  For a unit direction
+// (dx, dy) with both components nonzero the clip length with a voxel of
+// half-widths (hx, hy) is the trapezoid
+//   clamp((hs - |delta|) K, 0, M),  hs = hx |dy| + hy |dx|,  K = 1 / |dx dy|,
+//   M = min(2 hx / |dx|, 2 hy / |dy|).
+// hs - |delta| is formed in float64: for a ray nearly parallel to an axis K is
+// large, and the difference is the small distance of the ray from the voxel's
+// corner band, which float32 operands ~hs (relative error 6e-8) would swamp.
+// A zero direction component is marked by M = -1 (dx = 0) or M = -2 (dy = 0);
+// then K is the full chord and hs the index of the one x (or y) slab the ray
+// lies in.
 struct Ray2B {
-    double p, q;
-    float K, S, M, slab;
+    double p, q, hs;
+    float K, M;
+};
+// The curved fan's float32 form of the same clip, for rays with
+// min(|dx|, |dy|) >= 0.02 only: (K, S = hs K, M, 0).
+struct Ray2K {
+    float K, S, M, pad;
 };
 
 // Device-side geometry, passed by value.
@@ -101,6 +132,14 @@ struct DGeom {
     const double* view64;         // [n_views][kViewStride]
     const Ray2F* ray2f;           // [n_views][nu] (2D kinds)
     const Ray2B* ray2b;           // [n_views][nu] (2D kinds)
+    const Ray2K* ray2k;           // [n_views][nu] (curved fan)
+    // vertical cones (kConeV): float32 components D~_x, D~_y of the rays of
+    // each detector column and D~_z of each row (the values every cone kernel
+    // forms, (float)(D_k / sdd)), and sdd / D_z of each row in float64 (0 for
+    // a zero component)
+    const float2* cdxy;           // [n_views][nu]
+    const float* cdz;             // [n_views][nv]
+    const double* cisv;           // [n_views][nv]
     const int32_t* view_flags;    // [n_views] bit0: some ray has a zero direction component
     const Tile* tiles;
     const int32_t* rb_tile_ptr;
@@ -111,6 +150,7 @@ struct DGeom {
     const int32_t* rbj_chunk_ptr; // [m*n+1], index rb*n + J
     int32_t n_cols;
     int32_t mixed_boxes;          // column blocks differ in size (their (x, g) copies differ in layout)
+    int32_t vertical;             // cone: every view's detector columns run along z (kConeV)
 };
 
 struct Box {

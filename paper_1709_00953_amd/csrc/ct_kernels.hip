@@ -321,7 +321,8 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                     double thi = fmin(t1, fma((double)S1, ia, Cs)) - tref;
                     const bool empty = !(thi > tlo);
                     int jb = 0;
-                    float fb = 0.5f, dbf = 0.f, idb = 1e30f;
+                    double fb64 = 0.5, idb64 = 1e30;
+                    float dbf = 0.f;
                     if (empty) {
                         tlo = 0.0;
                         thi = 0.0;
@@ -331,10 +332,11 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                         const double pb = (fma(tref, d[B], o[B]) - lo[B]) * ih[B];
                         const double fl = floor(pb);
                         jb = (int)fl;
-                        fb = fminf((float)(pb - fl), 0x1.fffffep-1f);
+                        fb64 = pb - fl;
                         dbf = (float)(d[B] * ih[B]);       // voxels of B per mm of ray
-                        idb = (float)fmax(fmin(h[B] * id[B], 1e30), -1e30);
+                        idb64 = fmax(fmin(h[B] * id[B], 1e30), -1e30);
                     }
+                    const float idb = (float)idb64;
                     // the wave walks the slabs that some lane's ray overlaps: its
                     // lanes' ranges widened by one slab (float rounding), the
                     // union found by a uniform binary search over ballots (lanes
@@ -356,15 +358,26 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                         if (__ballot(uhi > mid)) lo2 = mid + 1;
                         else ue = mid;
                     }
-                    // tau of the B plane above voxel lj: lj idb + nf1
-                    const float nf1 = (float)((1.0 - (double)fb) * (double)idb);
-                    const float ias = (float)ia, tl = (float)tlo, th = (float)thi;
+                    // The B offset is kept as the distance to the next B plane
+                    // in the direction of travel, g (float64, then rounded), so
+                    // the crossings that lie in the box keep their precision
+                    // however small d_B is: going up, voxel lj of a slab ends
+                    // at the plane crossed at tau = lj idb + g idb; going down,
+                    // voxel lj starts at tau = (lj + 1) idb - g idb.
                     const bool up = d[B] >= 0.0;
+                    const double g64 = up ? 1.0 - fb64 : fb64;
+                    const float gb = (float)g64;
+                    const float nfs = (float)((up ? g64 : -g64) * idb64);
+                    const float ias = (float)ia, tl = (float)tlo, th = (float)thi;
                     const int rstep = d[A] > 0.0 ? nB : -nB;
                     // element index of (slab S0 + us, jb); the padding keeps it positive
                     int row = (d[A] > 0.0 ? S0 : nA - 1 - S0) * nB + us * rstep + jb + xg_pad(nx, ny, 1);
                     float uf = (float)us;
-                    float ts = __builtin_amdgcn_fmed3f(uf * ias, tl, th), fs = floorf(fmaf(ts, dbf, fb));
+                    // voxel (relative to jb) that the ray is in at tau
+                    auto vox_at = [&](float t) {
+                        return up ? floorf(fmaf(t, dbf, -gb)) + 1.f : floorf(fmaf(t, dbf, gb));
+                    };
+                    float ts = __builtin_amdgcn_fmed3f(uf * ias, tl, th), fs = vox_at(ts);
                     // DIR 1: every lane's ray goes up B, so the lower voxel of a
                     // slab is the one it starts in; DIR 2: every ray goes down
                     auto walk = [&](auto dir) {
@@ -377,9 +390,11 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                                 // slabs past S1 get zero lengths (tau clamped to th)
                                 uf += 1.f;
                                 const float te = __builtin_amdgcn_fmed3f(uf * ias, tl, th);
-                                const float fe = floorf(fmaf(te, dbf, fb));
+                                const float fe = DIR == 1 ? floorf(fmaf(te, dbf, -gb)) + 1.f
+                                                          : floorf(fmaf(te, dbf, gb));
                                 const float lj = DIR == 1 ? fs : fe;
-                                const float tc = __builtin_amdgcn_fmed3f(fmaf(lj, idb, nf1), ts, te);
+                                const float tc = __builtin_amdgcn_fmed3f(
+                                    DIR == 1 ? fmaf(lj, idb, nfs) : fmaf(lj + 1.f, idb, nfs), ts, te);
                                 const float l1 = tc - ts, l2 = te - tc;
                                 llo[q] = DIR == 1 ? l1 : l2;
                                 lhi[q] = DIR == 1 ? l2 : l1;
@@ -415,19 +430,24 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
 #pragma unroll
             for (int c = 0; c < DIMS; ++c) {
                 nb[c] = b1[c] - b0[c];
-                const WT ef = (WT)((fma(t0, d[c], o[c]) - lo[c]) * ih[c]);
+                // the distance to the first plane is formed in float64 before
+                // it is rounded: for a ray nearly parallel to the planes of
+                // axis c the crossing lies at that distance over a small
+                // direction component, so a float32 box-local position
+                // (error ~1e-7 voxel) would move it by 1e-7 / |d_c| voxels
+                const double ef = (fma(t0, d[c], o[c]) - lo[c]) * ih[c];
                 int i = (int)floor(ef);
-                if (d[c] < 0.0 && (WT)i == ef) i -= 1;
+                if (d[c] < 0.0 && (double)i == ef) i -= 1;
                 i = min(max(i, 0), nb[c] - 1);
                 ii[c] = d[c] == 0.0 ? zs[c] : i;
                 if (d[c] > 0.0) {
                     sg[c] = 1;
-                    dl[c] = (WT)(i + 1) - ef;
+                    dl[c] = (WT)((double)(i + 1) - ef);
                     inv[c] = (WT)(h[c] * id[c]);
                     tk[c] = dl[c] * inv[c];
                 } else if (d[c] < 0.0) {
                     sg[c] = -1;
-                    dl[c] = ef - (WT)i;
+                    dl[c] = (WT)(ef - (double)i);
                     inv[c] = (WT)(-h[c] * id[c]);
                     tk[c] = dl[c] * inv[c];
                 } else {                       // never crossed: dl * inv stays +inf
@@ -596,17 +616,19 @@ __global__ __launch_bounds__(256) void k_fwd_inl(DGeom G, FwdArgs a) {
 // K1: gather back-projection, 2D
 // ----------------------------------------------------------------------------
 // Clip length of the ray described by R with the voxel whose centre lies at
-// signed distance delta from it: the overlap of its two slab intervals.
-__device__ __forceinline__ float chord2(float delta, const Ray2B& R) {
-    return __builtin_amdgcn_fmed3f(R.S - fabsf(delta * R.K), 0.f, R.M);     // clamp to [0, M]
+// signed distance delta from it: the overlap of its two slab intervals.  The
+// difference hs - |delta| is small where the length is on its ramp, and is
+// formed in float64 before it is rounded (see Ray2B).
+__device__ __forceinline__ float chord2(double delta, const Ray2B& R) {
+    return __builtin_amdgcn_fmed3f((float)(R.hs - fabs(delta)) * R.K, 0.f, R.M);   // clamp to [0, M]
 }
 
 // Same, for rays with a zero direction component: such a ray lies in one
-// slab of that axis (index R.slab) and meets the voxels of that slab only.
-__device__ __forceinline__ float chord2_axis(float delta, const Ray2B& R, int ix, int iy) {
+// slab of that axis (index R.hs) and meets the voxels of that slab only.
+__device__ __forceinline__ float chord2_axis(double delta, const Ray2B& R, int ix, int iy) {
     if (R.M < 0.f) {
-        const float mine = (R.M == -1.f) ? (float)ix : (float)iy;
-        return mine == R.slab ? R.S : 0.f;
+        const int mine = (R.M == -1.f) ? ix : iy;
+        return (double)mine == R.hs ? R.K : 0.f;
     }
     return chord2(delta, R);
 }
@@ -717,7 +739,12 @@ __device__ __forceinline__ void view_params(const DGeom& G, const Tile& tl, doub
         // offsets at most 4 from the tile centre)
         const int kr = min(max((int)floor(bc + 0.5), 0), G.nu - 1);
         const double emax = G.pu * (fabs(bc - kr) + W + 4.0 * (fabs(bxs) + fabs(bys)) + 1.0);
-        if (!(P.flags & 1) && emax <= 2e-2) {
+        // and every candidate ray at least 0.02 (in sine) from an axis: K
+        // = 1 / |dx dy| then stays below ~50, so the float32 distance's error
+        // (< 1e-6 mm) moves a length by at most 5e-5 mm
+        const Ray2F& Fr = G.ray2f[(size_t)tl.view * G.nu + kr];
+        const bool off_axis = fmin(fabs(Fr.dx), fabs(Fr.dy)) >= emax + 0.02;
+        if (!(P.flags & 1) && emax <= 2e-2 && off_axis) {
             const Ray2B& Rr = G.ray2b[(size_t)tl.view * G.nu + kr];
             const double p = Rr.p, q = Rr.q;
             FanC f;
@@ -807,12 +834,11 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
                         __builtin_memcpy(&f, &P.Ac, sizeof f);
                         const float Xs = f.Xc + fmaf(lyf, f.Xy, lxf * f.Xx);
                         const float Rs = f.Rc + fmaf(lyf, f.Yy, lxf * f.Yx);
-                        // K, S, M (and the unused slab) of bin b: the second
-                        // half of its Ray2B
-                        const float4* KS = reinterpret_cast<const float4*>(RB);
+                        // K, S, M of bin b
+                        const float4* KS = reinterpret_cast<const float4*>(G.ray2k + (size_t)view * G.nu);
                         float ef = (float)(blo - f.kr);      // b - kr, an exact small integer
                         for (int b = blo; b <= bhi; ++b) {
-                            const float4 k = ldu(KS, 2u * (unsigned)b + 1u);
+                            const float4 k = ldu(KS, (unsigned)b);
                             const float rv = ldu(rr, (unsigned)b);
                             const float e = ef * f.pu;
                             const float e2 = e * e;
@@ -830,7 +856,7 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
                 if (vflags & 1) {
                     for (int b = blo; b <= bhi; ++b) {
                         const Ray2B Rb = ldu(RB, (unsigned)b);
-                        const float dlt = (float)fma(Rb.p, B, -Rb.q * A);
+                        const double dlt = fma(Rb.p, B, -Rb.q * A);
                         acc = fmaf(chord2_axis(dlt, Rb, ix, iy), ldu(rr, (unsigned)b), acc);
                     }
                 } else if (blo <= bhi) {
@@ -845,7 +871,7 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
                         const unsigned bn = (unsigned)min(b + 1, bhi);
                         Rn = ldu(RB, bn);
                         rn = ldu(rr, bn);
-                        const float dlt = (float)fma(Rb.p, B, -Rb.q * A);
+                        const double dlt = fma(Rb.p, B, -Rb.q * A);
                         acc = fmaf(chord2(dlt, Rb), rv, acc);
                     }
                 }
@@ -1012,6 +1038,25 @@ __device__ __forceinline__ void view_params3(const DGeom& G, const Tile& tl, con
     P.fv0 = v0;
     P.fv1 = max(v0, v1);
     P.chh = max(1, kRayC / max(1, min(P.fu1 - P.fu0, kRayC)));
+    // rays of the window with a direction component below kNearAxis (D~
+    // units, |D~| >= 1) take the float64 candidate path: the component is
+    // affine in (u, v), so its smallest magnitude over the window is at a
+    // corner unless it changes sign there
+    if (P.fu1 > P.fu0 && P.fv1 > P.fv0) {
+        const double ua = ((double)P.fu0 - c0u) * G.pu, ub = ((double)(P.fu1 - 1) - c0u) * G.pu;
+        const double va = ((double)P.fv0 - c0v) * G.pv, vb = ((double)(P.fv1 - 1) - c0v) * G.pv;
+        bool near = false;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double c = V[12 + k], eu = V[6 + k] * isdd, ev = V[9 + k] * isdd;
+            const double d00 = fma(va, ev, fma(ua, eu, c)), d01 = fma(vb, ev, fma(ua, eu, c));
+            const double d10 = fma(va, ev, fma(ub, eu, c)), d11 = fma(vb, ev, fma(ub, eu, c));
+            const double lo = fmin(fmin(d00, d01), fmin(d10, d11));
+            const double hi = fmax(fmax(d00, d01), fmax(d10, d11));
+            near = near || (lo < kNearAxis && hi > -kNearAxis);
+        }
+        if (near) P.flags |= 4;
+    }
     // plus the float32 rounding of the voxel's shadow centre and half-extent
     // (|beta| <= a few thousand bins)
     P.e2u = (float)fmin(e2u, 1e9) + 2e-3f + 2e-6f * fabsf((float)bu);
@@ -1032,32 +1077,44 @@ __device__ __forceinline__ void view_params3(const DGeom& G, const Tile& tl, con
 }
 
 // Clipped parameter extent of a staged ray in the voxel at offsets (du, dv)
-// (times the ray's |d| it is the intersection length); for a zero direction
-// component (careful views only) the ray stays in the source's slab of that
-// axis, so the voxel (indices vi) meets it only in that slab.
+// (times the ray's |d| it is the intersection length).  Views whose rays have
+// a zero or small direction component take clip3_precise instead.
 __device__ __forceinline__ float clip3(float du, float dv, const float4& q0, const float4& q1,
-                                       const float4& q2, const ViewP3& P, const int vi[3],
-                                       bool careful) {
+                                       const float4& q2) {
     const float s0 = fmaf(du, q0.x, dv * q1.x);
     const float s1 = fmaf(du, q0.y, dv * q1.y);
     const float s2 = fmaf(du, q0.z, dv * q1.z);
-    float lo = fmaxf(fmaxf(s0 - q0.w, s1 - q1.w), s2 - q2.x);
-    float hi = fminf(fminf(s0 + q0.w, s1 + q1.w), s2 + q2.x);
-    if (careful) {
-        const int zero = __float_as_int(q2.w);
-        if (zero) {
-            const float ss[3] = {s0, s1, s2}, ww[3] = {q0.w, q1.w, q2.x};
-            lo = -INFINITY;
-            hi = INFINITY;
+    const float lo = fmaxf(fmaxf(s0 - q0.w, s1 - q1.w), s2 - q2.x);
+    const float hi = fminf(fminf(s0 + q0.w, s1 + q1.w), s2 + q2.x);
+    return fmaxf(hi - lo, 0.f);
+}
+
+// The same extent with the slab bounds' numerators in float64.  For a ray
+// whose component D~_k is small the bound (du e_u,k + dv e_v,k -+ h_k) / D~_k
+// of axis k moves by the numerator's error over |D~_k|, and float32 offsets
+// (error ~1e-7 mm) would move it by up to 1e-7 / |D~_k| mm; here du, dv and the
+// numerators are float64 and only the quotient is float32 (relative error).
+// A zero component (the kernels' rule: |D~_k| rounded to float32 <= kAxisEpsF)
+// keeps the ray in the source's slab sk of that axis.  (Au, Bu, Bv): the
+// voxel centre's view-frame coordinates in float64.
+__device__ __forceinline__ float clip3_precise(const double* V, double u, double v, double Av,
+                                               double Bu, double Bv, const double h[3],
+                                               const int vi[3], const int sk[3]) {
+    const double isdd = V[16];
+    const double du = fma(-Av, u * isdd, Bu), dv = fma(-Av, v * isdd, Bv);
+    float lo = -INFINITY, hi = INFINITY;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                if ((zero >> k) & 1) {
-                    if (vi[k] != P.sk[k]) hi = -INFINITY;
-                } else {
-                    lo = fmaxf(lo, ss[k] - ww[k]);
-                    hi = fminf(hi, ss[k] + ww[k]);
-                }
-            }
+    for (int k = 0; k < 3; ++k) {
+        const double Dk = fma(v, V[9 + k], fma(u, V[6 + k], V[15] * V[12 + k]));
+        const float dk = (float)(Dk * isdd);
+        if (fabsf(dk) <= kAxisEpsF) {
+            if (vi[k] != sk[k]) hi = -INFINITY;
+        } else {
+            const double num = fma(du, V[6 + k], dv * V[9 + k]);
+            const float ik = __builtin_amdgcn_rcpf(dk);
+            const float a = (float)(num - h[k]) * ik, b = (float)(num + h[k]) * ik;
+            lo = fmaxf(lo, fminf(a, b));
+            hi = fminf(hi, fmaxf(a, b));
         }
     }
     return fmaxf(hi - lo, 0.f);
@@ -1135,7 +1192,8 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
             const int view = __builtin_amdgcn_readfirstlane(P.view);
             const int fu0 = __builtin_amdgcn_readfirstlane(P.fu0), fu1 = __builtin_amdgcn_readfirstlane(P.fu1);
             const int fv0 = __builtin_amdgcn_readfirstlane(P.fv0), fv1 = __builtin_amdgcn_readfirstlane(P.fv1);
-            const bool careful = (__builtin_amdgcn_readfirstlane(P.flags) & 1) != 0;
+            // zero or small direction components in the window (flag bits 0, 2)
+            const bool near = (__builtin_amdgcn_readfirstlane(P.flags) & 5) != 0;
             const int fw = fu1 - fu0, fh = fv1 - fv0;
             if (fw <= 0 || fh <= 0) continue;
             const float* rview = uniform_ptr(a.r + (size_t)view * G.nv * G.nu);
@@ -1212,27 +1270,45 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
                     // the rectangle row by row in one flat loop: the column
                     // offset (an exact small integer) is kept as a float, dv
                     // steps by stv at the end of a row, and the LDS byte
-                    // offset jumps to the next row there; one copy of the
-                    // loop per kind of view (a uniform branch)
+                    // offset jumps to the next row there (views with small
+                    // direction components: the float64 path, a uniform branch)
                     const int lb0 = ((va - cv0) * pw + (ua - cu0)) * 16;
                     const int lb_end = lb0 + (vb - va + 1) * pw * 16;   // where the last wrap lands
                     const int jump = (pw - nu_w + 1) * 16;
                     const float last = (float)(nu_w - 1);
-                    auto candidates = [&](auto careful_c) {
+                    if (near) {
+                        // float64 numerators (clip3_precise): the voxel centre's
+                        // view-frame coordinates from the tile centre's (recovered
+                        // from the float64 bases) plus its offsets
+                        const double* V = view_of(G, view);
+                        const double At = -P.slu * V[15] / pu;
+                        const double Bu = fma(At, ((double)P.uref - c0u) * pu * V[16], P.D0u) +
+                                          fma((double)oz * G.vz, V[8], fma((double)oy * G.vy, V[7], (double)ox * G.vx * V[6]));
+                        const double Bv = fma(At, ((double)P.vref - c0v) * pv * V[16], P.D0v) +
+                                          fma((double)oz * G.vz, V[11], fma((double)oy * G.vy, V[10], (double)ox * G.vx * V[9]));
+                        const double Av = At + fma((double)oz * G.vz, V[14], fma((double)oy * G.vy, V[13], (double)ox * G.vx * V[12]));
+                        const double h64[3] = {0.5 * G.vx, 0.5 * G.vy, 0.5 * G.vz};
+                        for (int iv = va; iv <= vb; ++iv) {
+                            const double v = ((double)iv - c0v) * pv;
+                            for (int iu = ua; iu <= ub; ++iu) {
+                                const float4 q2 = lds_f4(rc2, ((iv - cv0) * pw + (iu - cu0)) * 16);
+                                const double u = ((double)iu - c0u) * pu;
+                                acc = fmaf(clip3_precise(V, u, v, Av, Bu, Bv, h64, vi, P.sk), q2.y, acc);
+                            }
+                        }
+                    } else {
                         float kuf = 0.f, dv = dv0;
                         int lb = lb0;
                         do {
                             const float du = fmaf(kuf, stu, du0);
                             const float4 q0 = lds_f4(rc0, lb), q1 = lds_f4(rc1, lb), q2 = lds_f4(rc2, lb);
-                            acc = fmaf(clip3(du, dv, q0, q1, q2, P, vi, decltype(careful_c)::value), q2.y, acc);
+                            acc = fmaf(clip3(du, dv, q0, q1, q2), q2.y, acc);
                             const bool wrap = kuf == last;
                             kuf = wrap ? 0.f : kuf + 1.f;
                             dv = wrap ? dv + stv : dv;
                             lb += wrap ? jump : 16;
                         } while (lb != lb_end);
-                    };
-                    if (careful) candidates(std::true_type{});
-                    else candidates(std::false_type{});
+                    }
                 }
             }
         }
@@ -1265,6 +1341,375 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
 template <class BA>
 __global__ __launch_bounds__(256, 6) void k_back3(DGeom G, BA a) {
     back3_body(G, a, blockIdx.y, blockIdx.x, gridDim.x);
+}
+
+// ----------------------------------------------------------------------------
+// K1: gather back-projection, cone views with detector columns along z
+// ----------------------------------------------------------------------------
+// When e_v = +-z and e_u, n lie in the xy plane (a circular orbit about the z
+// axis), every ray of detector column u lies in the vertical plane through the
+// source and that column.  In the view frame of the 3D kernel above, the x and
+// y slab intervals of ray (u, v) in a voxel,
+//   s in [(du e_u,k -+ h_k) / D~_k(u)],  k = x, y,  du = Bu - A u / sdd,
+// depend on u and the voxel's column (A, Bu: view-frame coordinates of the
+// column's centre) only, and its z slab interval
+//   s in [(z_f - z_S) sdd / (e_v,z v) - A],  z_f = the voxel's two z faces,
+// on v and the voxel only.  The clip length of a pair is therefore
+//   |D~| max(0, min(X_hi(u), Z_hi(v)) - max(X_lo(u), Z_lo(v)))
+// with X the column's xy interval of ray u and Z the voxel's z interval of row
+// v: X is formed once per (column, u) and Z once per (voxel, v) instead of
+// three slab intervals per pair.  A work-group owns NC voxel columns x TZ
+// voxels in z (one voxel per lane, z fastest; col_tile_shape).  Per view it
+// stages in LDS, for the part of its detector window in hand, X of every
+// (column, u), the product |D~| r of every ray and sdd / (e_v,z v) of every row
+// (float64: the z bounds are differences of terms of the size of A); each
+// voxel then walks the rows of its shadow (from the corners of its box) and,
+// per row, the bins of its column's shadow.  Both bounds are formed in float64
+// up to a difference, so they keep their precision for rays nearly parallel
+// to a voxel face (the small direction components that the float32 bounds of
+// the general kernel lose).  A zero direction component (the kernels' rule)
+// keeps the ray in the source's slab of that axis.
+constexpr int kColWG = 6;         // resident work-groups per CU the register budget is set for
+constexpr int kColR = 512;        // rays of a view's window staged at once (fast path: the whole window)
+constexpr int kColV = 128;        // rows of a view's window staged at once
+constexpr int kColU = 4;          // X intervals kept per (view, column)
+
+// Per (view, column) of a round: A of the column's centre, 1 / A at the near
+// and far edge of its footprint, its bins [u0, u1] and X of the first kColU.
+struct ColView {
+    double A;
+    float ia0, ia1;
+    int32_t u0, u1;
+    float2 X[kColU];
+};
+// Per view of a round: the tile's detector window [u0, u1) x [v0, v1), whether
+// it is staged whole (fast) and whether the view has a zero component.
+struct WinView {
+    double zS;                    // source height
+    float ssv;                    // sdd e_v,z
+    int32_t view, u0, u1, v0, v1, fast, careful;
+};
+
+// X of the ray of bin iu in the voxel column (jx, jy) whose centre has
+// view-frame coordinates (A, B): the overlap of its x and y slab intervals,
+// with the bounds' numerators in float64.  dxy: the ray's float32 D~_x, D~_y;
+// a zero component keeps the ray in the source's slab (skx, sky) of that axis.
+__device__ __forceinline__ float2 col_interval(const DGeom& G, const double* V, const float2 dxy, double A,
+                                               double B, int iu, int jx, int jy, int skx, int sky) {
+    const double uu = ((double)iu - 0.5 * (double)(G.nu - 1)) * G.pu;
+    const double du = fma(-A, uu * V[16], B);
+    float lo = -INFINITY, hi = INFINITY;
+    const float dk[2] = {dxy.x, dxy.y};
+    const int ji[2] = {jx, jy}, sk[2] = {skx, sky};
+    const double hk[2] = {0.5 * G.vx, 0.5 * G.vy};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (fabsf(dk[k]) <= kAxisEpsF) {
+            if (ji[k] != sk[k]) hi = -INFINITY;
+        } else {
+            const double num = du * V[6 + k];
+            const float ik = __builtin_amdgcn_rcpf(dk[k]);
+            const float p = (float)(num - hk[k]) * ik, q = (float)(num + hk[k]) * ik;
+            lo = fmaxf(lo, fminf(p, q));
+            hi = fminf(hi, fmaxf(p, q));
+        }
+    }
+    return make_float2(lo, hi);
+}
+
+__device__ __forceinline__ int src_slab(double s, double o, double ih) {
+    return (int)fmin(fmax(floor((s - o) * ih), -1e9), 1e9);
+}
+
+template <class BA>
+__device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const int gi, const int bt,
+                                            const int n_tiles) {
+    __shared__ ColView cv[256];                  // [view slot][column]
+    __shared__ WinView wv[32];                   // [view slot]
+    __shared__ float sR[2][kColR];               // |D~| r of a window's rays; two views in flight
+    __shared__ double sI[2][kColV];              // sdd / D_z of its rows
+    __shared__ double sh[4];
+    const int t = threadIdx.x;
+    int TZ, CX, CY;
+    col_tile_shape(a.box.z1 - a.box.z0, TZ, CX, CY);
+    const int NC = CX * CY, NVR = 256 / NC;      // columns; views per round (at most 32)
+    const int tiles_x = a.tiles_x, tiles_y = a.tiles_y;
+    const int tx = bt % tiles_x, ty = (bt / tiles_x) % tiles_y, tz = bt / (tiles_x * tiles_y);
+    const int xs = a.box.x0 + tx * CX, ys = a.box.y0 + ty * CY, zs = a.box.z0 + tz * TZ;
+    const int nvx = min(CX, a.box.x1 - xs), nvy = min(CY, a.box.y1 - ys), nvz = min(TZ, a.box.z1 - zs);
+    // this lane's voxel: column c (cx, cy), level lz
+    const int lz = t % TZ, c = t / TZ;
+    const int ccx = c % CX, ccy = c / CX;
+    const int ix = xs + ccx, iy = ys + ccy, iz = zs + lz;
+    const bool valid = ccx < nvx && ccy < nvy && lz < nvz;
+    const double c0u = 0.5 * (double)(G.nu - 1), c0v = 0.5 * (double)(G.nv - 1);
+    const double zlo = G.oz + (double)iz * G.vz, zhi = zlo + G.vz;
+
+    int e0 = 0, e1 = a.n_ent;
+    if (a.gptr) {
+        e0 = a.gptr[gi];
+        e1 = a.gptr[gi + 1];
+    }
+    int nt = 0;                                          // views (tiles) of the group
+    for (int e = e0; e < e1; ++e) {
+        const int rb = get_entry(a, e).rb;
+        nt += G.rb_tile_ptr[rb + 1] - G.rb_tile_ptr[rb];
+    }
+
+    // rays [0, nr) (rows of pw bins from (ua, va)) and rows [0, nrow) of
+    // view `view`'s window part into buffer b
+    auto stage = [&](int view, int b, int pw, int ua, int va, int nr, int nrow) {
+        const float* rview = a.r + (size_t)view * G.nv * G.nu;
+        const float2* dxy = G.cdxy + (size_t)view * G.nu;
+        const float* dz = G.cdz + (size_t)view * G.nv;
+        for (int i = t; i < nr; i += 256) {
+            const int row = i / pw, iu = ua + (i - row * pw), iv = va + row;
+            const float2 q = ldu(dxy, (unsigned)iu);
+            const float z = ldu(dz, (unsigned)iv);
+            const float nrm = __builtin_amdgcn_sqrtf(fmaf(q.x, q.x, fmaf(q.y, q.y, z * z)));
+            sR[b][i] = nrm * ldu(rview, (unsigned)(iv * G.nu + iu));
+        }
+        const double* isv = G.cisv + (size_t)view * G.nv;
+        for (int i = t; i < nrow; i += 256) sI[b][i] = ldu(isv, (unsigned)(va + i));
+    };
+
+    float acc = 0.f;
+    // this voxel's part from rows [ka, kb] and bins [uL, uH] of a staged part
+    // of view slot j (buffer b; rows from va, bins from ua, pw bins a row)
+    auto gather = [&](const WinView& W, const ColView& C, int b, int pw, int ua, int va, int ka, int kb,
+                      int uL, int uH) {
+        const double A = C.A, zfl = zlo - W.zS, zfh = zhi - W.zS;
+        for (int k = ka; k <= kb; ++k) {
+            const double isv = sI[b][k - va];
+            float zl, zh;
+            if (W.careful && isv == 0.0) {
+                // a horizontal ray stays at the source's height
+                const bool in = iz == src_slab(W.zS, G.oz, G.ivz);
+                zl = in ? -INFINITY : INFINITY;
+                zh = in ? INFINITY : -INFINITY;
+            } else {
+                const float p = (float)fma(zfl, isv, -A), q = (float)fma(zfh, isv, -A);
+                zl = fminf(p, q);
+                zh = fmaxf(p, q);
+            }
+            const int ro = (k - va) * pw - ua;
+            for (int u = uL; u <= uH; ++u) {
+                const int i = u - C.u0;
+                float2 xi;
+                if (i < kColU) {
+                    xi = C.X[i];
+                } else {
+                    // a column more than kColU bins wide: X formed here
+                    const double* V = view_of(G, W.view);
+                    const double qx = G.ox + ((double)ix + 0.5) * G.vx - V[0];
+                    const double qy = G.oy + ((double)iy + 0.5) * G.vy - V[1];
+                    xi = col_interval(G, V, ldu(G.cdxy + (size_t)W.view * G.nu, (unsigned)u), A,
+                                      fma(qx, V[6], qy * V[7]), u, ix, iy, src_slab(V[0], G.ox, G.ivx),
+                                      src_slab(V[1], G.oy, G.ivy));
+                }
+                const float lo = fmaxf(xi.x, zl), hi = fminf(xi.y, zh);
+                acc = fmaf(fmaxf(hi - lo, 0.f), sR[b][ro + u], acc);
+            }
+        }
+    };
+    // this voxel's rows: the projections of its box's corners
+    auto rows_of = [&](const WinView& W, const ColView& C, int& k0, int& k1) {
+        if (!(C.ia0 < INFINITY)) {                 // footprint at the source's depth: every row
+            k0 = W.v0;
+            k1 = W.v1 - 1;
+            return;
+        }
+        const float f0 = (float)(W.ssv * (zlo - W.zS)), f1 = (float)(W.ssv * (zhi - W.zS));
+        const float vmin = fminf(fminf(f0 * C.ia0, f0 * C.ia1), fminf(f1 * C.ia0, f1 * C.ia1));
+        const float vmax = fmaxf(fmaxf(f0 * C.ia0, f0 * C.ia1), fmaxf(f1 * C.ia0, f1 * C.ia1));
+        const float ipv = (float)(1.0 / G.pv), fc = (float)c0v;
+        k0 = max(W.v0, (int)ceilf(fmaf(vmin, ipv, fc) - 1e-3f - 1e-6f * fabsf(vmin * ipv)));
+        k1 = min(W.v1 - 1, (int)floorf(fmaf(vmax, ipv, fc) + 1e-3f + 1e-6f * fabsf(vmax * ipv)));
+    };
+
+    for (int base = 0; base < nt; base += NVR) {
+        const int nvr = min(NVR, nt - base);
+        // phase A: lane (view slot j, column cc) of the round
+        {
+            const int j = t / NC, cc = t % NC;
+            if (j < nvr) {
+                int e = e0, off = base + j;
+                Tile tl{};
+                for (;;) {
+                    const int rb = get_entry(a, e).rb;
+                    const int cnt = G.rb_tile_ptr[rb + 1] - G.rb_tile_ptr[rb];
+                    if (off < cnt) {
+                        tl = G.tiles[G.rb_tile_ptr[rb] + off];
+                        break;
+                    }
+                    off -= cnt;
+                    ++e;
+                }
+                const double* V = view_of(G, tl.view);
+                const double sdd = V[15];
+                const int jx = xs + (cc % CX), jy = ys + (cc / CX);
+                const double qx = G.ox + ((double)jx + 0.5) * G.vx - V[0];
+                const double qy = G.oy + ((double)jy + 0.5) * G.vy - V[1];
+                const double A = fma(qx, V[12], qy * V[13]);
+                const double B = fma(qx, V[6], qy * V[7]);
+                const double ea = 0.5 * G.vx * fabs(V[12]) + 0.5 * G.vy * fabs(V[13]);
+                ColView& C = cv[t];
+                C.A = A;
+                const bool ok = A - ea > 0.0;
+                C.ia0 = ok ? __builtin_amdgcn_rcpf((float)(A - ea)) : INFINITY;
+                C.ia1 = ok ? __builtin_amdgcn_rcpf((float)(A + ea)) : -INFINITY;
+                // bins whose ray can meet the column: the projections of its
+                // footprint's corners (it lies in front of the source)
+                int u0 = tl.u0, u1 = tl.u1 - 1;
+                if (ok) {
+                    const float hxf = (float)(0.5 * G.vx), hyf = (float)(0.5 * G.vy);
+                    const float Af = (float)A, Bf = (float)B;
+                    const float nx = (float)V[12], ny = (float)V[13], ex = (float)V[6], ey = (float)V[7];
+                    float umin = INFINITY, umax = -INFINITY;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float px = (k & 1) ? hxf : -hxf, py = (k & 2) ? hyf : -hyf;
+                        const float uu = fmaf(py, ey, fmaf(px, ex, Bf)) *
+                                         __builtin_amdgcn_rcpf(fmaf(py, ny, fmaf(px, nx, Af)));
+                        umin = fminf(umin, uu);
+                        umax = fmaxf(umax, uu);
+                    }
+                    const float s = (float)(sdd / G.pu), fc = (float)c0u;
+                    const float bl = fmaf(umin, s, fc), bh = fmaf(umax, s, fc);
+                    u0 = max(u0, (int)ceilf(bl - 1e-3f - 1e-6f * fabsf(bl)));
+                    u1 = min(u1, (int)floorf(bh + 1e-3f + 1e-6f * fabsf(bh)));
+                }
+                C.u0 = u0;
+                C.u1 = u1;
+                const int skx = src_slab(V[0], G.ox, G.ivx), sky = src_slab(V[1], G.oy, G.ivy);
+#pragma unroll
+                for (int i = 0; i < kColU; ++i) {
+                    const int u = u0 + i;
+                    C.X[i] = u <= u1 ? col_interval(G, V, ldu(G.cdxy + (size_t)tl.view * G.nu, (unsigned)u), A, B,
+                                                    u, jx, jy, skx, sky)
+                                     : make_float2(0.f, 0.f);
+                }
+                if (cc == 0) {
+                    // the tile's window: the projections of its box's corners
+                    WinView& W = wv[j];
+                    W.view = tl.view;
+                    W.zS = V[2];
+                    W.ssv = (float)(sdd * V[11]);
+                    W.careful = G.view_flags[tl.view] & 1;
+                    const double x0 = G.ox + (double)xs * G.vx - V[0], y0 = G.oy + (double)ys * G.vy - V[1];
+                    const double z0 = G.oz + (double)zs * G.vz - V[2];
+                    const float ex = (float)V[6], ey = (float)V[7], nx = (float)V[12], ny = (float)V[13];
+                    const float xa = (float)x0, xb = (float)(x0 + nvx * G.vx);
+                    const float ya = (float)y0, yb = (float)(y0 + nvy * G.vy);
+                    const float za = (float)z0, zb = (float)(z0 + nvz * G.vz), ssv = W.ssv;
+                    float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+                    bool front = true;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float px = (k & 1) ? xb : xa, py = (k & 2) ? yb : ya;
+                        const float Ak = fmaf(py, ny, px * nx);
+                        front = front && Ak > 0.f;
+                        const float iA = __builtin_amdgcn_rcpf(Ak);
+                        const float uu = fmaf(py, ey, px * ex) * iA;
+                        umin = fminf(umin, uu);
+                        umax = fmaxf(umax, uu);
+                        vmin = fminf(vmin, fminf(za * iA, zb * iA));
+                        vmax = fmaxf(vmax, fmaxf(za * iA, zb * iA));
+                    }
+                    int wu0 = tl.u0, wu1 = tl.u1, wv0 = tl.v0, wv1 = tl.v1;
+                    if (front) {
+                        const float su = (float)(sdd / G.pu), fu = (float)c0u;
+                        const float bl = fmaf(umin, su, fu), bh = fmaf(umax, su, fu);
+                        wu0 = max(wu0, (int)ceilf(bl - 1e-3f - 1e-6f * fabsf(bl)));
+                        wu1 = min(wu1, (int)floorf(bh + 1e-3f + 1e-6f * fabsf(bh)) + 1);
+                        // v = sdd e_v,z (z - z_S) / A: scale the extremes by ssv
+                        const float sv = ssv / (float)G.pv, fv = (float)c0v;
+                        const float cl = fminf(vmin * sv, vmax * sv) + fv, ch = fmaxf(vmin * sv, vmax * sv) + fv;
+                        wv0 = max(wv0, (int)ceilf(cl - 1e-3f - 1e-6f * fabsf(cl)));
+                        wv1 = min(wv1, (int)floorf(ch + 1e-3f + 1e-6f * fabsf(ch)) + 1);
+                    }
+                    wu1 = max(wu0, wu1);
+                    wv1 = max(wv0, wv1);
+                    W.u0 = wu0;
+                    W.u1 = wu1;
+                    W.v0 = wv0;
+                    W.v1 = wv1;
+                    W.fast = (wu1 - wu0) * (wv1 - wv0) <= kColR && wv1 - wv0 <= kColV;
+                }
+            }
+        }
+        __syncthreads();
+        // the round's views, one barrier each: the next view's window is staged
+        // while this one's is gathered
+        if (wv[0].fast)
+            stage(wv[0].view, 0, max(1, wv[0].u1 - wv[0].u0), wv[0].u0, wv[0].v0,
+                  (wv[0].u1 - wv[0].u0) * (wv[0].v1 - wv[0].v0), wv[0].v1 - wv[0].v0);
+        __syncthreads();
+        for (int j = 0; j < nvr; ++j) {
+            const WinView& W = wv[j];
+            const ColView& C = cv[j * NC + c];
+            const int b = j & 1;
+            const int fast = __builtin_amdgcn_readfirstlane(W.fast);
+            const int pw = max(1, W.u1 - W.u0);
+            int k0 = 1, k1 = 0;
+            if (valid) rows_of(W, C, k0, k1);
+            const int uL = max(C.u0, W.u0), uH = min(C.u1, W.u1 - 1);
+            if (fast) {
+                if (j + 1 < nvr && wv[j + 1].fast) {
+                    const WinView& Wn = wv[j + 1];
+                    stage(Wn.view, b ^ 1, max(1, Wn.u1 - Wn.u0), Wn.u0, Wn.v0, (Wn.u1 - Wn.u0) * (Wn.v1 - Wn.v0),
+                          Wn.v1 - Wn.v0);
+                }
+                if (valid) gather(W, C, b, pw, W.u0, W.v0, k0, k1, uL, uH);
+                __syncthreads();
+            } else {
+                // a window too large to stage whole: parts of at most kColR
+                // rays and kColV rows, each between two barriers
+                const int ppw = max(1, min(pw, kColR));
+                for (int ua = W.u0; ua < W.u1; ua += ppw) {
+                    const int ub = min(W.u1, ua + ppw), qw = ub - ua;
+                    const int rows = max(1, min(kColV, kColR / qw));
+                    for (int va = W.v0; va < W.v1; va += rows) {
+                        const int vb = min(W.v1, va + rows);
+                        __syncthreads();
+                        stage(W.view, 0, qw, ua, va, qw * (vb - va), vb - va);
+                        __syncthreads();
+                        if (valid) gather(W, C, 0, qw, ua, va, max(k0, va), min(k1, vb - 1), max(uL, ua), min(uH, ub - 1));
+                    }
+                }
+                __syncthreads();
+                if (j + 1 < nvr && wv[j + 1].fast) {
+                    const WinView& Wn = wv[j + 1];
+                    stage(Wn.view, b ^ 1, max(1, Wn.u1 - Wn.u0), Wn.u0, Wn.v0, (Wn.u1 - Wn.u0) * (Wn.v1 - Wn.v0),
+                          Wn.v1 - Wn.v0);
+                    __syncthreads();
+                }
+            }
+        }
+    }
+
+    const int nxJ = a.box.x1 - a.box.x0, nyJ = a.box.y1 - a.box.y0;
+    const size_t gix = ((size_t)iz * G.ny + iy) * G.nx + ix;
+    if (a.fused) {
+        if (valid) {
+            const int nzJ = a.box.z1 - a.box.z0;
+            const int jx = ix - a.box.x0, jy = iy - a.box.y0, jz = iz - a.box.z0;
+            const float2 v = make_float2(a.x[gix], acc);
+            float2* basep = a.xg + (size_t)gi * a.xg_stride + xg_pad(nxJ, nyJ, nzJ);
+            basep[(jz * nyJ + jy) * nxJ + jx] = v;
+            basep[xg_copy(nxJ, nyJ, nzJ) + (jz * nxJ + jx) * nyJ + jy] = v;
+        }
+        const double p = valid ? (double)acc * (double)acc : 0.0;
+        const double tsum = block_sum256(p, sh);
+        if (threadIdx.x == 0) a.partial[(size_t)gi * n_tiles + bt] = tsum;
+    } else if (valid) {
+        a.g[gix] = (a.flags & 1) ? a.g[gix] + acc : acc;
+    }
+}
+
+template <class BA>
+__global__ __launch_bounds__(256, kColWG) void k_back3c(DGeom G, BA a) {
+    back3c_body(G, a, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // ----------------------------------------------------------------------------
@@ -1445,11 +1890,18 @@ __device__ __forceinline__ bool batch_step(const BatchArgs& B, const int k, cons
     return sr.n_groups > 0;            // a column without groups is skipped, as alone
 }
 
-__device__ __forceinline__ void box_tiles(const Box& b, const int dims, int& tx, int& ty, int& tz) {
+__device__ __forceinline__ void box_tiles(const Box& b, const int dims, const int vertical, int& tx, int& ty,
+                                          int& tz) {
     if (dims == 2) {
         tx = (b.x1 - b.x0 + kTile2 - 1) / kTile2;
         ty = (b.y1 - b.y0 + kTile2 - 1) / kTile2;
         tz = 1;
+    } else if (vertical) {
+        int TZ, CX, CY;
+        col_tile_shape(b.z1 - b.z0, TZ, CX, CY);
+        tx = (b.x1 - b.x0 + CX - 1) / CX;
+        ty = (b.y1 - b.y0 + CY - 1) / CY;
+        tz = (b.z1 - b.z0 + TZ - 1) / TZ;
     } else {
         tx = (b.x1 - b.x0 + kTile3x - 1) / kTile3x;
         ty = (b.y1 - b.y0 + kTile3y - 1) / kTile3y;
@@ -1464,7 +1916,7 @@ __device__ __forceinline__ int box_vox(const Box& b) {
 // occupancy as the single-job kernels: eight waves per SIMD in 2D, six in 3D;
 // NW waves per 2D tile (the 3D tile always takes four)
 template <int KIND, int NW>
-__global__ __launch_bounds__(64 * NW, KIND == kCone ? 6 : (NW <= 4 ? 8 : 32 / NW)) void kb_back(BatchArgs B) {
+__global__ __launch_bounds__(64 * NW, KIND == kCone ? 6 : (KIND == kConeV ? kColWG : (NW <= 4 ? 8 : 32 / NW))) void kb_back(BatchArgs B) {
     const int k = batch_job(B, blockIdx.x);
     const int L = blockIdx.x - B.prefix[k];
     const BJob J = cld(B.jobs, k);
@@ -1473,7 +1925,7 @@ __global__ __launch_bounds__(64 * NW, KIND == kCone ? 6 : (NW <= 4 ? 8 : 32 / NW
     const DGeom G = J.G;
     BackCore a{};
     a.box = cld(J.boxes, sr.col);
-    box_tiles(a.box, G.dims, a.tiles_x, a.tiles_y, a.tiles_z);
+    box_tiles(a.box, G.dims, G.vertical, a.tiles_x, a.tiles_y, a.tiles_z);
     const int nt = a.tiles_x * a.tiles_y * a.tiles_z;
     const int gi = L / nt, tile = L - gi * nt;
     if (gi >= sr.n_groups) return;
@@ -1487,7 +1939,8 @@ __global__ __launch_bounds__(64 * NW, KIND == kCone ? 6 : (NW <= 4 ? 8 : 32 / NW
     a.vox_J = box_vox(a.box);
     a.xg_stride = xg_size(a.box.x1 - a.box.x0, a.box.y1 - a.box.y0, a.box.z1 - a.box.z0);
     a.partial = J.pg;
-    if constexpr (KIND == kCone) back3_body(G, a, gi, tile, nt);
+    if constexpr (KIND == kConeV) back3c_body(G, a, gi, tile, nt);
+    else if constexpr (KIND == kCone) back3_body(G, a, gi, tile, nt);
     else back2_body<KIND, BackCore, NW>(G, a, gi, tile, nt);
 }
 
@@ -1526,7 +1979,7 @@ __global__ __launch_bounds__(256) void kb_step(BatchArgs B) {
     if (L >= sr.n_groups) return;
     const Box box = cld(J.boxes, sr.col);
     int tx, ty, tz;
-    box_tiles(box, J.G.dims, tx, ty, tz);
+    box_tiles(box, J.G.dims, J.G.vertical, tx, ty, tz);
     StepArgs a{};
     a.ent = J.ent + sr.ent_off;
     a.gptr = J.gptr + sr.gptr_off;
@@ -1713,7 +2166,9 @@ static hipError_t launch_back_as(const DGeom& G, const BA& a, int n_groups, int 
     const int nt = a.tiles_x * a.tiles_y * a.tiles_z;
     if (nt <= 0 || n_groups <= 0) return hipSuccess;
     const dim3 grid(nt, n_groups);
-    if (G.kind == kCone) {
+    if (G.kind == kCone && G.vertical) {
+        hipLaunchKernelGGL(k_back3c<BA>, grid, dim3(256), 0, st, G, a);
+    } else if (G.kind == kCone) {
         hipLaunchKernelGGL(k_back3<BA>, grid, dim3(256), 0, st, G, a);
     } else if (waves == 1) {
         launch_back2<BA, 1>(G, a, grid, st);
@@ -1761,7 +2216,7 @@ static hipError_t launch_batch_kind(int phase, const BatchArgs& b, int blocks, c
                                     hipStream_t st) {
     const dim3 grid(blocks);
     if (phase == kPhBack) {
-        if constexpr (KIND == kCone) {
+        if constexpr (KIND == kCone || KIND == kConeV) {
             hipLaunchKernelGGL((kb_back<KIND, 4>), grid, dim3(256), 0, st, b);
         } else {
             if (t.waves == 1) hipLaunchKernelGGL((kb_back<KIND, 1>), grid, dim3(64), 0, st, b);
@@ -1772,9 +2227,11 @@ static hipError_t launch_batch_kind(int phase, const BatchArgs& b, int blocks, c
             else return hipErrorInvalidValue;
         }
     } else {
-        if (t.split == 1) hipLaunchKernelGGL((kb_fwd<KIND, 1>), grid, dim3(kChunk), 0, st, b);
-        else if (t.split == 2) hipLaunchKernelGGL((kb_fwd<KIND, 2>), grid, dim3(2 * kChunk), 0, st, b);
-        else if (t.split == 4) hipLaunchKernelGGL((kb_fwd<KIND, 4>), grid, dim3(4 * kChunk), 0, st, b);
+        // the forward walk of a kConeV geometry is the cone's
+        constexpr int FK = KIND == kConeV ? kCone : KIND;
+        if (t.split == 1) hipLaunchKernelGGL((kb_fwd<FK, 1>), grid, dim3(kChunk), 0, st, b);
+        else if (t.split == 2) hipLaunchKernelGGL((kb_fwd<FK, 2>), grid, dim3(2 * kChunk), 0, st, b);
+        else if (t.split == 4) hipLaunchKernelGGL((kb_fwd<FK, 4>), grid, dim3(4 * kChunk), 0, st, b);
         else return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1789,6 +2246,7 @@ hipError_t launch_batch(int phase, int kind, const BatchArgs& b, int blocks, con
                 case kPar2D: return launch_batch_kind<kPar2D>(phase, b, blocks, t, st);
                 case kFanFlat: return launch_batch_kind<kFanFlat>(phase, b, blocks, t, st);
                 case kFanCurved: return launch_batch_kind<kFanCurved>(phase, b, blocks, t, st);
+                case kConeV: return launch_batch_kind<kConeV>(phase, b, blocks, t, st);
                 default: return launch_batch_kind<kCone>(phase, b, blocks, t, st);
             }
         case kPhStep: hipLaunchKernelGGL(kb_step, dim3(blocks), dim3(256), 0, st, b); break;

@@ -66,7 +66,7 @@ def test_true_residual_matches_oracle(ct, name):
 
 
 @pytest.mark.parametrize("name,E,alpha,s,b,sync,seed", [
-    ("c1_par2d", 20, 0.5, 1, 0.5, "column", 4200),
+    ("c1_par2d", 21, 0.5, 1, 0.5, "column", 4200),
     ("fan_curved", 12, 1.0, 2, 1.0, "epoch", 4201),
     ("cone", 6, 1.0, 3, 1.0, "column", 4202),
 ])

@@ -570,3 +570,35 @@ def test_area_matches_hit_bins_and_normalises(name):
     for J in range(g.n):
         if S[:, J].sum() > 0:
             assert P[:, J].sum() == pytest.approx(1.0, abs=1e-12)
+
+
+@pytest.mark.parametrize("name", ["fan_flat", "cone"])
+def test_matrix_free_group_step_equals_explicit(name):
+    """The matrix-free group step (rows generated chunk by chunk, cut to the
+    columns of J, generated twice) gives the explicit step's g-update, step
+    size and z rows; and with beta = 1 its A g is orthogonal to the new
+    residual (Eq. 11), against a dense pairwise-clip A."""
+    g = tiny_geoms()[name]
+    A = siddon.system_matrix(g)
+    S = csgd.BlockSystem(A, g)
+    rng = np.random.default_rng(11)
+    y = rng.uniform(0.5, 1.5, g.n_rays)
+    x0 = rng.uniform(0.0, 0.3, g.n_vox)
+    Ad = dense_clip(g)
+    for G in ([0], [1, 0]):
+        for J in range(g.n):
+            st = csgd.State(S, y, x0)
+            r0 = st.r.copy()
+            xnew, mu, rows = csgd.step_group(st, G, J, 1.0)
+            xm, mum, zm, nnz = csgd.step_group_matrix_free(g, S.group_rows(G), J, x0, r0, 1.0, chunk=7)
+            assert nnz == S.group(G, J).nnz
+            assert abs(mum - mu) <= 1e-12 * max(abs(mu), 1e-300)
+            np.testing.assert_allclose(xm, xnew, rtol=1e-12, atol=1e-14)
+            np.testing.assert_allclose(zm, st.z[J, rows], rtol=1e-12, atol=1e-13)
+            # Eq. (11) with beta = 1: (A g)^T (r - mu A g) = 0 on the group's rows
+            vox = S.vox[J]
+            AGJ = Ad[np.ix_(rows, vox)]
+            gd = AGJ.T @ r0[rows]
+            q = AGJ @ gd
+            if gd @ gd > 0:
+                assert abs(q @ (r0[rows] - mum * q)) <= 1e-10 * (q @ q) * max(mum, 1.0)
