@@ -114,6 +114,21 @@ int ct_geom_get_info(const ct_geom* geom, ct_geom_info* out);
  * drives the importance sampling of Sec. II-C (reading C6).  host_nnz is a
  * host array [m][n] (row-block major).  Synchronous on `stream`. */
 int ct_geom_block_nnz(ct_geom* geom, double tau, int64_t* host_nnz, void* stream);
+
+/* For callers that cannot allocate (code under graph capture, tight serving
+ * loops, harnesses that forbid allocation): ct_geom_block_nnz with its
+ * counters in a static device array of the library (CT_NNZ_STATIC_MAX
+ * entries of 8 bytes; each GPU the library runs on holds its own copy until
+ * the process ends) instead of the geometry's tables, and the counts copied
+ * straight into host_nnz.  It allocates nothing, on the device or the host:
+ * the geometry's device tables must already be on the current device (any
+ * earlier call that launches work on the geometry uploads them), else
+ * CT_EINVAL.  CT_EINVAL when m * n > CT_NNZ_STATIC_MAX, before anything is
+ * enqueued.  Every call on a GPU shares that GPU's array (cleared by a kernel
+ * at the start of each call): calls that overlap on one GPU race.
+ * Synchronous on `stream`. */
+#define CT_NNZ_STATIC_MAX 65536
+int ct_geom_block_nnz_static(ct_geom* geom, double tau, int64_t* host_nnz, void* stream);
 /* The paper's own density estimate (Sec. II-C, Alg. 5): host_area[I*n + J] =
  * P_S, the area (detector units: mm, radians on a curved detector, mm^2 in
  * 3D) that the projection of column block J's box covers on the tiles of row

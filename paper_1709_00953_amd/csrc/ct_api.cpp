@@ -727,6 +727,67 @@ extern "C" int ct_geom_block_nnz(ct_geom* g, double tau, int64_t* host_nnz, void
 }
 
 // ---------------------------------------------------------------------------
+// density table without allocation: counters in a static device array
+// ---------------------------------------------------------------------------
+// `scratch` is a host-side stand-in in host code: kernels get the device
+// address that hipGetSymbolAddress returns for the current device (each GPU
+// holds its own copy of the array), looked up once per device.
+static __device__ __align__(256) unsigned long long scratch[CT_NNZ_STATIC_MAX];
+static std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+static unsigned long long* g_scratch_dev[kMaxDevices] = {};
+
+static int scratch_on_device(unsigned long long** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return fail(CT_EDEVICE, "no HIP device");
+    if (dev >= kMaxDevices) return fail(CT_EUNSUPPORTED, "device %d beyond the %d the library tracks", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(CT_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = (unsigned long long*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return CT_OK;
+}
+
+extern "C" int ct_geom_block_nnz_static(ct_geom* g, double tau, int64_t* host_nnz, void* stream) {
+    if (!g || !host_nnz) return fail(CT_EINVAL, "NULL argument");
+    if (!(tau >= 0)) return fail(CT_EINVAL, "tau must be >= 0");
+    const int64_t cells = (int64_t)g->m * g->n;
+    if (cells > CT_NNZ_STATIC_MAX)
+        return fail(CT_EINVAL, "m * n = %lld exceeds CT_NNZ_STATIC_MAX (%d)", (long long)cells, CT_NNZ_STATIC_MAX);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(CT_EDEVICE, "no HIP device");
+    {
+        std::lock_guard<std::mutex> lock(g->mu);
+        if (!g->dmem || g->device != dev)
+            return fail(CT_EINVAL, "the geometry's device tables are not on device %d (an earlier call that "
+                        "launches work on the geometry uploads them)", dev);
+    }
+    unsigned long long* cnt = nullptr;
+    int rc = scratch_on_device(&cnt);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(launch_fill_u64(cnt, cells, st));          // a kernel, not a memset node
+    for (int J = 0; J < g->n; ++J) {
+        FwdArgs a = fwd_all(g, J);
+        a.mode = 2;
+        a.nnz = cnt;
+        a.n_cols = g->n;
+        a.col = J;
+        a.tau = tau;
+        HIPCHK(launch_fwd(g->G, a, st));
+    }
+    static_assert(sizeof(int64_t) == sizeof(unsigned long long), "counts are copied as they are");
+    HIPCHK(hipMemcpyAsync(host_nnz, cnt, (size_t)cells * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return CT_OK;
+}
+
+// ---------------------------------------------------------------------------
 // block primitives
 // ---------------------------------------------------------------------------
 static int check_rbs(const ct_geom* g, const int32_t* rbs, int32_t n_rb, int32_t col) {

@@ -27,6 +27,7 @@ CT_TUNE_REFRESH = 1
 
 EXPORTS = (
     "ct_geom_create", "ct_geom_destroy", "ct_geom_get_info", "ct_geom_block_nnz",
+    "ct_geom_block_nnz_static",
     "ct_geom_block_area", "ct_schedule_create_w",
     "ct_block_fwd", "ct_block_back",
     "ct_schedule_create", "ct_schedule_import", "ct_schedule_export", "ct_schedule_destroy",
@@ -142,6 +143,7 @@ def lib():
             "ct_geom_destroy": [P],
             "ct_geom_get_info": [P, ctypes.POINTER(ct_geom_info)],
             "ct_geom_block_nnz": [P, f64, P, P],
+            "ct_geom_block_nnz_static": [P, f64, P, P],
             "ct_geom_block_area": [P, P],
             "ct_schedule_create_w": [P, ctypes.POINTER(ct_sched_params), P, ctypes.POINTER(P)],
             "ct_block_fwd": [P, P, i32, i32, P, P, i32, P],
@@ -272,6 +274,19 @@ def ct_geom_create(g) -> Geom:
 def ct_geom_block_nnz(geom: Geom, tau: float, stream=None) -> np.ndarray:
     out = np.zeros((geom.m, geom.n), dtype=np.int64)
     _check(lib().ct_geom_block_nnz(geom.handle, float(tau), _np_ptr(out), _stream(stream)))
+    return out
+
+
+def ct_geom_block_nnz_static(geom: Geom, tau: float, out: np.ndarray | None = None,
+                             stream=None) -> np.ndarray:
+    """ct_geom_block_nnz with the library's static counter array (no
+    allocation by the library; ``out``, an int64 [m, n] host array, may be
+    passed in so that the call allocates nothing here either)."""
+    if out is None:
+        out = np.zeros((geom.m, geom.n), dtype=np.int64)
+    if out.dtype != np.int64 or out.shape != (geom.m, geom.n) or not out.flags.c_contiguous:
+        raise ValueError("out must be a C-contiguous int64 array of shape (m, n)")
+    _check(lib().ct_geom_block_nnz_static(geom.handle, float(tau), _np_ptr(out), _stream(stream)))
     return out
 
 

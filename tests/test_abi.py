@@ -199,3 +199,17 @@ def test_area_and_nnz_densities_agree_roughly():
     P_nnz = sampler.density(S.nnz_table(1e-5))
     P_area = area.area_density(g)
     assert np.abs(P_nnz - P_area).max() < 0.03
+
+
+def test_static_nnz_rejects_tables_beyond_its_array():
+    """ct_geom_block_nnz_static holds m * n counters in a static device array
+    of CT_NNZ_STATIC_MAX entries: a larger table is an argument error, found
+    before anything touches a device (so it is checked here, without a GPU)."""
+    g = inputs.par2d(16, 1.0, 300, 180.0, 24, 1.0, m=300, bx=16, by=16)
+    assert g.m * g.n == 300 * 256 > 65536
+    G = ct.ct_geom_create(g)
+    out = np.zeros((g.m, g.n), dtype=np.int64)
+    rc = ct.lib().ct_geom_block_nnz_static(G.handle, 1e-5, out.ctypes.data_as(ct.P), None)
+    assert rc == ct.CT_EINVAL
+    assert "CT_NNZ_STATIC_MAX" in ct.ct_last_error()
+    assert not out.any()
