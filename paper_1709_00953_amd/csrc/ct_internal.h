@@ -30,15 +30,16 @@ enum { kPar2D = 0, kFanFlat = 1, kFanCurved = 2, kCone = 3 };
 // xy plane): its back-projection takes the voxel-column kernel.
 constexpr int kConeV = 4;
 
-// Voxel-column tile of that kernel: 256 lanes = NC columns x TZ voxels in z
-// (z fastest), the columns CX x CY.  TZ is the largest power of two up to 32
-// whose tiles waste at most 1/8 of the lanes over the box's nz voxels
-// (at least 1).
+// Voxel-column tile of that kernel: CX x CY columns of TZ voxels in z, 256
+// lanes, each lane two voxels of a column (z and z + TZ / 2; one when TZ =
+// 1).  TZ is the largest power of two up to 32 whose tiles waste at most 1/8
+// of the voxels over the box's nz (at least 1).
+__host__ __device__ inline int col_vz(int tz) { return tz >= 2 ? 2 : 1; }
 __host__ __device__ inline void col_tile_shape(int nz, int& tz, int& cx, int& cy) {
     int t = 32;
     while (t > 1 && ((nz + t - 1) / t) * t - nz > nz / 8) t >>= 1;
     tz = t;
-    const int nc = 256 / t;                  // 8 .. 256 columns
+    const int nc = 256 / (t / col_vz(t));    // 16 .. 256 columns
     int lg = 0;
     while ((1 << lg) < nc) ++lg;
     cx = 1 << ((lg + 1) / 2);

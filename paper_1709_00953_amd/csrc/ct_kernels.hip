@@ -1372,7 +1372,7 @@ __global__ __launch_bounds__(256, 6) void k_back3(DGeom G, BA a) {
 constexpr int kColWG = 6;         // resident work-groups per CU the register budget is set for
 constexpr int kColR = 512;        // rays of a view's window staged at once (fast path: the whole window)
 constexpr int kColV = 128;        // rows of a view's window staged at once
-constexpr int kColU = 4;          // X intervals kept per (view, column)
+constexpr int kColU = 2;          // X intervals kept per (view, column); wider columns form the rest
 
 // Per (view, column) of a round: A of the column's centre, 1 / A at the near
 // and far edge of its footprint, its bins [u0, u1] and X of the first kColU.
@@ -1425,25 +1425,28 @@ template <class BA>
 __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const int gi, const int bt,
                                             const int n_tiles) {
     __shared__ ColView cv[256];                  // [view slot][column]
-    __shared__ WinView wv[32];                   // [view slot]
+    __shared__ WinView wv[16];                   // [view slot] (at least 16 columns: at most 16 views a round)
     __shared__ float sR[2][kColR];               // |D~| r of a window's rays; two views in flight
     __shared__ double sI[2][kColV];              // sdd / D_z of its rows
     __shared__ double sh[4];
     const int t = threadIdx.x;
     int TZ, CX, CY;
     col_tile_shape(a.box.z1 - a.box.z0, TZ, CX, CY);
-    const int NC = CX * CY, NVR = 256 / NC;      // columns; views per round (at most 32)
+    const int VZ = col_vz(TZ), TL = TZ / VZ;     // voxels a lane, lanes a column
+    const int NC = CX * CY, NVR = 256 / NC;      // columns; views per round
     const int tiles_x = a.tiles_x, tiles_y = a.tiles_y;
     const int tx = bt % tiles_x, ty = (bt / tiles_x) % tiles_y, tz = bt / (tiles_x * tiles_y);
     const int xs = a.box.x0 + tx * CX, ys = a.box.y0 + ty * CY, zs = a.box.z0 + tz * TZ;
     const int nvx = min(CX, a.box.x1 - xs), nvy = min(CY, a.box.y1 - ys), nvz = min(TZ, a.box.z1 - zs);
-    // this lane's voxel: column c (cx, cy), level lz
-    const int lz = t % TZ, c = t / TZ;
+    // this lane's voxels: column c (cx, cy), levels lz and lz + TL
+    const int lz = t % TL, c = t / TL;
     const int ccx = c % CX, ccy = c / CX;
-    const int ix = xs + ccx, iy = ys + ccy, iz = zs + lz;
-    const bool valid = ccx < nvx && ccy < nvy && lz < nvz;
-    const double c0u = 0.5 * (double)(G.nu - 1), c0v = 0.5 * (double)(G.nv - 1);
-    const double zlo = G.oz + (double)iz * G.vz, zhi = zlo + G.vz;
+    const int ix = xs + ccx, iy = ys + ccy;
+    const bool colv = ccx < nvx && ccy < nvy;
+    const bool valid0 = colv && lz < nvz, valid1 = colv && VZ == 2 && lz + TL < nvz;
+    const double c0v = 0.5 * (double)(G.nv - 1);
+    const float fc0v = (float)c0v, ipv = (float)(1.0 / G.pv);
+    const double zlo0 = G.oz + (double)(zs + lz) * G.vz, zlo1 = zlo0 + (double)TL * G.vz;
 
     int e0 = 0, e1 = a.n_ent;
     if (a.gptr) {
@@ -1456,14 +1459,18 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
         nt += G.rb_tile_ptr[rb + 1] - G.rb_tile_ptr[rb];
     }
 
-    // rays [0, nr) (rows of pw bins from (ua, va)) and rows [0, nrow) of
-    // view `view`'s window part into buffer b
+    // rays [0, nr) (rows of pw bins from (ua, va)) and rows [0, nrow) of a
+    // window part of `view` into buffer b
     auto stage = [&](int view, int b, int pw, int ua, int va, int nr, int nrow) {
         const float* rview = a.r + (size_t)view * G.nv * G.nu;
         const float2* dxy = G.cdxy + (size_t)view * G.nu;
         const float* dz = G.cdz + (size_t)view * G.nv;
+        // row of element i: (i + 1/2) / pw lies at least 1/(2 pw) from an
+        // integer, far beyond the rounding of rcp and the product for i < 2^12
+        const float ipw = __builtin_amdgcn_rcpf((float)pw);
         for (int i = t; i < nr; i += 256) {
-            const int row = i / pw, iu = ua + (i - row * pw), iv = va + row;
+            const int row = (int)(((float)i + 0.5f) * ipw);
+            const int iu = ua + (i - row * pw), iv = va + row;
             const float2 q = ldu(dxy, (unsigned)iu);
             const float z = ldu(dz, (unsigned)iv);
             const float nrm = __builtin_amdgcn_sqrtf(fmaf(q.x, q.x, fmaf(q.y, q.y, z * z)));
@@ -1473,18 +1480,38 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
         for (int i = t; i < nrow; i += 256) sI[b][i] = ldu(isv, (unsigned)(va + i));
     };
 
-    float acc = 0.f;
-    // this voxel's part from rows [ka, kb] and bins [uL, uH] of a staged part
-    // of view slot j (buffer b; rows from va, bins from ua, pw bins a row)
-    auto gather = [&](const WinView& W, const ColView& C, int b, int pw, int ua, int va, int ka, int kb,
-                      int uL, int uH) {
-        const double A = C.A, zfl = zlo - W.zS, zfh = zhi - W.zS;
-        for (int k = ka; k <= kb; ++k) {
+    float acc0 = 0.f, acc1 = 0.f;
+    // a voxel's rows of view W: the projections of its box's corners (zlo: its
+    // lower face), clipped to [va, vb]
+    auto rows_of = [&](const WinView& W, const ColView& C, double zlo, int va, int vb, int& k0, int& k1) {
+        if (!(C.ia0 < INFINITY)) {                 // footprint at the source's depth: every row
+            k0 = va;
+            k1 = vb;
+            return;
+        }
+        const float f0 = (float)((double)W.ssv * (zlo - W.zS)), f1 = f0 + (float)((double)W.ssv * G.vz);
+        const float p0 = f0 * C.ia0, p1 = f0 * C.ia1, q0 = f1 * C.ia0, q1 = f1 * C.ia1;
+        const float lo = fmaf(fminf(fminf(p0, p1), fminf(q0, q1)), ipv, fc0v);
+        const float hi = fmaf(fmaxf(fmaxf(p0, p1), fmaxf(q0, q1)), ipv, fc0v);
+        k0 = max(va, (int)ceilf(lo - 1e-3f - 1e-6f * fabsf(lo)));
+        k1 = min(vb, (int)floorf(hi + 1e-3f + 1e-6f * fabsf(hi)));
+    };
+    // one voxel's part from rows [k0, k1] of a staged part (buffer b, rows
+    // from va, bins [ua, ub) of pw a row) of view W
+    auto gather = [&](const WinView& W, const ColView& C, int b, int pw, int ua, int ub, int va, double zlo,
+                      int k0, int k1, float& acc) {
+        const double A = C.A, zfl = zlo - W.zS, zfh = zfl + G.vz;
+        const int uL = max(C.u0, ua), uH = min(C.u1, ub - 1);
+        const float2 X0 = C.X[0], X1 = C.X[1];
+        const bool s0 = C.u0 >= uL && C.u0 <= uH, s1 = C.u0 + 1 >= uL && C.u0 + 1 <= uH;
+        const int r0 = C.u0 - ua;
+        for (int k = k0; k <= k1; ++k) {
             const double isv = sI[b][k - va];
             float zl, zh;
             if (W.careful && isv == 0.0) {
                 // a horizontal ray stays at the source's height
-                const bool in = iz == src_slab(W.zS, G.oz, G.ivz);
+                const bool in = __builtin_amdgcn_readfirstlane(src_slab(W.zS, G.oz, G.ivz)) ==
+                                (int)floor((zlo - G.oz) * G.ivz + 0.5);
                 zl = in ? -INFINITY : INFINITY;
                 zh = in ? INFINITY : -INFINITY;
             } else {
@@ -1492,39 +1519,31 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                 zl = fminf(p, q);
                 zh = fmaxf(p, q);
             }
-            const int ro = (k - va) * pw - ua;
-            for (int u = uL; u <= uH; ++u) {
-                const int i = u - C.u0;
-                float2 xi;
-                if (i < kColU) {
-                    xi = C.X[i];
-                } else {
-                    // a column more than kColU bins wide: X formed here
-                    const double* V = view_of(G, W.view);
-                    const double qx = G.ox + ((double)ix + 0.5) * G.vx - V[0];
-                    const double qy = G.oy + ((double)iy + 0.5) * G.vy - V[1];
-                    xi = col_interval(G, V, ldu(G.cdxy + (size_t)W.view * G.nu, (unsigned)u), A,
-                                      fma(qx, V[6], qy * V[7]), u, ix, iy, src_slab(V[0], G.ox, G.ivx),
-                                      src_slab(V[1], G.oy, G.ivy));
-                }
-                const float lo = fmaxf(xi.x, zl), hi = fminf(xi.y, zh);
-                acc = fmaf(fmaxf(hi - lo, 0.f), sR[b][ro + u], acc);
+            const int ro = (k - va) * pw;
+            if (s0) acc = fmaf(fmaxf(fminf(X0.y, zh) - fmaxf(X0.x, zl), 0.f), sR[b][ro + r0], acc);
+            if (s1) acc = fmaf(fmaxf(fminf(X1.y, zh) - fmaxf(X1.x, zl), 0.f), sR[b][ro + r0 + 1], acc);
+            for (int u = max(uL, C.u0 + kColU); u <= uH; ++u) {
+                // a column more than kColU bins wide: X formed here
+                const double* V = view_of(G, W.view);
+                const double qx = G.ox + ((double)ix + 0.5) * G.vx - V[0];
+                const double qy = G.oy + ((double)iy + 0.5) * G.vy - V[1];
+                const float2 xi = col_interval(G, V, ldu(G.cdxy + (size_t)W.view * G.nu, (unsigned)u), A,
+                                               fma(qx, V[6], qy * V[7]), u, ix, iy, src_slab(V[0], G.ox, G.ivx),
+                                               src_slab(V[1], G.oy, G.ivy));
+                acc = fmaf(fmaxf(fminf(xi.y, zh) - fmaxf(xi.x, zl), 0.f), sR[b][ro + u - ua], acc);
             }
         }
     };
-    // this voxel's rows: the projections of its box's corners
-    auto rows_of = [&](const WinView& W, const ColView& C, int& k0, int& k1) {
-        if (!(C.ia0 < INFINITY)) {                 // footprint at the source's depth: every row
-            k0 = W.v0;
-            k1 = W.v1 - 1;
-            return;
+    auto both = [&](const WinView& W, const ColView& C, int b, int pw, int ua, int ub, int va, int vb) {
+        int k0, k1;
+        if (valid0) {
+            rows_of(W, C, zlo0, va, vb - 1, k0, k1);
+            gather(W, C, b, pw, ua, ub, va, zlo0, k0, k1, acc0);
         }
-        const float f0 = (float)(W.ssv * (zlo - W.zS)), f1 = (float)(W.ssv * (zhi - W.zS));
-        const float vmin = fminf(fminf(f0 * C.ia0, f0 * C.ia1), fminf(f1 * C.ia0, f1 * C.ia1));
-        const float vmax = fmaxf(fmaxf(f0 * C.ia0, f0 * C.ia1), fmaxf(f1 * C.ia0, f1 * C.ia1));
-        const float ipv = (float)(1.0 / G.pv), fc = (float)c0v;
-        k0 = max(W.v0, (int)ceilf(fmaf(vmin, ipv, fc) - 1e-3f - 1e-6f * fabsf(vmin * ipv)));
-        k1 = min(W.v1 - 1, (int)floorf(fmaf(vmax, ipv, fc) + 1e-3f + 1e-6f * fabsf(vmax * ipv)));
+        if (valid1) {
+            rows_of(W, C, zlo1, va, vb - 1, k0, k1);
+            gather(W, C, b, pw, ua, ub, va, zlo1, k0, k1, acc1);
+        }
     };
 
     for (int base = 0; base < nt; base += NVR) {
@@ -1547,6 +1566,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                 }
                 const double* V = view_of(G, tl.view);
                 const double sdd = V[15];
+                const double c0u = 0.5 * (double)(G.nu - 1);
                 const int jx = xs + (cc % CX), jy = ys + (cc / CX);
                 const double qx = G.ox + ((double)jx + 0.5) * G.vx - V[0];
                 const double qy = G.oy + ((double)jy + 0.5) * G.vy - V[1];
@@ -1574,8 +1594,8 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                         umin = fminf(umin, uu);
                         umax = fmaxf(umax, uu);
                     }
-                    const float s = (float)(sdd / G.pu), fc = (float)c0u;
-                    const float bl = fmaf(umin, s, fc), bh = fmaf(umax, s, fc);
+                    const float su = (float)(sdd / G.pu), fc = (float)c0u;
+                    const float bl = fmaf(umin, su, fc), bh = fmaf(umax, su, fc);
                     u0 = max(u0, (int)ceilf(bl - 1e-3f - 1e-6f * fabsf(bl)));
                     u1 = min(u1, (int)floorf(bh + 1e-3f + 1e-6f * fabsf(bh)));
                 }
@@ -1623,8 +1643,8 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                         wu0 = max(wu0, (int)ceilf(bl - 1e-3f - 1e-6f * fabsf(bl)));
                         wu1 = min(wu1, (int)floorf(bh + 1e-3f + 1e-6f * fabsf(bh)) + 1);
                         // v = sdd e_v,z (z - z_S) / A: scale the extremes by ssv
-                        const float sv = ssv / (float)G.pv, fv = (float)c0v;
-                        const float cl = fminf(vmin * sv, vmax * sv) + fv, ch = fmaxf(vmin * sv, vmax * sv) + fv;
+                        const float sv = ssv * ipv;
+                        const float cl = fminf(vmin * sv, vmax * sv) + fc0v, ch = fmaxf(vmin * sv, vmax * sv) + fc0v;
                         wv0 = max(wv0, (int)ceilf(cl - 1e-3f - 1e-6f * fabsf(cl)));
                         wv1 = min(wv1, (int)floorf(ch + 1e-3f + 1e-6f * fabsf(ch)) + 1);
                     }
@@ -1650,22 +1670,18 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
             const ColView& C = cv[j * NC + c];
             const int b = j & 1;
             const int fast = __builtin_amdgcn_readfirstlane(W.fast);
-            const int pw = max(1, W.u1 - W.u0);
-            int k0 = 1, k1 = 0;
-            if (valid) rows_of(W, C, k0, k1);
-            const int uL = max(C.u0, W.u0), uH = min(C.u1, W.u1 - 1);
             if (fast) {
                 if (j + 1 < nvr && wv[j + 1].fast) {
                     const WinView& Wn = wv[j + 1];
                     stage(Wn.view, b ^ 1, max(1, Wn.u1 - Wn.u0), Wn.u0, Wn.v0, (Wn.u1 - Wn.u0) * (Wn.v1 - Wn.v0),
                           Wn.v1 - Wn.v0);
                 }
-                if (valid) gather(W, C, b, pw, W.u0, W.v0, k0, k1, uL, uH);
+                both(W, C, b, max(1, W.u1 - W.u0), W.u0, W.u1, W.v0, W.v1);
                 __syncthreads();
             } else {
                 // a window too large to stage whole: parts of at most kColR
                 // rays and kColV rows, each between two barriers
-                const int ppw = max(1, min(pw, kColR));
+                const int pw = max(1, W.u1 - W.u0), ppw = min(pw, kColR);
                 for (int ua = W.u0; ua < W.u1; ua += ppw) {
                     const int ub = min(W.u1, ua + ppw), qw = ub - ua;
                     const int rows = max(1, min(kColV, kColR / qw));
@@ -1674,7 +1690,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                         __syncthreads();
                         stage(W.view, 0, qw, ua, va, qw * (vb - va), vb - va);
                         __syncthreads();
-                        if (valid) gather(W, C, 0, qw, ua, va, max(k0, va), min(k1, vb - 1), max(uL, ua), min(uH, ub - 1));
+                        both(W, C, 0, qw, ua, ub, va, vb);
                     }
                 }
                 __syncthreads();
@@ -1688,22 +1704,29 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
         }
     }
 
-    const int nxJ = a.box.x1 - a.box.x0, nyJ = a.box.y1 - a.box.y0;
-    const size_t gix = ((size_t)iz * G.ny + iy) * G.nx + ix;
-    if (a.fused) {
-        if (valid) {
-            const int nzJ = a.box.z1 - a.box.z0;
+    const int nxJ = a.box.x1 - a.box.x0, nyJ = a.box.y1 - a.box.y0, nzJ = a.box.z1 - a.box.z0;
+    double p = 0.0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const bool valid = q == 0 ? valid0 : valid1;
+        const float acc = q == 0 ? acc0 : acc1;
+        const int iz = zs + lz + q * TL;
+        const size_t gix = ((size_t)iz * G.ny + iy) * G.nx + ix;
+        if (!valid) continue;
+        if (a.fused) {
             const int jx = ix - a.box.x0, jy = iy - a.box.y0, jz = iz - a.box.z0;
             const float2 v = make_float2(a.x[gix], acc);
             float2* basep = a.xg + (size_t)gi * a.xg_stride + xg_pad(nxJ, nyJ, nzJ);
             basep[(jz * nyJ + jy) * nxJ + jx] = v;
             basep[xg_copy(nxJ, nyJ, nzJ) + (jz * nxJ + jx) * nyJ + jy] = v;
+            p += (double)acc * (double)acc;
+        } else {
+            a.g[gix] = (a.flags & 1) ? a.g[gix] + acc : acc;
         }
-        const double p = valid ? (double)acc * (double)acc : 0.0;
+    }
+    if (a.fused) {
         const double tsum = block_sum256(p, sh);
         if (threadIdx.x == 0) a.partial[(size_t)gi * n_tiles + bt] = tsum;
-    } else if (valid) {
-        a.g[gix] = (a.flags & 1) ? a.g[gix] + acc : acc;
     }
 }
 
