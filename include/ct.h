@@ -407,9 +407,15 @@ int ct_batch_set_tuning(ct_batch* batch, int32_t kind, const ct_tuning* t);
  * resident jobs, and every check_every epochs (and at the epoch cap) a job's
  * true relative residual is computed asynchronously and read back at the next
  * tick, which retires the job once it is <= rel_tol or the cap is reached.
- * A retired job's x is copied to the host and its device memory freed.  The
- * server allocates device memory itself (hipMalloc).  All ticks of a server
- * must use the same stream. */
+ * A retired job's x is copied to the host and its device memory reused.  The
+ * server allocates its device memory once, when it is created: an arena of
+ * the budget, sub-allocated per job, and a pinned host staging ring (a
+ * quarter of the budget, 64 MiB .. 1 GiB) for every copy between host and
+ * device; a tick allocates and frees nothing and waits for the device only
+ * for the residual norms of the previous tick.  A job's density table is
+ * counted on the device when it is admitted and read back asynchronously, so
+ * it joins the batch's epochs from a later tick.  All ticks of a server must
+ * use the same stream. */
 typedef struct ct_server ct_server;
 typedef struct ct_server_params {
     int32_t capacity;           /* most resident jobs (1..256)                  */
@@ -447,8 +453,9 @@ typedef struct ct_server_stats {
 } ct_server_stats;
 int ct_server_create(const ct_server_params* params, ct_server** out);
 void ct_server_destroy(ct_server* server);
-/* Queues a job; CT_EINVAL if its geometry is invalid or it can never fit the
- * budget. */
+/* Queues a job (its geometry is validated and its host tables built here);
+ * CT_EINVAL if the geometry is invalid or the job can never fit the budget or
+ * the staging ring. */
 int ct_server_submit(ct_server* server, const ct_server_job* job, int32_t* id);
 /* Retire finished jobs, admit queued ones, run one batch epoch. */
 int ct_server_tick(ct_server* server, void* stream, ct_server_stats* stats);

@@ -70,6 +70,7 @@ struct ct_geom {
     int32_t vertical = 0;              // cone with detector columns along z (kConeV)
     int device = -1;
     void* dmem = nullptr;               // device tables, uploaded on first use
+    bool dmem_owned = true;             // false: placed in caller memory (geom_table_bind)
     size_t dbytes = 0;
     std::mutex mu;
     DGeom G{};
@@ -554,57 +555,51 @@ static DevLayout dev_layout(const ct_geom* g) {
     return L;
 }
 
-// Upload the device tables on first use (the current device becomes the
-// geometry's device).  Later calls must be made with that device current.
-static int geom_ensure_device(ct_geom* g) {
-    std::lock_guard<std::mutex> lock(g->mu);
-    int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess) return fail(CT_EDEVICE, "no HIP device");
-    if (g->dmem) {
-        if (dev != g->device) return fail(CT_EINVAL, "geometry lives on device %d, current is %d", g->device, dev);
-        return CT_OK;
-    }
-    const std::vector<double>& v64 = g->v64;
+// The device-table image of a geometry (layout dev_layout) packed into host
+// memory `dst` of geom_table_bytes(g) bytes.
+size_t geom_table_bytes(const ct_geom* g) { return dev_layout(g).total; }
+
+int geom_table_pack(const ct_geom* g, void* dst) {
+    const DevLayout L = dev_layout(g);
     std::vector<Ray2F> rayf;
     std::vector<Ray2B> rayb;
     std::vector<Ray2K> rayk;
     std::vector<int32_t> flags;
     build_frames(g, rayf, rayb, rayk, flags);
-    DevLayout L = dev_layout(g);
-    void* mem = nullptr;
-    if (hipMalloc(&mem, L.total) != hipSuccess)
-        return fail(CT_ENOMEM, "hipMalloc(%zu) for geometry tables failed", L.total);
-    char* base = (char*)mem;
-    auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
-        if (!bytes) return hipSuccess;
-        return hipMemcpy(base + off, src, bytes, hipMemcpyHostToDevice);
-    };
-    hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = up(L.off_view, v64.data(), v64.size() * sizeof(double));
-    if (e == hipSuccess) e = up(L.off_rayf, rayf.data(), rayf.size() * sizeof(Ray2F));
-    if (e == hipSuccess) e = up(L.off_rayb, rayb.data(), rayb.size() * sizeof(Ray2B));
-    if (e == hipSuccess) e = up(L.off_rayk, rayk.data(), rayk.size() * sizeof(Ray2K));
     std::vector<float2> cdxy;
     std::vector<float> cdz;
     std::vector<double> cisv;
     if (g->vertical) build_columns(g, cdxy, cdz, cisv);
-    if (e == hipSuccess) e = up(L.off_cdxy, cdxy.data(), cdxy.size() * sizeof(float2));
-    if (e == hipSuccess) e = up(L.off_cdz, cdz.data(), cdz.size() * sizeof(float));
-    if (e == hipSuccess) e = up(L.off_cisv, cisv.data(), cisv.size() * sizeof(double));
-    if (e == hipSuccess) e = up(L.off_flags, flags.data(), flags.size() * sizeof(int32_t));
-    if (e == hipSuccess) e = up(L.off_tiles, g->tiles.data(), g->tiles.size() * sizeof(Tile));
-    if (e == hipSuccess) e = up(L.off_rbt, g->rb_tile_ptr.data(), g->rb_tile_ptr.size() * sizeof(int32_t));
-    if (e == hipSuccess) e = up(L.off_troff, g->tile_roff.data(), g->tile_roff.size() * sizeof(int32_t));
-    if (e == hipSuccess) e = up(L.off_chunks, g->chunks.data(), g->chunks.size() * sizeof(Chunk));
-    if (e == hipSuccess) e = up(L.off_rbc, g->rb_chunk_ptr.data(), g->rb_chunk_ptr.size() * sizeof(int32_t));
-    if (e == hipSuccess) e = up(L.off_wch, g->wchunks.data(), g->wchunks.size() * sizeof(Chunk));
-    if (e == hipSuccess) e = up(L.off_rbj, g->rbj_chunk_ptr.data(), g->rbj_chunk_ptr.size() * sizeof(int32_t));
-    if (e == hipSuccess) e = up(L.off_all, g->all_entries.data(), g->all_entries.size() * sizeof(Entry));
-    if (e == hipSuccess) e = up(L.off_boxes, g->boxes.data(), g->boxes.size() * sizeof(Box));
-    if (e != hipSuccess) {
-        (void)hipFree(mem);
-        return fail(CT_EDEVICE, "geometry upload: %s", hipGetErrorString(e));
-    }
+    char* base = (char*)dst;
+    std::memset(base, 0, L.total);
+    auto put = [&](size_t off, const void* src, size_t bytes) {
+        if (bytes) std::memcpy(base + off, src, bytes);
+    };
+    put(L.off_view, g->v64.data(), g->v64.size() * sizeof(double));
+    put(L.off_rayf, rayf.data(), rayf.size() * sizeof(Ray2F));
+    put(L.off_rayb, rayb.data(), rayb.size() * sizeof(Ray2B));
+    put(L.off_rayk, rayk.data(), rayk.size() * sizeof(Ray2K));
+    put(L.off_cdxy, cdxy.data(), cdxy.size() * sizeof(float2));
+    put(L.off_cdz, cdz.data(), cdz.size() * sizeof(float));
+    put(L.off_cisv, cisv.data(), cisv.size() * sizeof(double));
+    put(L.off_flags, flags.data(), flags.size() * sizeof(int32_t));
+    put(L.off_tiles, g->tiles.data(), g->tiles.size() * sizeof(Tile));
+    put(L.off_rbt, g->rb_tile_ptr.data(), g->rb_tile_ptr.size() * sizeof(int32_t));
+    put(L.off_troff, g->tile_roff.data(), g->tile_roff.size() * sizeof(int32_t));
+    put(L.off_chunks, g->chunks.data(), g->chunks.size() * sizeof(Chunk));
+    put(L.off_rbc, g->rb_chunk_ptr.data(), g->rb_chunk_ptr.size() * sizeof(int32_t));
+    put(L.off_wch, g->wchunks.data(), g->wchunks.size() * sizeof(Chunk));
+    put(L.off_rbj, g->rbj_chunk_ptr.data(), g->rbj_chunk_ptr.size() * sizeof(int32_t));
+    put(L.off_all, g->all_entries.data(), g->all_entries.size() * sizeof(Entry));
+    put(L.off_boxes, g->boxes.data(), g->boxes.size() * sizeof(Box));
+    return CT_OK;
+}
+
+// Point the geometry's device view at a table image in device memory `mem`
+// on device `dev`.  owned: the geometry frees it when destroyed.
+static void geom_bind(ct_geom* g, void* mem, int dev, bool owned) {
+    const DevLayout L = dev_layout(g);
+    char* base = (char*)mem;
     DGeom& G = g->G;
     const ct_geom_desc& d = g->d;
     G.kind = d.kind;
@@ -657,6 +652,42 @@ static int geom_ensure_device(ct_geom* g) {
     g->dbytes = L.total;
     g->device = dev;
     g->dmem = mem;
+    g->dmem_owned = owned;
+}
+
+// The tables in caller memory `mem` (device), filled from a packed image
+// already copied there (or being copied, in stream order, before any use).
+int geom_table_bind(ct_geom* g, void* mem) {
+    std::lock_guard<std::mutex> lock(g->mu);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(CT_EDEVICE, "no HIP device");
+    if (g->dmem) return fail(CT_EINVAL, "geometry tables are already on a device");
+    geom_bind(g, mem, dev, false);
+    return CT_OK;
+}
+
+// Upload the device tables on first use (the current device becomes the
+// geometry's device).  Later calls must be made with that device current.
+static int geom_ensure_device(ct_geom* g) {
+    std::lock_guard<std::mutex> lock(g->mu);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(CT_EDEVICE, "no HIP device");
+    if (g->dmem) {
+        if (dev != g->device) return fail(CT_EINVAL, "geometry lives on device %d, current is %d", g->device, dev);
+        return CT_OK;
+    }
+    const size_t bytes = geom_table_bytes(g);
+    std::vector<char> img(bytes);
+    geom_table_pack(g, img.data());
+    void* mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess)
+        return fail(CT_ENOMEM, "hipMalloc(%zu) for geometry tables failed", bytes);
+    const hipError_t e = hipMemcpy(mem, img.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return fail(CT_EDEVICE, "geometry upload: %s", hipGetErrorString(e));
+    }
+    geom_bind(g, mem, dev, true);
     return CT_OK;
 }
 
@@ -676,7 +707,7 @@ extern "C" int ct_geom_create(const ct_geom_desc* desc, ct_geom** out) {
 
 extern "C" void ct_geom_destroy(ct_geom* g) {
     if (!g) return;
-    if (g->dmem) (void)hipFree(g->dmem);
+    if (g->dmem && g->dmem_owned) (void)hipFree(g->dmem);
     delete g;
 }
 
@@ -700,6 +731,25 @@ static FwdArgs fwd_all(const ct_geom* g, int J) {
     a.n_ent = g->m;
     a.n_chunks = g->total_chunks;
     return a;
+}
+
+// The density count enqueued on `st` into the geometry's counter table
+// (device [m][n] unsigned 64-bit), without waiting: for callers that read it
+// back asynchronously (the serving loop).  The tables must be on the device.
+int geom_count_async(ct_geom* g, double tau, unsigned long long** counts, hipStream_t st) {
+    if (!g->dmem) return fail(CT_EINVAL, "geometry tables are not on a device");
+    HIPCHK(launch_fill_u64(g->d_nnz, (int64_t)g->m * g->n, st));
+    for (int J = 0; J < g->n; ++J) {
+        FwdArgs a = fwd_all(g, J);
+        a.mode = 2;
+        a.nnz = g->d_nnz;
+        a.n_cols = g->n;
+        a.col = J;
+        a.tau = tau;
+        HIPCHK(launch_fwd(g->G, a, st));
+    }
+    *counts = g->d_nnz;
+    return CT_OK;
 }
 
 extern "C" int ct_geom_block_nnz(ct_geom* g, double tau, int64_t* host_nnz, void* stream) {
@@ -1010,6 +1060,7 @@ struct ct_schedule {
     std::vector<Entry> uni;
     int device = -1;
     void* dmem = nullptr;               // device tables, uploaded on first use
+    bool dmem_owned = true;             // false: placed in caller memory (sched_table_bind)
     std::mutex mu;
     Entry* d_entries = nullptr;
     int32_t* d_gptr = nullptr;
@@ -1114,6 +1165,70 @@ static int sched_finish(ct_schedule* s) {
     return CT_OK;
 }
 
+// The device-table image of a schedule: entries, group offsets, beta, the
+// per-epoch unions, step and epoch records, 256-byte aligned segments.
+struct SchedLayout {
+    size_t ent, gptr, beta, uni, steps, epochs, total;
+};
+static SchedLayout sched_layout(const ct_schedule* sc, size_t n_steps, size_t n_epochs) {
+    SchedLayout L{};
+    L.ent = 0;
+    L.gptr = L.ent + align256(std::max<size_t>(1, sc->entries.size()) * sizeof(Entry));
+    L.beta = L.gptr + align256(std::max<size_t>(1, sc->gptr.size()) * sizeof(int32_t));
+    L.uni = L.beta + align256(std::max<size_t>(1, sc->beta.size()) * sizeof(double));
+    L.steps = L.uni + align256(std::max<size_t>(1, sc->uni.size()) * sizeof(Entry));
+    L.epochs = L.steps + align256(std::max<size_t>(1, n_steps) * sizeof(StepRec));
+    L.total = L.epochs + align256(std::max<size_t>(1, n_epochs) * sizeof(EpochRec));
+    return L;
+}
+
+size_t sched_table_bytes(const ct_schedule* sc) {
+    return sched_layout(sc, sc->cols.size(), sc->ecp.size() - 1).total;
+}
+
+int sched_table_pack(const ct_schedule* sc, void* dst) {
+    const std::vector<StepRec> steps = sched_step_recs(sc);
+    const std::vector<EpochRec> epochs = sched_epoch_recs(sc);
+    const SchedLayout L = sched_layout(sc, steps.size(), epochs.size());
+    char* base = (char*)dst;
+    std::memset(base, 0, L.total);
+    auto put = [&](size_t off, const void* src, size_t bytes) {
+        if (bytes) std::memcpy(base + off, src, bytes);
+    };
+    put(L.ent, sc->entries.data(), sc->entries.size() * sizeof(Entry));
+    put(L.gptr, sc->gptr.data(), sc->gptr.size() * sizeof(int32_t));
+    put(L.beta, sc->beta.data(), sc->beta.size() * sizeof(double));
+    put(L.uni, sc->uni.data(), sc->uni.size() * sizeof(Entry));
+    put(L.steps, steps.data(), steps.size() * sizeof(StepRec));
+    put(L.epochs, epochs.data(), epochs.size() * sizeof(EpochRec));
+    return CT_OK;
+}
+
+static void sched_bind(ct_schedule* sc, void* mem, int dev, bool owned) {
+    const SchedLayout L = sched_layout(sc, sc->cols.size(), sc->ecp.size() - 1);
+    char* base = (char*)mem;
+    sc->d_entries = (Entry*)(base + L.ent);
+    sc->d_gptr = (int32_t*)(base + L.gptr);
+    sc->d_beta = (double*)(base + L.beta);
+    sc->d_uni = (Entry*)(base + L.uni);
+    sc->d_steps = (StepRec*)(base + L.steps);
+    sc->d_epochs = (EpochRec*)(base + L.epochs);
+    sc->device = dev;
+    sc->dmem = mem;
+    sc->dmem_owned = owned;
+}
+
+// The tables in caller device memory `mem` holding (or receiving, in stream
+// order before any use) the packed image.
+int sched_table_bind(ct_schedule* sc, void* mem) {
+    std::lock_guard<std::mutex> lock(sc->mu);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(CT_EDEVICE, "no HIP device");
+    if (sc->dmem) return fail(CT_EINVAL, "schedule tables are already on a device");
+    sched_bind(sc, mem, dev, false);
+    return CT_OK;
+}
+
 static int sched_ensure_device(ct_schedule* sc) {
     std::lock_guard<std::mutex> lock(sc->mu);
     int dev = -1;
@@ -1122,55 +1237,23 @@ static int sched_ensure_device(ct_schedule* sc) {
         if (dev != sc->device) return fail(CT_EINVAL, "schedule lives on device %d, current is %d", sc->device, dev);
         return CT_OK;
     }
-    const size_t b_ent = align256(std::max<size_t>(1, sc->entries.size()) * sizeof(Entry));
-    const size_t b_gptr = align256(std::max<size_t>(1, sc->gptr.size()) * sizeof(int32_t));
-    const size_t b_beta = align256(std::max<size_t>(1, sc->beta.size()) * sizeof(double));
-    const size_t b_uni = align256(std::max<size_t>(1, sc->uni.size()) * sizeof(Entry));
-    const std::vector<StepRec> steps = sched_step_recs(sc);
-    const std::vector<EpochRec> epochs = sched_epoch_recs(sc);
-    const size_t b_steps = align256(std::max<size_t>(1, steps.size()) * sizeof(StepRec));
-    const size_t b_epochs = align256(std::max<size_t>(1, epochs.size()) * sizeof(EpochRec));
+    const size_t bytes = sched_table_bytes(sc);
+    std::vector<char> img(bytes);
+    sched_table_pack(sc, img.data());
     void* mem = nullptr;
-    if (hipMalloc(&mem, b_ent + b_gptr + b_beta + b_uni + b_steps + b_epochs) != hipSuccess)
-        return fail(CT_ENOMEM, "hipMalloc for schedule tables failed");
-    char* base = (char*)mem;
-    Entry* d_entries = (Entry*)base;
-    int32_t* d_gptr = (int32_t*)(base + b_ent);
-    double* d_beta = (double*)(base + b_ent + b_gptr);
-    Entry* d_uni = (Entry*)(base + b_ent + b_gptr + b_beta);
-    StepRec* d_steps = (StepRec*)(base + b_ent + b_gptr + b_beta + b_uni);
-    EpochRec* d_epochs = (EpochRec*)(base + b_ent + b_gptr + b_beta + b_uni + b_steps);
-    hipError_t e = hipSuccess;
-    if (!sc->entries.empty())
-        e = hipMemcpy(d_entries, sc->entries.data(), sc->entries.size() * sizeof(Entry), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !sc->gptr.empty())
-        e = hipMemcpy(d_gptr, sc->gptr.data(), sc->gptr.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !sc->beta.empty())
-        e = hipMemcpy(d_beta, sc->beta.data(), sc->beta.size() * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !sc->uni.empty())
-        e = hipMemcpy(d_uni, sc->uni.data(), sc->uni.size() * sizeof(Entry), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !steps.empty())
-        e = hipMemcpy(d_steps, steps.data(), steps.size() * sizeof(StepRec), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !epochs.empty())
-        e = hipMemcpy(d_epochs, epochs.data(), epochs.size() * sizeof(EpochRec), hipMemcpyHostToDevice);
+    if (hipMalloc(&mem, bytes) != hipSuccess) return fail(CT_ENOMEM, "hipMalloc for schedule tables failed");
+    const hipError_t e = hipMemcpy(mem, img.data(), bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(mem);
         return fail(CT_EDEVICE, "schedule upload: %s", hipGetErrorString(e));
     }
-    sc->d_entries = d_entries;
-    sc->d_gptr = d_gptr;
-    sc->d_beta = d_beta;
-    sc->d_uni = d_uni;
-    sc->d_steps = d_steps;
-    sc->d_epochs = d_epochs;
-    sc->device = dev;
-    sc->dmem = mem;
+    sched_bind(sc, mem, dev, true);
     return CT_OK;
 }
 
 extern "C" void ct_schedule_destroy(ct_schedule* s) {
     if (!s) return;
-    if (s->dmem) (void)hipFree(s->dmem);
+    if (s->dmem && s->dmem_owned) (void)hipFree(s->dmem);
     delete s;
 }
 

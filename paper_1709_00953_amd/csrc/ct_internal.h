@@ -348,3 +348,19 @@ hipError_t launch_resnorm(const float* y, const float* p, int64_t n, double* par
                           hipStream_t st);
 
 }  // namespace ct
+
+// Device-table images of geometries and schedules, for callers that place
+// them in device memory of their own (the serving loop's arena): the image's
+// size, the image packed into host memory, and the object bound to a copy of
+// it in device memory (not freed by the object's destroy).
+struct ct_geom;
+struct ct_schedule;
+size_t geom_table_bytes(const ct_geom* g);
+int geom_table_pack(const ct_geom* g, void* dst);
+int geom_table_bind(ct_geom* g, void* mem);
+size_t sched_table_bytes(const ct_schedule* sc);
+int sched_table_pack(const ct_schedule* sc, void* dst);
+int sched_table_bind(ct_schedule* sc, void* mem);
+// The density count of a geometry whose tables are on the device, enqueued
+// on st without waiting; *counts: its device [m][n] table.
+int geom_count_async(ct_geom* g, double tau, unsigned long long** counts, hipStream_t st);

@@ -1369,7 +1369,7 @@ __global__ __launch_bounds__(256, 6) void k_back3(DGeom G, BA a) {
 // to a voxel face (the small direction components that the float32 bounds of
 // the general kernel lose).  A zero direction component (the kernels' rule)
 // keeps the ray in the source's slab of that axis.
-constexpr int kColWG = 6;         // resident work-groups per CU the register budget is set for
+constexpr int kColWG = 5;         // resident work-groups per CU the register budget is set for (96 VGPRs)
 constexpr int kColR = 512;        // rays of a view's window staged at once (fast path: the whole window)
 constexpr int kColV = 128;        // rows of a view's window staged at once
 constexpr int kColU = 2;          // X intervals kept per (view, column); wider columns form the rest
@@ -1481,68 +1481,70 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
     };
 
     float acc0 = 0.f, acc1 = 0.f;
-    // a voxel's rows of view W: the projections of its box's corners (zlo: its
-    // lower face), clipped to [va, vb]
-    auto rows_of = [&](const WinView& W, const ColView& C, double zlo, int va, int vb, int& k0, int& k1) {
-        if (!(C.ia0 < INFINITY)) {                 // footprint at the source's depth: every row
-            k0 = va;
-            k1 = vb;
-            return;
-        }
-        const float f0 = (float)((double)W.ssv * (zlo - W.zS)), f1 = f0 + (float)((double)W.ssv * G.vz);
-        const float p0 = f0 * C.ia0, p1 = f0 * C.ia1, q0 = f1 * C.ia0, q1 = f1 * C.ia1;
-        const float lo = fmaf(fminf(fminf(p0, p1), fminf(q0, q1)), ipv, fc0v);
-        const float hi = fmaf(fmaxf(fmaxf(p0, p1), fmaxf(q0, q1)), ipv, fc0v);
-        k0 = max(va, (int)ceilf(lo - 1e-3f - 1e-6f * fabsf(lo)));
-        k1 = min(vb, (int)floorf(hi + 1e-3f + 1e-6f * fabsf(hi)));
-    };
-    // one voxel's part from rows [k0, k1] of a staged part (buffer b, rows
-    // from va, bins [ua, ub) of pw a row) of view W
-    auto gather = [&](const WinView& W, const ColView& C, int b, int pw, int ua, int ub, int va, double zlo,
-                      int k0, int k1, float& acc) {
-        const double A = C.A, zfl = zlo - W.zS, zfh = zfl + G.vz;
-        const int uL = max(C.u0, ua), uH = min(C.u1, ub - 1);
-        const float2 X0 = C.X[0], X1 = C.X[1];
-        const bool s0 = C.u0 >= uL && C.u0 <= uH, s1 = C.u0 + 1 >= uL && C.u0 + 1 <= uH;
-        const int r0 = C.u0 - ua;
-        for (int k = k0; k <= k1; ++k) {
-            const double isv = sI[b][k - va];
-            float zl, zh;
-            if (W.careful && isv == 0.0) {
-                // a horizontal ray stays at the source's height
-                const bool in = __builtin_amdgcn_readfirstlane(src_slab(W.zS, G.oz, G.ivz)) ==
-                                (int)floor((zlo - G.oz) * G.ivz + 0.5);
-                zl = in ? -INFINITY : INFINITY;
-                zh = in ? INFINITY : -INFINITY;
-            } else {
-                const float p = (float)fma(zfl, isv, -A), q = (float)fma(zfh, isv, -A);
-                zl = fminf(p, q);
-                zh = fmaxf(p, q);
-            }
-            const int ro = (k - va) * pw;
-            if (s0) acc = fmaf(fmaxf(fminf(X0.y, zh) - fmaxf(X0.x, zl), 0.f), sR[b][ro + r0], acc);
-            if (s1) acc = fmaf(fmaxf(fminf(X1.y, zh) - fmaxf(X1.x, zl), 0.f), sR[b][ro + r0 + 1], acc);
-            for (int u = max(uL, C.u0 + kColU); u <= uH; ++u) {
-                // a column more than kColU bins wide: X formed here
-                const double* V = view_of(G, W.view);
-                const double qx = G.ox + ((double)ix + 0.5) * G.vx - V[0];
-                const double qy = G.oy + ((double)iy + 0.5) * G.vy - V[1];
-                const float2 xi = col_interval(G, V, ldu(G.cdxy + (size_t)W.view * G.nu, (unsigned)u), A,
-                                               fma(qx, V[6], qy * V[7]), u, ix, iy, src_slab(V[0], G.ox, G.ivx),
-                                               src_slab(V[1], G.oy, G.ivy));
-                acc = fmaf(fmaxf(fminf(xi.y, zh) - fmaxf(xi.x, zl), 0.f), sR[b][ro + u - ua], acc);
-            }
-        }
-    };
+    // this lane's two voxels from a staged part of view W (buffer b, rows
+    // [va, vb), bins [ua, ub) of pw a row)
     auto both = [&](const WinView& W, const ColView& C, int b, int pw, int ua, int ub, int va, int vb) {
-        int k0, k1;
-        if (valid0) {
-            rows_of(W, C, zlo0, va, vb - 1, k0, k1);
-            gather(W, C, b, pw, ua, ub, va, zlo0, k0, k1, acc0);
-        }
-        if (valid1) {
-            rows_of(W, C, zlo1, va, vb - 1, k0, k1);
-            gather(W, C, b, pw, ua, ub, va, zlo1, k0, k1, acc1);
+        // shared by the lane's voxels: the column's bins in the part and their X
+        const double A = C.A;
+        const int cu0 = C.u0, uL = max(cu0, ua), uH = min(C.u1, ub - 1);
+        const float2 X0 = C.X[0], X1 = C.X[1];
+        const bool s0 = cu0 >= uL && cu0 <= uH, s1 = cu0 + 1 >= uL && cu0 + 1 <= uH;
+        const bool wide = uH >= cu0 + kColU;
+        const float ia0 = C.ia0, ia1 = C.ia1;
+        const bool every_row = !(ia0 < INFINITY);   // footprint at the source's depth
+        // rows of a voxel: v = sdd e_v,z (z - z_S) / A over its box's corners;
+        // f = sdd e_v,z (z - z_S) at its faces is affine in its level
+        const float svz = W.ssv * (float)G.vz;
+        const float f00 = (float)((double)W.ssv * (G.oz + (double)zs * G.vz - W.zS));
+        const float mrg = 1e-3f + 1e-6f * (float)G.nv;
+        const bool careful = W.careful != 0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const bool valid = q == 0 ? valid0 : valid1;
+            if (!valid) continue;
+            const int lev = lz + q * TL;
+            int k0 = va, k1 = vb - 1;
+            if (!every_row) {
+                const float f0 = fmaf((float)lev, svz, f00), f1 = f0 + svz;
+                const float lo = fminf(fminf(f0 * ia0, f0 * ia1), fminf(f1 * ia0, f1 * ia1));
+                const float hi = fmaxf(fmaxf(f0 * ia0, f0 * ia1), fmaxf(f1 * ia0, f1 * ia1));
+                k0 = max(k0, (int)ceilf(fmaf(lo, ipv, fc0v) - mrg));
+                k1 = min(k1, (int)floorf(fmaf(hi, ipv, fc0v) + mrg));
+            }
+            const double zl0 = (q == 0 ? zlo0 : zlo1);
+            const double zfl = zl0 - W.zS, zfh = zfl + G.vz;
+            float acc = q == 0 ? acc0 : acc1;
+            int ro = (k0 - va) * pw + (cu0 - ua);
+            for (int k = k0; k <= k1; ++k, ro += pw) {
+                const double isv = sI[b][k - va];
+                float zl, zh;
+                if (careful && isv == 0.0) {
+                    // a horizontal ray stays at the source's height
+                    const bool in = src_slab(W.zS, G.oz, G.ivz) == zs + lev;
+                    zl = in ? -INFINITY : INFINITY;
+                    zh = in ? INFINITY : -INFINITY;
+                } else {
+                    const float p = (float)fma(zfl, isv, -A), r = (float)fma(zfh, isv, -A);
+                    zl = fminf(p, r);
+                    zh = fmaxf(p, r);
+                }
+                if (s0) acc = fmaf(fmaxf(fminf(X0.y, zh) - fmaxf(X0.x, zl), 0.f), sR[b][ro], acc);
+                if (s1) acc = fmaf(fmaxf(fminf(X1.y, zh) - fmaxf(X1.x, zl), 0.f), sR[b][ro + 1], acc);
+                if (wide) {
+                    // a column more than kColU bins wide: X of the rest formed here
+                    const double* V = view_of(G, W.view);
+                    const double qx = G.ox + ((double)ix + 0.5) * G.vx - V[0];
+                    const double qy = G.oy + ((double)iy + 0.5) * G.vy - V[1];
+                    for (int u = max(uL, cu0 + kColU); u <= uH; ++u) {
+                        const float2 xi = col_interval(G, V, ldu(G.cdxy + (size_t)W.view * G.nu, (unsigned)u), A,
+                                                       fma(qx, V[6], qy * V[7]), u, ix, iy,
+                                                       src_slab(V[0], G.ox, G.ivx), src_slab(V[1], G.oy, G.ivy));
+                        acc = fmaf(fmaxf(fminf(xi.y, zh) - fmaxf(xi.x, zl), 0.f), sR[b][ro + (u - cu0)], acc);
+                    }
+                }
+            }
+            if (q == 0) acc0 = acc;
+            else acc1 = acc;
         }
     };
 
