@@ -31,9 +31,10 @@ enum { kPar2D = 0, kFanFlat = 1, kFanCurved = 2, kCone = 3 };
 constexpr int kConeV = 4;
 
 // Voxel-column tile of that kernel: CX x CY columns of TZ voxels in z, 256
-// lanes, each lane two voxels of a column (z and z + TZ / 2; one when TZ =
-// 1).  TZ is the largest power of two up to 32 whose tiles waste at most 1/8
+// lanes, each lane VZ voxels of a column (levels l, l + TZ / VZ): two, or
+// one when TZ = 1.  TZ is the largest power of two up to 32 whose tiles waste at most 1/8
 // of the voxels over the box's nz (at least 1).
+constexpr int kColVoxels = 2;       // voxels a lane at most
 __host__ __device__ inline int col_vz(int tz) { return tz >= 2 ? 2 : 1; }
 __host__ __device__ inline void col_tile_shape(int nz, int& tz, int& cx, int& cy) {
     int t = 32;

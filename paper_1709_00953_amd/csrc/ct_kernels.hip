@@ -1359,36 +1359,54 @@ __global__ __launch_bounds__(256, 6) void k_back3(DGeom G, BA a) {
 // with X the column's xy interval of ray u and Z the voxel's z interval of row
 // v: X is formed once per (column, u) and Z once per (voxel, v) instead of
 // three slab intervals per pair.  A work-group owns NC voxel columns x TZ
-// voxels in z (one voxel per lane, z fastest; col_tile_shape).  Per view it
-// stages in LDS, for the part of its detector window in hand, X of every
-// (column, u), the product |D~| r of every ray and sdd / (e_v,z v) of every row
-// (float64: the z bounds are differences of terms of the size of A); each
-// voxel then walks the rows of its shadow (from the corners of its box) and,
-// per row, the bins of its column's shadow.  Both bounds are formed in float64
-// up to a difference, so they keep their precision for rays nearly parallel
-// to a voxel face (the small direction components that the float32 bounds of
-// the general kernel lose).  A zero direction component (the kernels' rule)
+// voxels in z (z fastest, col_vz voxels a lane; col_tile_shape) and walks the
+// group's views in rounds of 256 / NC.  At the start of a round one lane per
+// (view, column) forms the tile's detector window, the column's bins in it,
+// X of its first two and the constants of its voxels' row ranges.  Per view
+// the work-group stages in LDS the product |D~| r of every ray of the window
+// and sdd / (e_v,z v) of every row (float64: the z bounds are differences of
+// terms of the size of A); each voxel then takes the rows of its shadow and,
+// per row, the bins of its column.  Both bounds are formed in float64 up to a
+// difference, so they keep their precision for rays nearly parallel to a
+// voxel face (the small direction components that the float32 bounds of the
+// general kernel lose).  A zero direction component (the kernels' rule)
 // keeps the ray in the source's slab of that axis.
 constexpr int kColWG = 5;         // resident work-groups per CU the register budget is set for (96 VGPRs)
 constexpr int kColR = 512;        // rays of a view's window staged at once (fast path: the whole window)
 constexpr int kColV = 128;        // rows of a view's window staged at once
 constexpr int kColU = 2;          // X intervals kept per (view, column); wider columns form the rest
+constexpr int kColVZ = kColVoxels;  // voxels a lane at most (col_tile_shape)
 
-// Per (view, column) of a round: A of the column's centre, 1 / A at the near
-// and far edge of its footprint, its bins [u0, u1] and X of the first kColU.
+// Per (view, column) of a round.
 struct ColView {
-    double A;
-    float ia0, ia1;
-    int32_t u0, u1;
-    float2 X[kColU];
+    double A;                     // view-frame depth of the column's centre
+    float sl0, sl1;               // 1 / (A -+ half the footprint's depth extent), over the row pitch
+    float cl, ch;                 // centre row -+ margin (-+1e30 where the footprint reaches the source's depth)
+    int32_t u0, u1;               // its bins within the tile's window
+    int32_t co;                   // u0 - the window's first bin, clamped to [-2, window width - 1]
+    int32_t pad;
+    float2 X[kColU];              // X of bins u0 and u0 + 1 (empty where absent)
 };
 // Per view of a round: the tile's detector window [u0, u1) x [v0, v1), whether
-// it is staged whole (fast) and whether the view has a zero component.
+// it is staged whole (flag 1) and whether the view has a zero component (2).
+// A voxel at level l has f = sdd e_v,z (z - z_S) in [fl, fl + |svz|] with
+// fl = f00 + l svz.
 struct WinView {
     double zS;                    // source height
-    float ssv;                    // sdd e_v,z
-    int32_t view, u0, u1, v0, v1, fast, careful;
+    float svz, f00;
+    int32_t view, u0, u1, v0, v1, flags;
 };
+
+__device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float rflf(float v) { return __int_as_float(rfl(__float_as_int(v))); }
+
+// The fields of a WinView that the staging needs, in scalar registers.
+struct WinS {
+    int view, u0, u1, v0, v1, flags;
+};
+__device__ __forceinline__ WinS win_s(const WinView& w) {
+    return WinS{rfl(w.view), rfl(w.u0), rfl(w.u1), rfl(w.v0), rfl(w.v1), rfl(w.flags)};
+}
 
 // X of the ray of bin iu in the voxel column (jx, jy) whose centre has
 // view-frame coordinates (A, B): the overlap of its x and y slab intervals,
@@ -1421,32 +1439,48 @@ __device__ __forceinline__ int src_slab(double s, double o, double ih) {
     return (int)fmin(fmax(floor((s - o) * ih), -1e9), 1e9);
 }
 
+// The overlap of X and Z, at least 0.
+__device__ __forceinline__ float col_clip(float2 X, float zl, float zh) {
+    return fmaxf(fminf(X.y, zh) - fmaxf(X.x, zl), 0.f);
+}
+
 template <class BA>
 __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const int gi, const int bt,
                                             const int n_tiles) {
     __shared__ ColView cv[256];                  // [view slot][column]
     __shared__ WinView wv[16];                   // [view slot] (at least 16 columns: at most 16 views a round)
-    __shared__ float sR[2][kColR];               // |D~| r of a window's rays; two views in flight
+    // |D~| r of a window's rays, two views in flight; two zero floats before
+    // and after each buffer, so that the two bins a voxel reads per row stay
+    // inside it (the row loops below)
+    __shared__ float sRb[2][kColR + 4];
     __shared__ double sI[2][kColV];              // sdd / D_z of its rows
     __shared__ double sh[4];
     const int t = threadIdx.x;
     int TZ, CX, CY;
     col_tile_shape(a.box.z1 - a.box.z0, TZ, CX, CY);
-    const int VZ = col_vz(TZ), TL = TZ / VZ;     // voxels a lane, lanes a column
-    const int NC = CX * CY, NVR = 256 / NC;      // columns; views per round
+    TZ = rfl(TZ);
+    CX = rfl(CX);
+    CY = rfl(CY);
+    const int VZ = rfl(col_vz(TZ)), TL = rfl(TZ / VZ);     // voxels a lane, lanes a column
+    const int NC = CX * CY, NVR = 256 / NC;                // columns; views per round
+    // all four are powers of two: lane indices split with shifts and masks
+    const int lgTL = __builtin_ctz(TL), lgNC = __builtin_ctz(NC), lgCX = __builtin_ctz(CX);
     const int tiles_x = a.tiles_x, tiles_y = a.tiles_y;
     const int tx = bt % tiles_x, ty = (bt / tiles_x) % tiles_y, tz = bt / (tiles_x * tiles_y);
     const int xs = a.box.x0 + tx * CX, ys = a.box.y0 + ty * CY, zs = a.box.z0 + tz * TZ;
     const int nvx = min(CX, a.box.x1 - xs), nvy = min(CY, a.box.y1 - ys), nvz = min(TZ, a.box.z1 - zs);
-    // this lane's voxels: column c (cx, cy), levels lz and lz + TL
-    const int lz = t % TL, c = t / TL;
-    const int ccx = c % CX, ccy = c / CX;
+    // this lane's voxels: column c (cx, cy), levels lz, lz + TL, ...
+    const int lz = t & (TL - 1), c = t >> lgTL;
+    const int ccx = c & (CX - 1), ccy = c >> lgCX;
     const int ix = xs + ccx, iy = ys + ccy;
     const bool colv = ccx < nvx && ccy < nvy;
-    const bool valid0 = colv && lz < nvz, valid1 = colv && VZ == 2 && lz + TL < nvz;
+    bool valid[kColVZ];
+#pragma unroll
+    for (int q = 0; q < kColVZ; ++q) valid[q] = colv && q < VZ && lz + q * TL < nvz;
     const double c0v = 0.5 * (double)(G.nv - 1);
     const float fc0v = (float)c0v, ipv = (float)(1.0 / G.pv);
-    const double zlo0 = G.oz + (double)(zs + lz) * G.vz, zlo1 = zlo0 + (double)TL * G.vz;
+    // every value of sRb is zero or a product written by stage(): finite
+    for (int i = t; i < 2 * (kColR + 4); i += 256) (&sRb[0][0])[i] = 0.f;
 
     int e0 = 0, e1 = a.n_ent;
     if (a.gptr) {
@@ -1474,85 +1508,135 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
             const float2 q = ldu(dxy, (unsigned)iu);
             const float z = ldu(dz, (unsigned)iv);
             const float nrm = __builtin_amdgcn_sqrtf(fmaf(q.x, q.x, fmaf(q.y, q.y, z * z)));
-            sR[b][i] = nrm * ldu(rview, (unsigned)(iv * G.nu + iu));
+            sRb[b][2 + i] = nrm * ldu(rview, (unsigned)(iv * G.nu + iu));
         }
         const double* isv = G.cisv + (size_t)view * G.nv;
         for (int i = t; i < nrow; i += 256) sI[b][i] = ldu(isv, (unsigned)(va + i));
     };
 
-    float acc0 = 0.f, acc1 = 0.f;
-    // this lane's two voxels from a staged part of view W (buffer b, rows
-    // [va, vb), bins [ua, ub) of pw a row)
-    auto both = [&](const WinView& W, const ColView& C, int b, int pw, int ua, int ub, int va, int vb) {
-        // shared by the lane's voxels: the column's bins in the part and their X
-        const double A = C.A;
-        const int cu0 = C.u0, uL = max(cu0, ua), uH = min(C.u1, ub - 1);
-        const float2 X0 = C.X[0], X1 = C.X[1];
-        const bool s0 = cu0 >= uL && cu0 <= uH, s1 = cu0 + 1 >= uL && cu0 + 1 <= uH;
-        const bool wide = uH >= cu0 + kColU;
-        const float ia0 = C.ia0, ia1 = C.ia1;
-        const bool every_row = !(ia0 < INFINITY);   // footprint at the source's depth
-        // rows of a voxel: v = sdd e_v,z (z - z_S) / A over its box's corners;
-        // f = sdd e_v,z (z - z_S) at its faces is affine in its level
-        const float svz = W.ssv * (float)G.vz;
-        const float f00 = (float)((double)W.ssv * (G.oz + (double)zs * G.vz - W.zS));
-        const float mrg = 1e-3f + 1e-6f * (float)G.nv;
-        const bool careful = W.careful != 0;
+    float accv[kColVZ];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const bool valid = q == 0 ? valid0 : valid1;
-            if (!valid) continue;
+    for (int q = 0; q < kColVZ; ++q) accv[q] = 0.f;
+    // this lane's voxels from a staged part of view j (buffer b, rows
+    // [va, vb), bins [ua, ub) of pw a row).  FAST: the part is the whole
+    // window, whose bins ColView already holds; CAREFUL: the view has a ray
+    // with a zero direction component.
+    auto both = [&](auto fast_c, auto careful_c, int j, const WinS& Ws, const ColView& C, int b, int pw, int ua,
+                    int ub, int va, int vb) {
+        constexpr bool FAST = decltype(fast_c)::value, CAREFUL = decltype(careful_c)::value;
+        const float* R = &sRb[b][2];
+        const double* SI = sI[b];
+        const double zS = __hiloint2double(rfl(__double2hiint(wv[j].zS)), rfl(__double2loint(wv[j].zS)));
+        const float svz = rflf(wv[j].svz), f00 = rflf(wv[j].f00), asvz = fabsf(svz);
+        const double A = C.A;
+        const int cu0 = C.u0, cu1 = C.u1;
+        float2 X0 = C.X[0], X1 = C.X[1];
+        int co = C.co;
+        int xu0 = cu0 + kColU, uH = cu1;
+        if constexpr (!FAST) {
+            // the part's bins: an absent bin gets an empty interval (clip 0;
+            // the value it reads is not used)
+            const int uL = max(cu0, ua);
+            uH = min(cu1, ub - 1);
+            if (!(cu0 >= uL && cu0 <= uH)) X0 = make_float2(INFINITY, -INFINITY);
+            if (!(cu0 + 1 >= uL && cu0 + 1 <= uH)) X1 = make_float2(INFINITY, -INFINITY);
+            // where the offset of bin cu0 lies outside [-2, pw - 1] neither
+            // bin is in the part, and the clamped offset keeps the reads in
+            // the buffer and its zero pads
+            co = min(max(cu0 - ua, -2), pw - 1);
+            xu0 = max(uL, cu0 + kColU);
+        }
+        const bool wide = xu0 <= uH;
+        const float sl0 = C.sl0, sl1 = C.sl1, cl = C.cl, ch = C.ch;
+        const float fva = (float)va, fvb = (float)(vb - 1);
+        const int nrow = vb - va;
+#pragma unroll
+        for (int q = 0; q < kColVZ; ++q) {
+            if (!valid[q]) continue;
             const int lev = lz + q * TL;
-            int k0 = va, k1 = vb - 1;
-            if (!every_row) {
-                const float f0 = fmaf((float)lev, svz, f00), f1 = f0 + svz;
-                const float lo = fminf(fminf(f0 * ia0, f0 * ia1), fminf(f1 * ia0, f1 * ia1));
-                const float hi = fmaxf(fmaxf(f0 * ia0, f0 * ia1), fmaxf(f1 * ia0, f1 * ia1));
-                k0 = max(k0, (int)ceilf(fmaf(lo, ipv, fc0v) - mrg));
-                k1 = min(k1, (int)floorf(fmaf(hi, ipv, fc0v) + mrg));
-            }
-            const double zl0 = (q == 0 ? zlo0 : zlo1);
-            const double zfl = zl0 - W.zS, zfh = zfl + G.vz;
-            float acc = q == 0 ? acc0 : acc1;
-            int ro = (k0 - va) * pw + (cu0 - ua);
-            for (int k = k0; k <= k1; ++k, ro += pw) {
-                const double isv = sI[b][k - va];
-                float zl, zh;
-                if (careful && isv == 0.0) {
+            // rows of the voxel: v = f / A' over the depths A' of its column's
+            // footprint, f over its two faces
+            const float fl = fmaf((float)lev, svz, f00), fh = fl + asvz;
+            const float lo = fmaf(fl, fl >= 0.f ? sl1 : sl0, cl);
+            const float hi = fmaf(fh, fh >= 0.f ? sl0 : sl1, ch);
+            const int k0 = (int)fmaxf(ceilf(lo), fva), k1 = (int)fminf(floorf(hi), fvb);
+            // the voxel's faces, formed per view rather than held
+            int giz = zs + lev;
+            asm volatile("" : "+v"(giz));
+            const double zfl = fma((double)giz, G.vz, G.oz) - zS, zfh = zfl + G.vz;
+            bool in_src = false;
+            if constexpr (CAREFUL) in_src = src_slab(zS, G.oz, G.ivz) == zs + lev;
+            auto zint = [&](double isv, float& zl, float& zh) {
+                if (CAREFUL && isv == 0.0) {
                     // a horizontal ray stays at the source's height
-                    const bool in = src_slab(W.zS, G.oz, G.ivz) == zs + lev;
-                    zl = in ? -INFINITY : INFINITY;
-                    zh = in ? INFINITY : -INFINITY;
+                    zl = in_src ? -INFINITY : INFINITY;
+                    zh = in_src ? INFINITY : -INFINITY;
                 } else {
                     const float p = (float)fma(zfl, isv, -A), r = (float)fma(zfh, isv, -A);
                     zl = fminf(p, r);
                     zh = fmaxf(p, r);
                 }
-                if (s0) acc = fmaf(fmaxf(fminf(X0.y, zh) - fmaxf(X0.x, zl), 0.f), sR[b][ro], acc);
-                if (s1) acc = fmaf(fmaxf(fminf(X1.y, zh) - fmaxf(X1.x, zl), 0.f), sR[b][ro + 1], acc);
-                if (wide) {
-                    // a column more than kColU bins wide: X of the rest formed here
-                    const double* V = view_of(G, W.view);
-                    const double qx = G.ox + ((double)ix + 0.5) * G.vx - V[0];
-                    const double qy = G.oy + ((double)iy + 0.5) * G.vy - V[1];
-                    for (int u = max(uL, cu0 + kColU); u <= uH; ++u) {
-                        const float2 xi = col_interval(G, V, ldu(G.cdxy + (size_t)W.view * G.nu, (unsigned)u), A,
-                                                       fma(qx, V[6], qy * V[7]), u, ix, iy,
-                                                       src_slab(V[0], G.ox, G.ivx), src_slab(V[1], G.oy, G.ivy));
-                        acc = fmaf(fmaxf(fminf(xi.y, zh) - fmaxf(xi.x, zl), 0.f), sR[b][ro + (u - cu0)], acc);
+            };
+            float acc = accv[q];
+            if (__all(k1 - k0 <= 1 && !wide)) {
+                // at most two rows in every lane (the usual case): both
+                // without a loop, a row beyond k1 with an empty interval
+                const int iA = min(k0 - va, nrow - 1), iB = min(iA + 1, nrow - 1);
+                float zlA, zhA, zlB, zhB;
+                zint(SI[iA], zlA, zhA);
+                zint(SI[iB], zlB, zhB);
+                zlA = k0 <= k1 ? zlA : INFINITY;
+                zlB = k0 < k1 ? zlB : INFINITY;
+                const int rA = iA * pw + co, rB = iB * pw + co;
+                acc = fmaf(col_clip(X0, zlA, zhA), R[rA], acc);
+                acc = fmaf(col_clip(X1, zlA, zhA), R[rA + 1], acc);
+                acc = fmaf(col_clip(X0, zlB, zhB), R[rB], acc);
+                acc = fmaf(col_clip(X1, zlB, zhB), R[rB + 1], acc);
+            } else {
+                int rb = (k0 - va) * pw;
+                for (int k = k0; k <= k1; ++k, rb += pw) {
+                    float zl, zh;
+                    zint(SI[k - va], zl, zh);
+                    acc = fmaf(col_clip(X0, zl, zh), R[rb + co], acc);
+                    acc = fmaf(col_clip(X1, zl, zh), R[rb + co + 1], acc);
+                    if (wide) {
+                        // a column more than kColU bins wide: X of the rest formed here
+                        const int view = rfl(wv[j].view);
+                        const double* V = view_of(G, view);
+                        int wix = ix, wiy = iy;
+                        asm volatile("" : "+v"(wix), "+v"(wiy));
+                        const double qx = G.ox + ((double)wix + 0.5) * G.vx - V[0];
+                        const double qy = G.oy + ((double)wiy + 0.5) * G.vy - V[1];
+                        for (int u = xu0; u <= uH; ++u) {
+                            const float2 xi = col_interval(G, V, ldu(G.cdxy + (size_t)view * G.nu, (unsigned)u), A,
+                                                           fma(qx, V[6], qy * V[7]), u, ix, iy,
+                                                           src_slab(V[0], G.ox, G.ivx), src_slab(V[1], G.oy, G.ivy));
+                            acc = fmaf(col_clip(xi, zl, zh), R[rb + (u - ua)], acc);
+                        }
                     }
                 }
             }
-            if (q == 0) acc0 = acc;
-            else acc1 = acc;
+            accv[q] = acc;
         }
+    };
+    auto both_u = [&](auto fast_c, int j, const WinS& W, int b, int pw, int ua, int ub, int va, int vb) {
+        const ColView& C = cv[j * NC + c];
+        if (W.flags & 2)
+            both(fast_c, std::true_type{}, j, W, C, b, pw, ua, ub, va, vb);
+        else
+            both(fast_c, std::false_type{}, j, W, C, b, pw, ua, ub, va, vb);
     };
 
     for (int base = 0; base < nt; base += NVR) {
         const int nvr = min(NVR, nt - base);
-        // phase A: lane (view slot j, column cc) of the round
+        // phase A: lane (view slot j, column cc) of the round.  The tile's
+        // corner and extent pass through an empty asm statement, so that the
+        // float64 terms formed from them stay in this loop instead of being
+        // held in registers across it (more than the budget holds)
         {
-            const int j = t / NC, cc = t % NC;
+            int pt = t, pxs = xs, pys = ys, pzs = zs, pnx = nvx, pny = nvy, pnz = nvz;
+            asm volatile("" : "+v"(pt), "+s"(pxs), "+s"(pys), "+s"(pzs), "+s"(pnx), "+s"(pny), "+s"(pnz));
+            const int j = pt >> lgNC, cc = pt & (NC - 1);
             if (j < nvr) {
                 int e = e0, off = base + j;
                 Tile tl{};
@@ -1569,61 +1653,18 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                 const double* V = view_of(G, tl.view);
                 const double sdd = V[15];
                 const double c0u = 0.5 * (double)(G.nu - 1);
-                const int jx = xs + (cc % CX), jy = ys + (cc / CX);
-                const double qx = G.ox + ((double)jx + 0.5) * G.vx - V[0];
-                const double qy = G.oy + ((double)jy + 0.5) * G.vy - V[1];
-                const double A = fma(qx, V[12], qy * V[13]);
-                const double B = fma(qx, V[6], qy * V[7]);
-                const double ea = 0.5 * G.vx * fabs(V[12]) + 0.5 * G.vy * fabs(V[13]);
-                ColView& C = cv[t];
-                C.A = A;
-                const bool ok = A - ea > 0.0;
-                C.ia0 = ok ? __builtin_amdgcn_rcpf((float)(A - ea)) : INFINITY;
-                C.ia1 = ok ? __builtin_amdgcn_rcpf((float)(A + ea)) : -INFINITY;
-                // bins whose ray can meet the column: the projections of its
-                // footprint's corners (it lies in front of the source)
-                int u0 = tl.u0, u1 = tl.u1 - 1;
-                if (ok) {
-                    const float hxf = (float)(0.5 * G.vx), hyf = (float)(0.5 * G.vy);
-                    const float Af = (float)A, Bf = (float)B;
-                    const float nx = (float)V[12], ny = (float)V[13], ex = (float)V[6], ey = (float)V[7];
-                    float umin = INFINITY, umax = -INFINITY;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const float px = (k & 1) ? hxf : -hxf, py = (k & 2) ? hyf : -hyf;
-                        const float uu = fmaf(py, ey, fmaf(px, ex, Bf)) *
-                                         __builtin_amdgcn_rcpf(fmaf(py, ny, fmaf(px, nx, Af)));
-                        umin = fminf(umin, uu);
-                        umax = fmaxf(umax, uu);
-                    }
-                    const float su = (float)(sdd / G.pu), fc = (float)c0u;
-                    const float bl = fmaf(umin, su, fc), bh = fmaf(umax, su, fc);
-                    u0 = max(u0, (int)ceilf(bl - 1e-3f - 1e-6f * fabsf(bl)));
-                    u1 = min(u1, (int)floorf(bh + 1e-3f + 1e-6f * fabsf(bh)));
-                }
-                C.u0 = u0;
-                C.u1 = u1;
-                const int skx = src_slab(V[0], G.ox, G.ivx), sky = src_slab(V[1], G.oy, G.ivy);
-#pragma unroll
-                for (int i = 0; i < kColU; ++i) {
-                    const int u = u0 + i;
-                    C.X[i] = u <= u1 ? col_interval(G, V, ldu(G.cdxy + (size_t)tl.view * G.nu, (unsigned)u), A, B,
-                                                    u, jx, jy, skx, sky)
-                                     : make_float2(0.f, 0.f);
-                }
-                if (cc == 0) {
-                    // the tile's window: the projections of its box's corners
-                    WinView& W = wv[j];
-                    W.view = tl.view;
-                    W.zS = V[2];
-                    W.ssv = (float)(sdd * V[11]);
-                    W.careful = G.view_flags[tl.view] & 1;
-                    const double x0 = G.ox + (double)xs * G.vx - V[0], y0 = G.oy + (double)ys * G.vy - V[1];
-                    const double z0 = G.oz + (double)zs * G.vz - V[2];
+                const float su = (float)(sdd / G.pu), fu = (float)c0u;
+                // the tile's window: the projections of its box's corners (every
+                // lane of the view slot forms it; its column lane 0 stores it)
+                const double ssv = sdd * V[11];
+                int wu0 = tl.u0, wu1 = tl.u1, wv0 = tl.v0, wv1 = tl.v1;
+                {
+                    const double x0 = G.ox + (double)pxs * G.vx - V[0], y0 = G.oy + (double)pys * G.vy - V[1];
+                    const double z0 = G.oz + (double)pzs * G.vz - V[2];
                     const float ex = (float)V[6], ey = (float)V[7], nx = (float)V[12], ny = (float)V[13];
-                    const float xa = (float)x0, xb = (float)(x0 + nvx * G.vx);
-                    const float ya = (float)y0, yb = (float)(y0 + nvy * G.vy);
-                    const float za = (float)z0, zb = (float)(z0 + nvz * G.vz), ssv = W.ssv;
+                    const float xa = (float)x0, xb = (float)(x0 + pnx * G.vx);
+                    const float ya = (float)y0, yb = (float)(y0 + pny * G.vy);
+                    const float za = (float)z0, zb = (float)(z0 + pnz * G.vz);
                     float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
                     bool front = true;
 #pragma unroll
@@ -1638,47 +1679,103 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                         vmin = fminf(vmin, fminf(za * iA, zb * iA));
                         vmax = fmaxf(vmax, fmaxf(za * iA, zb * iA));
                     }
-                    int wu0 = tl.u0, wu1 = tl.u1, wv0 = tl.v0, wv1 = tl.v1;
                     if (front) {
-                        const float su = (float)(sdd / G.pu), fu = (float)c0u;
                         const float bl = fmaf(umin, su, fu), bh = fmaf(umax, su, fu);
                         wu0 = max(wu0, (int)ceilf(bl - 1e-3f - 1e-6f * fabsf(bl)));
                         wu1 = min(wu1, (int)floorf(bh + 1e-3f + 1e-6f * fabsf(bh)) + 1);
                         // v = sdd e_v,z (z - z_S) / A: scale the extremes by ssv
-                        const float sv = ssv * ipv;
+                        const float sv = (float)ssv * ipv;
                         const float cl = fminf(vmin * sv, vmax * sv) + fc0v, ch = fmaxf(vmin * sv, vmax * sv) + fc0v;
                         wv0 = max(wv0, (int)ceilf(cl - 1e-3f - 1e-6f * fabsf(cl)));
                         wv1 = min(wv1, (int)floorf(ch + 1e-3f + 1e-6f * fabsf(ch)) + 1);
                     }
                     wu1 = max(wu0, wu1);
                     wv1 = max(wv0, wv1);
-                    W.u0 = wu0;
-                    W.u1 = wu1;
-                    W.v0 = wv0;
-                    W.v1 = wv1;
-                    W.fast = (wu1 - wu0) * (wv1 - wv0) <= kColR && wv1 - wv0 <= kColV;
+                    if (cc == 0) {
+                        WinView& W = wv[j];
+                        W.view = tl.view;
+                        W.zS = V[2];
+                        const double svz = ssv * G.vz;
+                        W.svz = (float)svz;
+                        // the lower f of the two faces of level 0
+                        W.f00 = (float)(ssv * (G.oz + (double)pzs * G.vz - V[2]) + fmin(svz, 0.0));
+                        W.u0 = wu0;
+                        W.u1 = wu1;
+                        W.v0 = wv0;
+                        W.v1 = wv1;
+                        const bool fast = (wu1 - wu0) * (wv1 - wv0) <= kColR && wv1 - wv0 <= kColV;
+                        W.flags = (fast ? 1 : 0) | ((G.view_flags[tl.view] & 1) ? 2 : 0);
+                    }
+                }
+                // the column
+                const int jx = pxs + (cc & (CX - 1)), jy = pys + (cc >> lgCX);
+                const double qx = G.ox + ((double)jx + 0.5) * G.vx - V[0];
+                const double qy = G.oy + ((double)jy + 0.5) * G.vy - V[1];
+                const double A = fma(qx, V[12], qy * V[13]);
+                const double B = fma(qx, V[6], qy * V[7]);
+                const double ea = 0.5 * G.vx * fabs(V[12]) + 0.5 * G.vy * fabs(V[13]);
+                ColView& C = cv[pt];
+                C.A = A;
+                const bool ok = A - ea > 0.0;
+                // row ranges: v = f / A' / pv + c0v over A' in [A - ea, A + ea];
+                // a footprint at the source's depth takes every row
+                const float mrg = 1e-3f + 1e-6f * (float)G.nv;
+                C.sl0 = ok ? __builtin_amdgcn_rcpf((float)(A - ea)) * ipv : 0.f;
+                C.sl1 = ok ? __builtin_amdgcn_rcpf((float)(A + ea)) * ipv : 0.f;
+                C.cl = ok ? fc0v - mrg : -1e30f;
+                C.ch = ok ? fc0v + mrg : 1e30f;
+                // bins in the window whose ray can meet the column: the
+                // projections of its footprint's corners (it lies in front of
+                // the source)
+                int u0 = wu0, u1 = wu1 - 1;
+                if (ok) {
+                    const float hxf = (float)(0.5 * G.vx), hyf = (float)(0.5 * G.vy);
+                    const float Af = (float)A, Bf = (float)B;
+                    const float nx = (float)V[12], ny = (float)V[13], ex = (float)V[6], ey = (float)V[7];
+                    float umin = INFINITY, umax = -INFINITY;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float px = (k & 1) ? hxf : -hxf, py = (k & 2) ? hyf : -hyf;
+                        const float uu = fmaf(py, ey, fmaf(px, ex, Bf)) *
+                                         __builtin_amdgcn_rcpf(fmaf(py, ny, fmaf(px, nx, Af)));
+                        umin = fminf(umin, uu);
+                        umax = fmaxf(umax, uu);
+                    }
+                    const float bl = fmaf(umin, su, fu), bh = fmaf(umax, su, fu);
+                    u0 = max(u0, (int)ceilf(bl - 1e-3f - 1e-6f * fabsf(bl)));
+                    u1 = min(u1, (int)floorf(bh + 1e-3f + 1e-6f * fabsf(bh)));
+                }
+                C.u0 = u0;
+                C.u1 = u1;
+                C.co = min(u0 - wu0, max(1, wu1 - wu0) - 1);    // u0 >= wu0
+                const int skx = src_slab(V[0], G.ox, G.ivx), sky = src_slab(V[1], G.oy, G.ivy);
+#pragma unroll
+                for (int i = 0; i < kColU; ++i) {
+                    const int u = u0 + i;
+                    C.X[i] = u <= u1 ? col_interval(G, V, ldu(G.cdxy + (size_t)tl.view * G.nu, (unsigned)u), A, B,
+                                                    u, jx, jy, skx, sky)
+                                     : make_float2(INFINITY, -INFINITY);
                 }
             }
         }
         __syncthreads();
         // the round's views, one barrier each: the next view's window is staged
         // while this one's is gathered
-        if (wv[0].fast)
-            stage(wv[0].view, 0, max(1, wv[0].u1 - wv[0].u0), wv[0].u0, wv[0].v0,
-                  (wv[0].u1 - wv[0].u0) * (wv[0].v1 - wv[0].v0), wv[0].v1 - wv[0].v0);
+        WinS W = win_s(wv[0]);
+        if (W.flags & 1)
+            stage(W.view, 0, max(1, W.u1 - W.u0), W.u0, W.v0, (W.u1 - W.u0) * (W.v1 - W.v0), W.v1 - W.v0);
         __syncthreads();
         for (int j = 0; j < nvr; ++j) {
-            const WinView& W = wv[j];
-            const ColView& C = cv[j * NC + c];
             const int b = j & 1;
-            const int fast = __builtin_amdgcn_readfirstlane(W.fast);
-            if (fast) {
-                if (j + 1 < nvr && wv[j + 1].fast) {
-                    const WinView& Wn = wv[j + 1];
+            const bool more = j + 1 < nvr;
+            const WinS Wn = win_s(wv[more ? j + 1 : j]);
+            const bool empty = W.u1 <= W.u0 || W.v1 <= W.v0;
+            if (W.flags & 1) {
+                if (more && (Wn.flags & 1))
                     stage(Wn.view, b ^ 1, max(1, Wn.u1 - Wn.u0), Wn.u0, Wn.v0, (Wn.u1 - Wn.u0) * (Wn.v1 - Wn.v0),
                           Wn.v1 - Wn.v0);
-                }
-                both(W, C, b, max(1, W.u1 - W.u0), W.u0, W.u1, W.v0, W.v1);
+                if (!empty)
+                    both_u(std::true_type{}, j, W, b, max(1, W.u1 - W.u0), W.u0, W.u1, W.v0, W.v1);
                 __syncthreads();
             } else {
                 // a window too large to stage whole: parts of at most kColR
@@ -1692,29 +1789,28 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                         __syncthreads();
                         stage(W.view, 0, qw, ua, va, qw * (vb - va), vb - va);
                         __syncthreads();
-                        both(W, C, 0, qw, ua, ub, va, vb);
+                        both_u(std::false_type{}, j, W, 0, qw, ua, ub, va, vb);
                     }
                 }
                 __syncthreads();
-                if (j + 1 < nvr && wv[j + 1].fast) {
-                    const WinView& Wn = wv[j + 1];
+                if (more && (Wn.flags & 1)) {
                     stage(Wn.view, b ^ 1, max(1, Wn.u1 - Wn.u0), Wn.u0, Wn.v0, (Wn.u1 - Wn.u0) * (Wn.v1 - Wn.v0),
                           Wn.v1 - Wn.v0);
                     __syncthreads();
                 }
             }
+            W = Wn;
         }
     }
 
     const int nxJ = a.box.x1 - a.box.x0, nyJ = a.box.y1 - a.box.y0, nzJ = a.box.z1 - a.box.z0;
     double p = 0.0;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const bool valid = q == 0 ? valid0 : valid1;
-        const float acc = q == 0 ? acc0 : acc1;
+    for (int q = 0; q < kColVZ; ++q) {
+        const float acc = accv[q];
         const int iz = zs + lz + q * TL;
         const size_t gix = ((size_t)iz * G.ny + iy) * G.nx + ix;
-        if (!valid) continue;
+        if (!valid[q]) continue;
         if (a.fused) {
             const int jx = ix - a.box.x0, jy = iy - a.box.y0, jz = iz - a.box.z0;
             const float2 v = make_float2(a.x[gix], acc);
