@@ -1388,7 +1388,9 @@ struct ColView {
     float2 X[kColU];              // X of bins u0 and u0 + 1 (empty where absent)
 };
 // Per view of a round: the tile's detector window [u0, u1) x [v0, v1), whether
-// it is staged whole (flag 1) and whether the view has a zero component (2).
+// it is staged whole (flag 1), whether the view has a zero component (2) and
+// whether every voxel of the tile has at most two rows and every column at
+// most two bins (4).
 // A voxel at level l has f = sdd e_v,z (z - z_S) in [fl, fl + |svz|] with
 // fl = f00 + l svz.
 struct WinView {
@@ -1578,7 +1580,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                 }
             };
             float acc = accv[q];
-            if (__all(k1 - k0 <= 1 && !wide)) {
+            if ((FAST && (Ws.flags & 4)) || __all(k1 - k0 <= 1 && !wide)) {
                 // at most two rows in every lane (the usual case): both
                 // without a loop, a row beyond k1 with an empty interval
                 const int iA = min(k0 - va, nrow - 1), iB = min(iA + 1, nrow - 1);
@@ -1587,13 +1589,13 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                 zint(SI[iB], zlB, zhB);
                 zlA = k0 <= k1 ? zlA : INFINITY;
                 zlB = k0 < k1 ? zlB : INFINITY;
-                const int rA = iA * pw + co, rB = iB * pw + co;
+                const int rA = __umul24(iA, pw) + co, rB = __umul24(iB, pw) + co;
                 acc = fmaf(col_clip(X0, zlA, zhA), R[rA], acc);
                 acc = fmaf(col_clip(X1, zlA, zhA), R[rA + 1], acc);
                 acc = fmaf(col_clip(X0, zlB, zhB), R[rB], acc);
                 acc = fmaf(col_clip(X1, zlB, zhB), R[rB + 1], acc);
             } else {
-                int rb = (k0 - va) * pw;
+                int rb = __umul24(k0 - va, pw);
                 for (int k = k0; k <= k1; ++k, rb += pw) {
                     float zl, zh;
                     zint(SI[k - va], zl, zh);
@@ -1748,6 +1750,31 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                 C.u0 = u0;
                 C.u1 = u1;
                 C.co = min(u0 - wu0, max(1, wu1 - wu0) - 1);    // u0 >= wu0
+                // at most two bins, and at most two rows at every level: the
+                // rows of a voxel span hi - lo = fh s - fl s' + (ch - cl),
+                // which is convex in the level, so its largest value is at the
+                // lowest or the highest level; below 1.9 (not 2: the voxels
+                // round their own bounds) it leaves room for two integers
+                bool simple = u1 <= u0 + 1 && ok;
+                {
+                    const float svz = (float)(ssv * G.vz), asvz = fabsf(svz);
+                    const float f00 = (float)(ssv * (G.oz + (double)pzs * G.vz - V[2]) + fmin(ssv * G.vz, 0.0));
+#pragma unroll
+                    for (int e2 = 0; e2 < 2; ++e2) {
+                        const float fl = fmaf((float)(e2 ? pnz - 1 : 0), svz, f00), fh = fl + asvz;
+                        const float lo = fl * (fl >= 0.f ? C.sl1 : C.sl0) + C.cl;
+                        const float hi = fh * (fh >= 0.f ? C.sl0 : C.sl1) + C.ch;
+                        simple = simple && hi - lo < 1.9f;
+                    }
+                }
+                // where the view slot's NC lanes lie in one wave (NC <= 64, a
+                // power of two); else each voxel decides with a vote
+                const unsigned long long bal = __ballot(!simple);
+                if (NC <= 64) {
+                    const unsigned long long slot = (NC == 64 ? ~0ull : ((1ull << NC) - 1ull))
+                                                    << ((pt & 63) & ~(NC - 1));
+                    if (cc == 0 && (bal & slot) == 0ull) wv[j].flags |= 4;
+                }
                 const int skx = src_slab(V[0], G.ox, G.ivx), sky = src_slab(V[1], G.oy, G.ivy);
 #pragma unroll
                 for (int i = 0; i < kColU; ++i) {
