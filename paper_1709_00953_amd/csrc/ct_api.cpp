@@ -500,9 +500,19 @@ struct DevLayout {
 // ray depend on its detector column only, the z component on its row only.
 // Same operations as the kernels' float64 ray vector D = v e_v + u e_u + sdd n
 // (with e_v,x = e_v,y = e_u,z = n_z = 0 the other terms are exact zeros).
+// The exponent e of the column kernel's interval scale 2^e: the largest
+// power of two with 2^e sqrt(vx^2 + vy^2) <= 1.
+static int col_scale_exp(const ct_geom_desc& d) {
+    const double diag = std::sqrt(d.vx * d.vx + d.vy * d.vy);
+    int e = (int)std::floor(std::log2(1.0 / diag));
+    while (std::ldexp(diag, e) > 1.0) --e;
+    return e;
+}
+
 static void build_columns(const ct_geom* g, std::vector<float2>& dxy, std::vector<float>& dz,
                           std::vector<double>& isv) {
     const ct_geom_desc& d = g->d;
+    const int ke = col_scale_exp(d);
     dxy.assign((size_t)d.n_views * d.nu, float2{});
     dz.assign((size_t)d.n_views * d.nv, 0.f);
     isv.assign((size_t)d.n_views * d.nv, 0.0);
@@ -520,7 +530,7 @@ static void build_columns(const ct_geom* g, std::vector<float2>& dxy, std::vecto
             const double Dz = v * W[11];
             const float f = (float)(Dz * is);
             dz[(size_t)k * d.nv + iv] = f;
-            isv[(size_t)k * d.nv + iv] = std::fabs(f) <= kAxisEpsF ? 0.0 : sdd / Dz;
+            isv[(size_t)k * d.nv + iv] = std::fabs(f) <= kAxisEpsF ? 0.0 : std::ldexp(sdd / Dz, ke);
         }
     }
 }
@@ -623,6 +633,7 @@ static void geom_bind(ct_geom* g, void* mem, int dev, bool owned) {
     G.ivx = 1.0 / d.vx;
     G.ivy = 1.0 / d.vy;
     G.ivz = 1.0 / d.vz;
+    G.colk_e = col_scale_exp(d);
     G.view64 = (const double*)(base + L.off_view);
     G.ray2f = g->dims == 2 ? (const Ray2F*)(base + L.off_rayf) : nullptr;
     G.ray2b = g->dims == 2 ? (const Ray2B*)(base + L.off_rayb) : nullptr;

@@ -157,6 +157,12 @@ struct DGeom {
     int32_t n_cols;
     int32_t mixed_boxes;          // column blocks differ in size (their (x, g) copies differ in layout)
     int32_t vertical;             // cone: every view's detector columns run along z (kConeV)
+    // vertical cones: the exponent e of 2^e, the largest power of two at most
+    // 1 / (the xy diagonal of a voxel).  A ray's parameter s (point =
+    // S + s D / sdd) spans at most that diagonal in a voxel column, as
+    // |D_xy| >= sdd, so every clip length times 2^e is at most 1; the scaling
+    // is exact.  The table cisv holds 2^e sdd / D_z.
+    int32_t colk_e;
 };
 
 struct Box {

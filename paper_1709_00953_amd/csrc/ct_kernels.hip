@@ -1411,17 +1411,19 @@ __device__ __forceinline__ WinS win_s(const WinView& w) {
 }
 
 // X of the ray of bin iu in the voxel column (jx, jy) whose centre has
-// view-frame coordinates (A, B): the overlap of its x and y slab intervals,
-// with the bounds' numerators in float64.  dxy: the ray's float32 D~_x, D~_y;
-// a zero component keeps the ray in the source's slab (skx, sky) of that axis.
+// view-frame coordinates (A, B): the overlap of its x and y slab intervals
+// (half widths hx, hy), with the bounds' numerators in float64.  dxy: the
+// ray's float32 D~_x, D~_y; a zero component keeps the ray in the source's
+// slab (skx, sky) of that axis.
 __device__ __forceinline__ float2 col_interval(const DGeom& G, const double* V, const float2 dxy, double A,
-                                               double B, int iu, int jx, int jy, int skx, int sky) {
+                                               double B, int iu, int jx, int jy, int skx, int sky, double hx,
+                                               double hy) {
     const double uu = ((double)iu - 0.5 * (double)(G.nu - 1)) * G.pu;
     const double du = fma(-A, uu * V[16], B);
     float lo = -INFINITY, hi = INFINITY;
     const float dk[2] = {dxy.x, dxy.y};
     const int ji[2] = {jx, jy}, sk[2] = {skx, sky};
-    const double hk[2] = {0.5 * G.vx, 0.5 * G.vy};
+    const double hk[2] = {hx, hy};
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         if (fabsf(dk[k]) <= kAxisEpsF) {
@@ -1441,9 +1443,11 @@ __device__ __forceinline__ int src_slab(double s, double o, double ih) {
     return (int)fmin(fmax(floor((s - o) * ih), -1e9), 1e9);
 }
 
-// The overlap of X and Z, at least 0.
+// The overlap of X and Z, at least 0: the intervals are scaled by 2^colk_e,
+// so the overlap is at most 1 and the clamp to [0, 1] (an output modifier of
+// the subtraction) is its lower bound alone.
 __device__ __forceinline__ float col_clip(float2 X, float zl, float zh) {
-    return fmaxf(fminf(X.y, zh) - fmaxf(X.x, zl), 0.f);
+    return __builtin_amdgcn_fmed3f(fminf(X.y, zh) - fmaxf(X.x, zl), 0.f, 1.f);
 }
 
 template <class BA>
@@ -1455,7 +1459,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
     // and after each buffer, so that the two bins a voxel reads per row stay
     // inside it (the row loops below)
     __shared__ float sRb[2][kColR + 4];
-    __shared__ double sI[2][kColV];              // sdd / D_z of its rows
+    __shared__ double sI[2][kColV + 1];          // 2^e sdd / D_z of its rows; one more read, not used
     __shared__ double sh[4];
     const int t = threadIdx.x;
     int TZ, CX, CY;
@@ -1479,10 +1483,9 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
     bool valid[kColVZ];
 #pragma unroll
     for (int q = 0; q < kColVZ; ++q) valid[q] = colv && q < VZ && lz + q * TL < nvz;
-    const double c0v = 0.5 * (double)(G.nv - 1);
-    const float fc0v = (float)c0v, ipv = (float)(1.0 / G.pv);
-    // every value of sRb is zero or a product written by stage(): finite
+    // every value of sRb and sI is zero or one written by stage(): finite
     for (int i = t; i < 2 * (kColR + 4); i += 256) (&sRb[0][0])[i] = 0.f;
+    for (int i = t; i < 2 * (kColV + 1); i += 256) (&sI[0][0])[i] = 0.0;
 
     int e0 = 0, e1 = a.n_ent;
     if (a.gptr) {
@@ -1552,6 +1555,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
         const float sl0 = C.sl0, sl1 = C.sl1, cl = C.cl, ch = C.ch;
         const float fva = (float)va, fvb = (float)(vb - 1);
         const int nrow = vb - va;
+        const int rlast = __umul24(nrow - 1, pw) + co;     // ray offset of the part's last row
 #pragma unroll
         for (int q = 0; q < kColVZ; ++q) {
             if (!valid[q]) continue;
@@ -1561,7 +1565,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
             const float fl = fmaf((float)lev, svz, f00), fh = fl + asvz;
             const float lo = fmaf(fl, fl >= 0.f ? sl1 : sl0, cl);
             const float hi = fmaf(fh, fh >= 0.f ? sl0 : sl1, ch);
-            const int k0 = (int)fmaxf(ceilf(lo), fva), k1 = (int)fminf(floorf(hi), fvb);
+            const int k0 = (int)__builtin_amdgcn_fmed3f(ceilf(lo), fva, fvb), k1 = (int)fminf(floorf(hi), fvb);
             // the voxel's faces, formed per view rather than held
             int giz = zs + lev;
             asm volatile("" : "+v"(giz));
@@ -1582,14 +1586,16 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
             float acc = accv[q];
             if ((FAST && (Ws.flags & 4)) || __all(k1 - k0 <= 1 && !wide)) {
                 // at most two rows in every lane (the usual case): both
-                // without a loop, a row beyond k1 with an empty interval
-                const int iA = min(k0 - va, nrow - 1), iB = min(iA + 1, nrow - 1);
+                // without a loop, a row beyond k1 with an empty interval (row
+                // k0 + 1 may be one past the part: its values are read, and
+                // its ray offset held in the part, but not used)
+                const int iA = k0 - va;
                 float zlA, zhA, zlB, zhB;
                 zint(SI[iA], zlA, zhA);
-                zint(SI[iB], zlB, zhB);
+                zint(SI[iA + 1], zlB, zhB);
                 zlA = k0 <= k1 ? zlA : INFINITY;
                 zlB = k0 < k1 ? zlB : INFINITY;
-                const int rA = __umul24(iA, pw) + co, rB = __umul24(iB, pw) + co;
+                const int rA = __umul24(iA, pw) + co, rB = min(rA + pw, rlast);
                 acc = fmaf(col_clip(X0, zlA, zhA), R[rA], acc);
                 acc = fmaf(col_clip(X1, zlA, zhA), R[rA + 1], acc);
                 acc = fmaf(col_clip(X0, zlB, zhB), R[rB], acc);
@@ -1609,11 +1615,14 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                         asm volatile("" : "+v"(wix), "+v"(wiy));
                         const double qx = G.ox + ((double)wix + 0.5) * G.vx - V[0];
                         const double qy = G.oy + ((double)wiy + 0.5) * G.vy - V[1];
+                        const double A0 = fma(qx, V[12], qy * V[13]);
                         for (int u = xu0; u <= uH; ++u) {
-                            const float2 xi = col_interval(G, V, ldu(G.cdxy + (size_t)view * G.nu, (unsigned)u), A,
+                            const float2 xi = col_interval(G, V, ldu(G.cdxy + (size_t)view * G.nu, (unsigned)u), A0,
                                                            fma(qx, V[6], qy * V[7]), u, ix, iy,
-                                                           src_slab(V[0], G.ox, G.ivx), src_slab(V[1], G.oy, G.ivy));
-                            acc = fmaf(col_clip(xi, zl, zh), R[rb + (u - ua)], acc);
+                                                           src_slab(V[0], G.ox, G.ivx), src_slab(V[1], G.oy, G.ivy),
+                                                           0.5 * G.vx, 0.5 * G.vy);
+                            acc = fmaf(col_clip(make_float2(ldexpf(xi.x, G.colk_e), ldexpf(xi.y, G.colk_e)), zl, zh),
+                                       R[rb + (u - ua)], acc);
                         }
                     }
                 }
@@ -1636,8 +1645,13 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
         // float64 terms formed from them stay in this loop instead of being
         // held in registers across it (more than the budget holds)
         {
-            int pt = t, pxs = xs, pys = ys, pzs = zs, pnx = nvx, pny = nvy, pnz = nvz;
-            asm volatile("" : "+v"(pt), "+s"(pxs), "+s"(pys), "+s"(pzs), "+s"(pnx), "+s"(pny), "+s"(pnz));
+            int pt = t, pxs = xs, pys = ys, pzs = zs, pnx = nvx, pny = nvy, pnz = nvz, pnv = G.nv;
+            double ppv = G.pv, phx = G.vx, phy = G.vy;
+            asm volatile("" : "+v"(pt), "+s"(pxs), "+s"(pys), "+s"(pzs), "+s"(pnx), "+s"(pny), "+s"(pnz), "+s"(pnv));
+            asm volatile("" : "+s"(ppv), "+s"(phx), "+s"(phy));
+            const float fc0v = (float)(0.5 * (double)(pnv - 1)), ipv = (float)(1.0 / ppv);
+            phx *= 0.5;
+            phy *= 0.5;
             const int j = pt >> lgNC, cc = pt & (NC - 1);
             if (j < nvr) {
                 int e = e0, off = base + j;
@@ -1715,13 +1729,13 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                 const double qy = G.oy + ((double)jy + 0.5) * G.vy - V[1];
                 const double A = fma(qx, V[12], qy * V[13]);
                 const double B = fma(qx, V[6], qy * V[7]);
-                const double ea = 0.5 * G.vx * fabs(V[12]) + 0.5 * G.vy * fabs(V[13]);
+                const double ea = phx * fabs(V[12]) + phy * fabs(V[13]);
                 ColView& C = cv[pt];
-                C.A = A;
+                C.A = ldexp(A, G.colk_e);                       // the scale of the intervals
                 const bool ok = A - ea > 0.0;
                 // row ranges: v = f / A' / pv + c0v over A' in [A - ea, A + ea];
                 // a footprint at the source's depth takes every row
-                const float mrg = 1e-3f + 1e-6f * (float)G.nv;
+                const float mrg = 1e-3f + 1e-6f * (float)pnv;
                 C.sl0 = ok ? __builtin_amdgcn_rcpf((float)(A - ea)) * ipv : 0.f;
                 C.sl1 = ok ? __builtin_amdgcn_rcpf((float)(A + ea)) * ipv : 0.f;
                 C.cl = ok ? fc0v - mrg : -1e30f;
@@ -1731,7 +1745,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                 // the source)
                 int u0 = wu0, u1 = wu1 - 1;
                 if (ok) {
-                    const float hxf = (float)(0.5 * G.vx), hyf = (float)(0.5 * G.vy);
+                    const float hxf = (float)phx, hyf = (float)phy;
                     const float Af = (float)A, Bf = (float)B;
                     const float nx = (float)V[12], ny = (float)V[13], ex = (float)V[6], ey = (float)V[7];
                     float umin = INFINITY, umax = -INFINITY;
@@ -1779,9 +1793,14 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
 #pragma unroll
                 for (int i = 0; i < kColU; ++i) {
                     const int u = u0 + i;
-                    C.X[i] = u <= u1 ? col_interval(G, V, ldu(G.cdxy + (size_t)tl.view * G.nu, (unsigned)u), A, B,
-                                                    u, jx, jy, skx, sky)
-                                     : make_float2(INFINITY, -INFINITY);
+                    float2 xi = make_float2(INFINITY, -INFINITY);
+                    if (u <= u1) {
+                        xi = col_interval(G, V, ldu(G.cdxy + (size_t)tl.view * G.nu, (unsigned)u), A, B, u, jx, jy,
+                                          skx, sky, phx, phy);
+                        xi.x = ldexpf(xi.x, G.colk_e);
+                        xi.y = ldexpf(xi.y, G.colk_e);
+                    }
+                    C.X[i] = xi;
                 }
             }
         }
@@ -1834,7 +1853,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
     double p = 0.0;
 #pragma unroll
     for (int q = 0; q < kColVZ; ++q) {
-        const float acc = accv[q];
+        const float acc = ldexpf(accv[q], -G.colk_e);  // exact
         const int iz = zs + lz + q * TL;
         const size_t gix = ((size_t)iz * G.ny + iy) * G.nx + ix;
         if (!valid[q]) continue;
@@ -1855,8 +1874,11 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
     }
 }
 
+// The standalone products (entries inline in the arguments: more scalar
+// registers) get the register budget of four work-groups per CU, where they
+// need no scratch; the solver's launches keep kColWG.
 template <class BA>
-__global__ __launch_bounds__(256, kColWG) void k_back3c(DGeom G, BA a) {
+__global__ __launch_bounds__(256, BA::kInl ? 4 : kColWG) void k_back3c(DGeom G, BA a) {
     back3c_body(G, a, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
