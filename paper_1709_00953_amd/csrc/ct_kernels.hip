@@ -1379,8 +1379,9 @@ constexpr int kColVZ = kColVoxels;  // voxels a lane at most (col_tile_shape)
 
 // Per (view, column) of a round.
 struct ColView {
-    double A;                     // view-frame depth of the column's centre
-    float sl0, sl1;               // 1 / (A -+ half the footprint's depth extent), over the row pitch
+    double A;                     // view-frame depth of the column's centre, times 2^colk_e
+    float sm, sh;                 // mean and half difference of 1 / (A -+ half the footprint's depth
+                                  // extent), over the row pitch
     float cl, ch;                 // centre row -+ margin (-+1e30 where the footprint reaches the source's depth)
     int32_t u0, u1;               // its bins within the tile's window
     int32_t co;                   // u0 - the window's first bin, clamped to [-2, window width - 1]
@@ -1460,6 +1461,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
     // inside it (the row loops below)
     __shared__ float sRb[2][kColR + 4];
     __shared__ double sI[2][kColV + 1];          // 2^e sdd / D_z of its rows; one more read, not used
+    __shared__ double zlev[32];                  // height of the lower face of each level of the tile
     __shared__ double sh[4];
     const int t = threadIdx.x;
     int TZ, CX, CY;
@@ -1486,6 +1488,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
     // every value of sRb and sI is zero or one written by stage(): finite
     for (int i = t; i < 2 * (kColR + 4); i += 256) (&sRb[0][0])[i] = 0.f;
     for (int i = t; i < 2 * (kColV + 1); i += 256) (&sI[0][0])[i] = 0.0;
+    if (t < 32) zlev[t] = fma((double)(zs + t), G.vz, G.oz);
 
     int e0 = 0, e1 = a.n_ent;
     if (a.gptr) {
@@ -1530,9 +1533,9 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                     int ub, int va, int vb) {
         constexpr bool FAST = decltype(fast_c)::value, CAREFUL = decltype(careful_c)::value;
         const float* R = &sRb[b][2];
-        const double* SI = sI[b];
-        const double zS = __hiloint2double(rfl(__double2hiint(wv[j].zS)), rfl(__double2loint(wv[j].zS)));
-        const float svz = rflf(wv[j].svz), f00 = rflf(wv[j].f00), asvz = fabsf(svz);
+        const double* SIv = sI[b] - va;                  // row k at SIv[k]
+        const double zS = wv[j].zS;
+        const float svz = wv[j].svz, f00 = wv[j].f00, asvz = fabsf(svz);
         const double A = C.A;
         const int cu0 = C.u0, cu1 = C.u1;
         float2 X0 = C.X[0], X1 = C.X[1];
@@ -1552,59 +1555,61 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
             xu0 = max(uL, cu0 + kColU);
         }
         const bool wide = xu0 <= uH;
-        const float sl0 = C.sl0, sl1 = C.sl1, cl = C.cl, ch = C.ch;
+        const float sm = C.sm, sh = C.sh, cl = C.cl, ch = C.ch;
         const float fva = (float)va, fvb = (float)(vb - 1);
-        const int nrow = vb - va;
-        const int rlast = __umul24(nrow - 1, pw) + co;     // ray offset of the part's last row
+        const int rva = co - __umul24(va, pw);           // ray offset of row k: k pw + rva
+        // f of the lower face of the lane's voxel q, stepped by TL levels
+        const float dfl = (float)TL * svz;
+        float fl = fmaf((float)lz, svz, f00);
+        int ssrc = 0;                                    // the source's level in the tile
+        if constexpr (CAREFUL) ssrc = src_slab(zS, G.oz, G.ivz) - zs;
 #pragma unroll
         for (int q = 0; q < kColVZ; ++q) {
+            if (q > 0) fl += dfl;
             if (!valid[q]) continue;
-            const int lev = lz + q * TL;
             // rows of the voxel: v = f / A' over the depths A' of its column's
-            // footprint, f over its two faces
-            const float fl = fmaf((float)lev, svz, f00), fh = fl + asvz;
-            const float lo = fmaf(fl, fl >= 0.f ? sl1 : sl0, cl);
-            const float hi = fmaf(fh, fh >= 0.f ? sl0 : sl1, ch);
+            // footprint, f over its two faces: [f sm - |f| sh, f sm + |f| sh]
+            // is f over the two depths
+            const float fh = fl + asvz;
+            const float lo = fmaf(-fabsf(fl), sh, fmaf(fl, sm, cl));
+            const float hi = fmaf(fabsf(fh), sh, fmaf(fh, sm, ch));
             const int k0 = (int)__builtin_amdgcn_fmed3f(ceilf(lo), fva, fvb), k1 = (int)fminf(floorf(hi), fvb);
-            // the voxel's faces, formed per view rather than held
-            int giz = zs + lev;
-            asm volatile("" : "+v"(giz));
-            const double zfl = fma((double)giz, G.vz, G.oz) - zS, zfh = zfl + G.vz;
+            // the voxel's lower face over the source
+            const double zfl = zlev[lz + q * TL] - zS;
             bool in_src = false;
-            if constexpr (CAREFUL) in_src = src_slab(zS, G.oz, G.ivz) == zs + lev;
+            if constexpr (CAREFUL) in_src = lz == ssrc - q * TL;
             auto zint = [&](double isv, float& zl, float& zh) {
                 if (CAREFUL && isv == 0.0) {
                     // a horizontal ray stays at the source's height
                     zl = in_src ? -INFINITY : INFINITY;
                     zh = in_src ? INFINITY : -INFINITY;
                 } else {
-                    const float p = (float)fma(zfl, isv, -A), r = (float)fma(zfh, isv, -A);
-                    zl = fminf(p, r);
-                    zh = fmaxf(p, r);
+                    const double p = fma(zfl, isv, -A);
+                    const float pf = (float)p, rf = (float)fma(G.vz, isv, p);
+                    zl = fminf(pf, rf);
+                    zh = fmaxf(pf, rf);
                 }
             };
             float acc = accv[q];
             if ((FAST && (Ws.flags & 4)) || __all(k1 - k0 <= 1 && !wide)) {
                 // at most two rows in every lane (the usual case): both
-                // without a loop, a row beyond k1 with an empty interval (row
-                // k0 + 1 may be one past the part: its values are read, and
-                // its ray offset held in the part, but not used)
-                const int iA = k0 - va;
+                // without a loop.  A row past k1 reads the zero pad before the
+                // buffer instead of its rays; its row constant (row k0 + 1 may
+                // be one past the part) is read but not used.
                 float zlA, zhA, zlB, zhB;
-                zint(SI[iA], zlA, zhA);
-                zint(SI[iA + 1], zlB, zhB);
-                zlA = k0 <= k1 ? zlA : INFINITY;
-                zlB = k0 < k1 ? zlB : INFINITY;
-                const int rA = __umul24(iA, pw) + co, rB = min(rA + pw, rlast);
+                zint(SIv[k0], zlA, zhA);
+                zint(SIv[k0 + 1], zlB, zhB);
+                const int r0 = __umul24(k0, pw) + rva;
+                const int rA = k0 <= k1 ? r0 : -2, rB = k0 < k1 ? r0 + pw : -2;
                 acc = fmaf(col_clip(X0, zlA, zhA), R[rA], acc);
                 acc = fmaf(col_clip(X1, zlA, zhA), R[rA + 1], acc);
                 acc = fmaf(col_clip(X0, zlB, zhB), R[rB], acc);
                 acc = fmaf(col_clip(X1, zlB, zhB), R[rB + 1], acc);
             } else {
-                int rb = __umul24(k0 - va, pw);
+                int rb = __umul24(k0, pw) + rva - co;
                 for (int k = k0; k <= k1; ++k, rb += pw) {
                     float zl, zh;
-                    zint(SI[k - va], zl, zh);
+                    zint(SIv[k], zl, zh);
                     acc = fmaf(col_clip(X0, zl, zh), R[rb + co], acc);
                     acc = fmaf(col_clip(X1, zl, zh), R[rb + co + 1], acc);
                     if (wide) {
@@ -1736,8 +1741,10 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                 // row ranges: v = f / A' / pv + c0v over A' in [A - ea, A + ea];
                 // a footprint at the source's depth takes every row
                 const float mrg = 1e-3f + 1e-6f * (float)pnv;
-                C.sl0 = ok ? __builtin_amdgcn_rcpf((float)(A - ea)) * ipv : 0.f;
-                C.sl1 = ok ? __builtin_amdgcn_rcpf((float)(A + ea)) * ipv : 0.f;
+                const float sl0 = ok ? __builtin_amdgcn_rcpf((float)(A - ea)) * ipv : 0.f;
+                const float sl1 = ok ? __builtin_amdgcn_rcpf((float)(A + ea)) * ipv : 0.f;
+                C.sm = 0.5f * (sl0 + sl1);
+                C.sh = 0.5f * (sl0 - sl1);
                 C.cl = ok ? fc0v - mrg : -1e30f;
                 C.ch = ok ? fc0v + mrg : 1e30f;
                 // bins in the window whose ray can meet the column: the
@@ -1776,8 +1783,8 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
 #pragma unroll
                     for (int e2 = 0; e2 < 2; ++e2) {
                         const float fl = fmaf((float)(e2 ? pnz - 1 : 0), svz, f00), fh = fl + asvz;
-                        const float lo = fl * (fl >= 0.f ? C.sl1 : C.sl0) + C.cl;
-                        const float hi = fh * (fh >= 0.f ? C.sl0 : C.sl1) + C.ch;
+                        const float lo = fl * (fl >= 0.f ? sl1 : sl0) + C.cl;
+                        const float hi = fh * (fh >= 0.f ? sl0 : sl1) + C.ch;
                         simple = simple && hi - lo < 1.9f;
                     }
                 }
