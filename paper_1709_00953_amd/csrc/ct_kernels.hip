@@ -656,13 +656,18 @@ struct ViewP {
 // sine and quadratic cosine are exact to 3e-11 and 7e-9 (times distances
 // below a metre and a tile), so the distance needs no float64 product per
 // candidate, and a candidate reads only K, S, M of its bin and r.
+// Where W < 1 a voxel has at most two candidates, b and b + 1 (flag bit 2):
+// the second's distance is the first's turned by one pitch,
+// X' = X cos pu - Y sin pu with Y = X sin e + R cos e, instead of a second
+// polynomial.
 struct FanC {
     float Xx, Xy, Yx, Yy;         // X and R per voxel step along x and y
     float Xc, Rc;                 // X and R at the tile centre
     int32_t kr;                   // reference bin
     float pu;                     // bin pitch (rad)
+    float cp, sp;                 // cos pu, sin pu
 };
-static_assert(sizeof(FanC) <= 4 * sizeof(double), "FanC overlays Ac, Bc, ax, ay");
+static_assert(sizeof(FanC) <= 6 * sizeof(double), "FanC overlays Ac, Bc, ax, ay, bx, by");
 
 template <int KIND>
 __device__ __forceinline__ void view_params(const DGeom& G, const Tile& tl, double cx, double cy,
@@ -756,8 +761,15 @@ __device__ __forceinline__ void view_params(const DGeom& G, const Tile& tl, doub
             f.Rc = (float)(p * P.Ac + q * P.Bc);
             f.kr = kr;
             f.pu = (float)G.pu;
+            // pu <= emax <= 2e-2: the series are exact in float32
+            const double pu2 = G.pu * G.pu;
+            f.cp = (float)fma(pu2, -0.5, 1.0);
+            f.sp = (float)(G.pu * fma(pu2, -1.0 / 6.0, 1.0));
             __builtin_memcpy(&P.Ac, &f, sizeof f);
             P.flags |= 2;
+            // candidates [ceil(beta - W), floor(beta + W)]: at most two
+            // where W < 1 (the margin covers the rounding of beta -+ W)
+            if ((float)fmin(W, 1e9) + 2e-3f + 1e-6f * fabsf((float)bc) < 0.999f) P.flags |= 4;
         }
     }
 }
@@ -799,7 +811,10 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
     float acc = 0.f;
     for (int base = 0; base < nt; base += 64 * NW) {
         // lane `lane` of wave `w` prepares the view with flat index base + NW lane + w
-        const int f = base + NW * lane + w;
+        // the lane's slot and view index formed here, not held across the loop
+        int slot = threadIdx.x;
+        asm volatile("" : "+v"(slot));
+        const int f = base + NW * (slot & 63) + (slot >> 6);
         if (f < nt) {
             int e = e0, off = f;
             for (;;) {
@@ -807,7 +822,7 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
                 const int cnt = G.rb_tile_ptr[rb + 1] - G.rb_tile_ptr[rb];
                 if (off < cnt) {
                     const Tile tl = G.tiles[G.rb_tile_ptr[rb] + off];
-                    view_params<KIND>(G, tl, tcx, tcy, dt, vp[w][lane]);
+                    view_params<KIND>(G, tl, tcx, tcy, dt, vp[slot >> 6][slot & 63]);
                     break;
                 }
                 off -= cnt;
@@ -828,6 +843,30 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
                 const int bhi = min((int)floorf(beta + P.W), u1 - 1);
                 const Ray2B* RB = G.ray2b + (size_t)view * G.nu;
                 const float* rr = a.r + (size_t)view * G.nu;
+                if (KIND == kFanCurved && (vflags & 4)) {
+                    // at most two candidates: bins b0 = blo and b0 + 1, read
+                    // where in range and their clips zeroed where not
+                    FanC f;
+                    __builtin_memcpy(&f, &P.Ac, sizeof f);
+                    const float Xs = f.Xc + fmaf(lyf, f.Xy, lxf * f.Xx);
+                    const float Rs = f.Rc + fmaf(lyf, f.Yy, lxf * f.Yx);
+                    const float4* KS = reinterpret_cast<const float4*>(G.ray2k + (size_t)view * G.nu);
+                    const int b0 = min(blo, u1 - 1), b1 = min(b0 + 1, u1 - 1);
+                    const float4 k0 = ldu(KS, (unsigned)b0), k1 = ldu(KS, (unsigned)b1);
+                    const float r0 = ldu(rr, (unsigned)b0), r1 = ldu(rr, (unsigned)b1);
+                    const float e = (float)(b0 - f.kr) * f.pu;
+                    const float e2 = e * e;
+                    const float sn = e * fmaf(e2, -1.f / 6.f, 1.f);
+                    const float cs = fmaf(e2, -0.5f, 1.f);
+                    const float d0 = fmaf(cs, Xs, -sn * Rs);
+                    const float y0 = fmaf(sn, Xs, cs * Rs);
+                    const float d1 = fmaf(d0, f.cp, -y0 * f.sp);
+                    const float c0 = __builtin_amdgcn_fmed3f(k0.y - fabsf(d0 * k0.x), 0.f, k0.z);
+                    const float c1 = __builtin_amdgcn_fmed3f(k1.y - fabsf(d1 * k1.x), 0.f, k1.z);
+                    acc = fmaf(blo <= bhi ? c0 : 0.f, r0, acc);
+                    acc = fmaf(blo < bhi ? c1 : 0.f, r1, acc);
+                    continue;
+                }
                 if (KIND == kFanCurved && (vflags & 2)) {
                     if (blo <= bhi) {
                         FanC f;
@@ -911,12 +950,15 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
     }
 }
 
-// At most 64 VGPRs (eight waves per SIMD); with four waves, 20 KB of LDS:
-// eight work-groups per CU, so a launch of 2048 tiles (four groups of a
-// 128 x 256 block) is resident in one round.  Eight or sixteen waves per tile
-// (up to 80 KB of LDS) spread a small launch's views over more SIMDs.
+// At most 64 VGPRs (eight waves per SIMD, the second bound); with four
+// waves, 20 KB of LDS: eight work-groups per CU, so a launch of 2048 tiles
+// (four groups of a 128 x 256 block) is resident in one round.  Eight or
+// sixteen waves per tile (up to 80 KB of LDS) spread a small launch's views
+// over more SIMDs.  One wave per tile keeps a lane's curved-fan state in
+// registers at seven waves per SIMD (72 VGPRs).
+constexpr int back2_waves(int nw) { return nw == 1 ? 7 : (nw <= 4 ? 8 : 32 / nw); }
 template <int KIND, class BA, int NW>
-__global__ __launch_bounds__(64 * NW, NW <= 4 ? 8 : 32 / NW) void k_back2(DGeom G, BA a) {
+__global__ __launch_bounds__(64 * NW, back2_waves(NW)) void k_back2(DGeom G, BA a) {
     back2_body<KIND, BA, NW>(G, a, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
@@ -2093,7 +2135,7 @@ __device__ __forceinline__ int box_vox(const Box& b) {
 // occupancy as the single-job kernels: eight waves per SIMD in 2D, six in 3D;
 // NW waves per 2D tile (the 3D tile always takes four)
 template <int KIND, int NW>
-__global__ __launch_bounds__(64 * NW, KIND == kCone ? 6 : (KIND == kConeV ? kColWG : (NW <= 4 ? 8 : 32 / NW))) void kb_back(BatchArgs B) {
+__global__ __launch_bounds__(64 * NW, KIND == kCone ? 6 : (KIND == kConeV ? kColWG : back2_waves(NW))) void kb_back(BatchArgs B) {
     const int k = batch_job(B, blockIdx.x);
     const int L = blockIdx.x - B.prefix[k];
     const BJob J = cld(B.jobs, k);

@@ -68,6 +68,45 @@ def test_reference_bin_distance_matches_float64():
     assert err.max() <= 1.5e-6, err.max()
 
 
+def test_turned_next_bin_distance_matches_float64():
+    """Where a voxel has at most two candidate bins, the second's distance is
+    the first's turned by one pitch: X' = X cos pu - Y sin pu with the depth
+    Y = X sin e + R cos e in the first bin's frame, in float32 as the kernel
+    forms it, against the float64 distance of bin b + 1."""
+    rng = np.random.default_rng(8)
+    sid, pu, nu, vx = 500.0, 1e-3, 768, 0.5
+    c0 = 0.5 * (nu - 1)
+    n = 20000
+    th = rng.uniform(0.0, 2.0 * np.pi, n)
+    s17 = rng.choice([-1.0, 1.0], n)
+    eA = np.stack([np.cos(th), np.sin(th)], 1)
+    eB = s17[:, None] * np.stack([-np.sin(th), np.cos(th)], 1)
+    w17 = eA[:, 0] * eB[:, 1] - eA[:, 1] * eB[:, 0]
+    q = rng.uniform(-125.0, 125.0, (n, 2)) + sid * eA                   # voxel centre from the source
+    A, B = (q * eA).sum(1), (q * eB).sum(1)
+    bc = np.arctan2(B, A) / pu + c0
+    kr = np.clip(np.floor(bc + 0.5) + rng.integers(-3, 4, n), 0, nu - 1)   # reference bin near the shadow
+    g = (kr - c0) * pu
+    p, qq = w17 * np.cos(g), w17 * np.sin(g)
+    Xs, Rs = f32(p * B - qq * A), f32(p * A + qq * B)                    # float32 X, R (rounded once)
+    b0 = np.floor(bc + rng.uniform(-0.7, 0.7, n))
+    e = ((b0 - kr).astype(f32) * f32(pu)).astype(f32)
+    assert np.abs(e).max() <= 2e-2
+    one = np.ones(n, dtype=f32)
+    e2 = (e * e).astype(f32)
+    sn = (e * _fma32(e2, np.full(n, f32(-1.0 / 6.0)), one)).astype(f32)
+    cs = _fma32(e2, np.full(n, f32(-0.5)), one)
+    d0 = _fma32(cs, Xs, (-(sn * Rs)).astype(f32))
+    y0 = _fma32(sn, Xs, (cs * Rs).astype(f32))
+    cp, sp = np.full(n, f32(np.cos(pu))), f32(np.sin(pu))
+    d1 = _fma32(d0, cp, (-(y0 * sp)).astype(f32))
+    for bb, got in ((b0, d0), (b0 + 1, d1)):
+        gb = (bb - c0) * pu
+        ref = w17 * (np.cos(gb) * B - np.sin(gb) * A)
+        err = np.abs(got.astype(np.float64) - ref)
+        assert err.max() <= 1.5e-6, err.max()
+
+
 def test_polynomial_angle_bound():
     """The cubic sine and quadratic cosine at |e| <= 2e-2 against float64."""
     e = np.linspace(-2e-2, 2e-2, 100001)
