@@ -809,12 +809,17 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
     }
 
     float acc = 0.f;
+    ViewP* const vpf = &vp[0][0];                        // flat: view base + i at vpf[i]
     for (int base = 0; base < nt; base += 64 * NW) {
-        // lane `lane` of wave `w` prepares the view with flat index base + NW lane + w
-        // the lane's slot and view index formed here, not held across the loop
-        int slot = threadIdx.x;
+        // thread i prepares view base + i, so that where the group has fewer
+        // views than threads whole waves have none (their lanes would idle
+        // through the set-up); wave w then takes views w, w + NW, ...  The
+        // thread index is formed from the voxel indices (held anyway) and
+        // passes through an empty asm statement, so neither it nor the slot's
+        // address is held across the loop.
+        int slot = (wu << 6) | ((iy - ys) << 3) | (ix - xs);
         asm volatile("" : "+v"(slot));
-        const int f = base + NW * (slot & 63) + (slot >> 6);
+        const int f = base + slot;
         if (f < nt) {
             int e = e0, off = f;
             for (;;) {
@@ -822,7 +827,7 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
                 const int cnt = G.rb_tile_ptr[rb + 1] - G.rb_tile_ptr[rb];
                 if (off < cnt) {
                     const Tile tl = G.tiles[G.rb_tile_ptr[rb] + off];
-                    view_params<KIND>(G, tl, tcx, tcy, dt, vp[slot >> 6][slot & 63]);
+                    view_params<KIND>(G, tl, tcx, tcy, dt, vpf[slot]);
                     break;
                 }
                 off -= cnt;
@@ -833,7 +838,7 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
         const int nb = min(64, (nt - base - wu + NW - 1) / NW);
         if (valid) {
             for (int j = 0; j < nb; ++j) {
-                const ViewP& P = vp[wu][j];
+                const ViewP& P = vpf[NW * j + wu];
                 const int view = __builtin_amdgcn_readfirstlane(P.view);
                 const int u0 = __builtin_amdgcn_readfirstlane(P.u0);
                 const int u1 = __builtin_amdgcn_readfirstlane(P.u1);
@@ -954,11 +959,12 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
 // waves, 20 KB of LDS: eight work-groups per CU, so a launch of 2048 tiles
 // (four groups of a 128 x 256 block) is resident in one round.  Eight or
 // sixteen waves per tile (up to 80 KB of LDS) spread a small launch's views
-// over more SIMDs.  One wave per tile keeps a lane's curved-fan state in
-// registers at seven waves per SIMD (72 VGPRs).
-constexpr int back2_waves(int nw) { return nw == 1 ? 7 : (nw <= 4 ? 8 : 32 / nw); }
+// over more SIMDs.  One wave per tile, and the standalone products (entries
+// inline in the arguments), keep a lane's curved-fan state in registers at
+// seven waves per SIMD (72 VGPRs).
+constexpr int back2_waves(int nw, bool inl) { return (nw == 1 || (inl && nw <= 4)) ? 7 : (nw <= 4 ? 8 : 32 / nw); }
 template <int KIND, class BA, int NW>
-__global__ __launch_bounds__(64 * NW, back2_waves(NW)) void k_back2(DGeom G, BA a) {
+__global__ __launch_bounds__(64 * NW, back2_waves(NW, BA::kInl)) void k_back2(DGeom G, BA a) {
     back2_body<KIND, BA, NW>(G, a, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
@@ -2135,7 +2141,7 @@ __device__ __forceinline__ int box_vox(const Box& b) {
 // occupancy as the single-job kernels: eight waves per SIMD in 2D, six in 3D;
 // NW waves per 2D tile (the 3D tile always takes four)
 template <int KIND, int NW>
-__global__ __launch_bounds__(64 * NW, KIND == kCone ? 6 : (KIND == kConeV ? kColWG : back2_waves(NW))) void kb_back(BatchArgs B) {
+__global__ __launch_bounds__(64 * NW, KIND == kCone ? 6 : (KIND == kConeV ? kColWG : back2_waves(NW, false))) void kb_back(BatchArgs B) {
     const int k = batch_job(B, blockIdx.x);
     const int L = blockIdx.x - B.prefix[k];
     const BJob J = cld(B.jobs, k);
