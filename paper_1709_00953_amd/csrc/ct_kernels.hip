@@ -809,17 +809,21 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
     }
 
     float acc = 0.f;
-    ViewP* const vpf = &vp[0][0];                        // flat: view base + i at vpf[i]
+    ViewP* const vpf = &vp[0][0];                        // view slots, flat
     for (int base = 0; base < nt; base += 64 * NW) {
-        // thread i prepares view base + i, so that where the group has fewer
-        // views than threads whole waves have none (their lanes would idle
-        // through the set-up); wave w then takes views w, w + NW, ...  The
+        // Up to four waves a tile, thread i prepares view base + i, so that
+        // where the group has fewer views than threads whole waves have none
+        // (their lanes would idle through the set-up); wave w then takes
+        // views w, w + NW, ...  With eight or sixteen waves, lane l of wave w
+        // prepares the view of flat index NW l + w, the set-up of a few views
+        // in every wave: one or two waves' 64-lane loads of it measured
+        // slower (the paper's 2D setting: 82 against 67 us per launch).  The
         // thread index is formed from the voxel indices (held anyway) and
         // passes through an empty asm statement, so neither it nor the slot's
         // address is held across the loop.
         int slot = (wu << 6) | ((iy - ys) << 3) | (ix - xs);
         asm volatile("" : "+v"(slot));
-        const int f = base + slot;
+        const int f = NW >= 8 ? base + NW * (slot & 63) + (slot >> 6) : base + slot;
         if (f < nt) {
             int e = e0, off = f;
             for (;;) {
@@ -838,7 +842,7 @@ __device__ __forceinline__ void back2_body(const DGeom& G, const BA& a, const in
         const int nb = min(64, (nt - base - wu + NW - 1) / NW);
         if (valid) {
             for (int j = 0; j < nb; ++j) {
-                const ViewP& P = vpf[NW * j + wu];
+                const ViewP& P = NW >= 8 ? vpf[wu * 64 + j] : vpf[NW * j + wu];
                 const int view = __builtin_amdgcn_readfirstlane(P.view);
                 const int u0 = __builtin_amdgcn_readfirstlane(P.u0);
                 const int u1 = __builtin_amdgcn_readfirstlane(P.u1);
