@@ -1508,10 +1508,12 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                                             const int n_tiles) {
     __shared__ ColView cv[256];                  // [view slot][column]
     __shared__ WinView wv[16];                   // [view slot] (at least 16 columns: at most 16 views a round)
-    // |D~| r of a window's rays, two views in flight; two zero floats before
-    // and after each buffer, so that the two bins a voxel reads per row stay
+    // |D~| r of a window's rays, two views in flight.  Two zero floats before
+    // each buffer, and room after it for one more row of the widest window
+    // (one row of kColR) and two floats, so that the two bins a voxel reads
+    // per row, and the row after a staged part (zeroed by stage()), stay
     // inside it (the row loops below)
-    __shared__ float sRb[2][kColR + 4];
+    __shared__ float sRb[2][2 * kColR + 4];
     __shared__ double sI[2][kColV + 1];          // 2^e sdd / D_z of its rows; one more read, not used
     __shared__ double zlev[32];                  // height of the lower face of each level of the tile
     __shared__ double sh[4];
@@ -1538,7 +1540,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
 #pragma unroll
     for (int q = 0; q < kColVZ; ++q) valid[q] = colv && q < VZ && lz + q * TL < nvz;
     // every value of sRb and sI is zero or one written by stage(): finite
-    for (int i = t; i < 2 * (kColR + 4); i += 256) (&sRb[0][0])[i] = 0.f;
+    for (int i = t; i < 2 * (2 * kColR + 4); i += 256) (&sRb[0][0])[i] = 0.f;
     for (int i = t; i < 2 * (kColV + 1); i += 256) (&sI[0][0])[i] = 0.0;
     if (t < 32) zlev[t] = fma((double)(zs + t), G.vz, G.oz);
 
@@ -1556,6 +1558,9 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
     // rays [0, nr) (rows of pw bins from (ua, va)) and rows [0, nrow) of a
     // window part of `view` into buffer b
     auto stage = [&](int view, int b, int pw, int ua, int va, int nr, int nrow) {
+        // the buffer index passes through an empty asm statement, so the
+        // buffers' offsets are formed here rather than held across the views
+        asm volatile("" : "+s"(b));
         const float* rview = a.r + (size_t)view * G.nv * G.nu;
         const float2* dxy = G.cdxy + (size_t)view * G.nu;
         const float* dz = G.cdz + (size_t)view * G.nv;
@@ -1570,6 +1575,8 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
             const float nrm = __builtin_amdgcn_sqrtf(fmaf(q.x, q.x, fmaf(q.y, q.y, z * z)));
             sRb[b][2 + i] = nrm * ldu(rview, (unsigned)(iv * G.nu + iu));
         }
+        // the row after the part reads zeros (and two more floats)
+        for (int i = t; i < pw + 2; i += 256) sRb[b][2 + nr + i] = 0.f;
         const double* isv = G.cisv + (size_t)view * G.nv;
         for (int i = t; i < nrow; i += 256) sI[b][i] = ldu(isv, (unsigned)(va + i));
     };
@@ -1644,15 +1651,17 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
             };
             float acc = accv[q];
             if ((FAST && (Ws.flags & 4)) || __all(k1 - k0 <= 1 && !wide)) {
-                // at most two rows in every lane (the usual case): both
-                // without a loop.  A row past k1 reads the zero pad before the
-                // buffer instead of its rays; its row constant (row k0 + 1 may
-                // be one past the part) is read but not used.
+                // at most two rows in every lane (the usual case): rows k0
+                // and k0 + 1 without a loop.  A row outside [k0, k1] misses
+                // the voxel by more than the row range's margin (1e-3 of a
+                // row), far beyond rounding, so its clips are exactly 0; row
+                // k0 + 1 may be one past the part, whose rays the staging
+                // left zero (its row constant, read from the pad, is not
+                // used).
                 float zlA, zhA, zlB, zhB;
                 zint(SIv[k0], zlA, zhA);
                 zint(SIv[k0 + 1], zlB, zhB);
-                const int r0 = __umul24(k0, pw) + rva;
-                const int rA = k0 <= k1 ? r0 : -2, rB = k0 < k1 ? r0 + pw : -2;
+                const int rA = __umul24(k0, pw) + rva, rB = rA + pw;
                 acc = fmaf(col_clip(X0, zlA, zhA), R[rA], acc);
                 acc = fmaf(col_clip(X1, zlA, zhA), R[rA + 1], acc);
                 acc = fmaf(col_clip(X0, zlB, zhB), R[rB], acc);
@@ -1688,7 +1697,11 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
         }
     };
     auto both_u = [&](auto fast_c, int j, const WinS& W, int b, int pw, int ua, int ub, int va, int vb) {
-        const ColView& C = cv[j * NC + c];
+        // the lane's column index passes through an empty asm statement, so
+        // its slot's address is formed per view rather than held
+        int cc = c;
+        asm volatile("" : "+v"(cc));
+        const ColView& C = cv[j * NC + cc];
         if (W.flags & 2)
             both(fast_c, std::true_type{}, j, W, C, b, pw, ua, ub, va, vb);
         else
@@ -1873,7 +1886,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
         for (int j = 0; j < nvr; ++j) {
             const int b = j & 1;
             const bool more = j + 1 < nvr;
-            const WinS Wn = win_s(wv[more ? j + 1 : j]);
+            const WinS Wn = win_s(wv[min(j + 1, nvr - 1)]);
             const bool empty = W.u1 <= W.u0 || W.v1 <= W.v0;
             if (W.flags & 1) {
                 if (more && (Wn.flags & 1))
