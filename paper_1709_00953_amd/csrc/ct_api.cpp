@@ -509,11 +509,11 @@ static int col_scale_exp(const ct_geom_desc& d) {
     return e;
 }
 
-static void build_columns(const ct_geom* g, std::vector<float2>& dxy, std::vector<float>& dz,
+static void build_columns(const ct_geom* g, std::vector<float4>& dxy, std::vector<float>& dz,
                           std::vector<double>& isv) {
     const ct_geom_desc& d = g->d;
     const int ke = col_scale_exp(d);
-    dxy.assign((size_t)d.n_views * d.nu, float2{});
+    dxy.assign((size_t)d.n_views * d.nu, float4{});
     dz.assign((size_t)d.n_views * d.nv, 0.f);
     isv.assign((size_t)d.n_views * d.nv, 0.0);
     for (int k = 0; k < d.n_views; ++k) {
@@ -521,9 +521,12 @@ static void build_columns(const ct_geom* g, std::vector<float2>& dxy, std::vecto
         const double sdd = W[15], is = W[16];
         for (int iu = 0; iu < d.nu; ++iu) {
             const double u = ((double)iu - 0.5 * (double)(d.nu - 1)) * d.pu;
-            float2& q = dxy[(size_t)k * d.nu + iu];
-            q.x = (float)(std::fma(u, W[6], sdd * W[12]) * is);
-            q.y = (float)(std::fma(u, W[7], sdd * W[13]) * is);
+            float4& q = dxy[(size_t)k * d.nu + iu];
+            const double qx = std::fma(u, W[6], sdd * W[12]) * is, qy = std::fma(u, W[7], sdd * W[13]) * is;
+            q.x = (float)qx;
+            q.y = (float)qy;
+            q.z = (float)(qx * qx + qy * qy);
+            q.w = 0.f;
         }
         for (int iv = 0; iv < d.nv; ++iv) {
             const double v = ((double)iv - 0.5 * (double)(d.nv - 1)) * d.pv;
@@ -547,7 +550,7 @@ static DevLayout dev_layout(const ct_geom* g) {
     L.off_rayf = take(g->dims == 2 ? (size_t)g->d.n_views * g->d.nu * sizeof(Ray2F) : 0);
     L.off_rayb = take(g->dims == 2 ? (size_t)g->d.n_views * g->d.nu * sizeof(Ray2B) : 0);
     L.off_rayk = take(g->dims == 2 ? (size_t)g->d.n_views * g->d.nu * sizeof(Ray2K) : 0);
-    L.off_cdxy = take(g->vertical ? (size_t)g->d.n_views * g->d.nu * sizeof(float2) : 0);
+    L.off_cdxy = take(g->vertical ? (size_t)g->d.n_views * g->d.nu * sizeof(float4) : 0);
     L.off_cdz = take(g->vertical ? (size_t)g->d.n_views * g->d.nv * sizeof(float) : 0);
     L.off_cisv = take(g->vertical ? (size_t)g->d.n_views * g->d.nv * sizeof(double) : 0);
     L.off_flags = take((size_t)g->d.n_views * sizeof(int32_t));
@@ -576,7 +579,7 @@ int geom_table_pack(const ct_geom* g, void* dst) {
     std::vector<Ray2K> rayk;
     std::vector<int32_t> flags;
     build_frames(g, rayf, rayb, rayk, flags);
-    std::vector<float2> cdxy;
+    std::vector<float4> cdxy;
     std::vector<float> cdz;
     std::vector<double> cisv;
     if (g->vertical) build_columns(g, cdxy, cdz, cisv);
@@ -589,7 +592,7 @@ int geom_table_pack(const ct_geom* g, void* dst) {
     put(L.off_rayf, rayf.data(), rayf.size() * sizeof(Ray2F));
     put(L.off_rayb, rayb.data(), rayb.size() * sizeof(Ray2B));
     put(L.off_rayk, rayk.data(), rayk.size() * sizeof(Ray2K));
-    put(L.off_cdxy, cdxy.data(), cdxy.size() * sizeof(float2));
+    put(L.off_cdxy, cdxy.data(), cdxy.size() * sizeof(float4));
     put(L.off_cdz, cdz.data(), cdz.size() * sizeof(float));
     put(L.off_cisv, cisv.data(), cisv.size() * sizeof(double));
     put(L.off_flags, flags.data(), flags.size() * sizeof(int32_t));
@@ -638,7 +641,7 @@ static void geom_bind(ct_geom* g, void* mem, int dev, bool owned) {
     G.ray2f = g->dims == 2 ? (const Ray2F*)(base + L.off_rayf) : nullptr;
     G.ray2b = g->dims == 2 ? (const Ray2B*)(base + L.off_rayb) : nullptr;
     G.ray2k = g->dims == 2 ? (const Ray2K*)(base + L.off_rayk) : nullptr;
-    G.cdxy = g->vertical ? (const float2*)(base + L.off_cdxy) : nullptr;
+    G.cdxy = g->vertical ? (const float4*)(base + L.off_cdxy) : nullptr;
     G.cdz = g->vertical ? (const float*)(base + L.off_cdz) : nullptr;
     G.cisv = g->vertical ? (const double*)(base + L.off_cisv) : nullptr;
     G.view_flags = (const int32_t*)(base + L.off_flags);

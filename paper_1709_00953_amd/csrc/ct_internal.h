@@ -140,10 +140,11 @@ struct DGeom {
     const Ray2B* ray2b;           // [n_views][nu] (2D kinds)
     const Ray2K* ray2k;           // [n_views][nu] (curved fan)
     // vertical cones (kConeV): float32 components D~_x, D~_y of the rays of
-    // each detector column and D~_z of each row (the values every cone kernel
-    // forms, (float)(D_k / sdd)), and sdd / D_z of each row in float64 (0 for
-    // a zero component)
-    const float2* cdxy;           // [n_views][nu]
+    // each detector column (the values every cone kernel forms,
+    // (float)(D_k / sdd)) with D~_x^2 + D~_y^2 (from float64) and a zero, D~_z
+    // of each row, and 2^colk_e sdd / D_z of each row in float64 (0 for a
+    // zero component)
+    const float4* cdxy;           // [n_views][nu]
     const float* cdz;             // [n_views][nv]
     const double* cisv;           // [n_views][nv]
     const int32_t* view_flags;    // [n_views] bit0: some ray has a zero direction component

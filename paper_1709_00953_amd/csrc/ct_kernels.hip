@@ -1437,7 +1437,7 @@ struct ColView {
     float cl, ch;                 // centre row -+ margin (-+1e30 where the footprint reaches the source's depth)
     int32_t u0, u1;               // its bins within the tile's window
     int32_t co;                   // u0 - the window's first bin, clamped to [-2, window width - 1]
-    int32_t pad;
+    int32_t rva;                  // co - v0 (window width): row k's rays from k (width) + rva
     float2 X[kColU];              // X of bins u0 and u0 + 1 (empty where absent)
 };
 // Per view of a round: the tile's detector window [u0, u1) x [v0, v1), whether
@@ -1449,6 +1449,7 @@ struct ColView {
 struct WinView {
     double zS;                    // source height
     float svz, f00;
+    float fv0, fv1, dfl;          // v0 and v1 - 1 as floats; svz times the lanes of a column
     int32_t view, u0, u1, v0, v1, flags;
 };
 
@@ -1491,6 +1492,8 @@ __device__ __forceinline__ float2 col_interval(const DGeom& G, const double* V, 
     }
     return make_float2(lo, hi);
 }
+
+__device__ __forceinline__ float2 f4xy(const float4 q) { return make_float2(q.x, q.y); }
 
 __device__ __forceinline__ int src_slab(double s, double o, double ih) {
     return (int)fmin(fmax(floor((s - o) * ih), -1e9), 1e9);
@@ -1562,17 +1565,17 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
         // buffers' offsets are formed here rather than held across the views
         asm volatile("" : "+s"(b));
         const float* rview = a.r + (size_t)view * G.nv * G.nu;
-        const float2* dxy = G.cdxy + (size_t)view * G.nu;
+        const float4* dxy = G.cdxy + (size_t)view * G.nu;
         const float* dz = G.cdz + (size_t)view * G.nv;
         // row of element i: (i + 1/2) / pw lies at least 1/(2 pw) from an
         // integer, far beyond the rounding of rcp and the product for i < 2^12
         const float ipw = __builtin_amdgcn_rcpf((float)pw);
         for (int i = t; i < nr; i += 256) {
             const int row = (int)(((float)i + 0.5f) * ipw);
-            const int iu = ua + (i - row * pw), iv = va + row;
-            const float2 q = ldu(dxy, (unsigned)iu);
+            const int iu = ua + (i - __umul24(row, pw)), iv = va + row;
+            const float q2 = ldu(reinterpret_cast<const float*>(dxy + iu), 2u);   // D~_x^2 + D~_y^2
             const float z = ldu(dz, (unsigned)iv);
-            const float nrm = __builtin_amdgcn_sqrtf(fmaf(q.x, q.x, fmaf(q.y, q.y, z * z)));
+            const float nrm = __builtin_amdgcn_sqrtf(fmaf(z, z, q2));
             sRb[b][2 + i] = nrm * ldu(rview, (unsigned)(iv * G.nu + iu));
         }
         // the row after the part reads zeros (and two more floats)
@@ -1595,6 +1598,8 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
         const double* SIv = sI[b] - va;                  // row k at SIv[k]
         const double zS = wv[j].zS;
         const float svz = wv[j].svz, f00 = wv[j].f00, asvz = fabsf(svz);
+        int rva = C.rva;
+        float fva = wv[j].fv0, fvb = wv[j].fv1;
         const double A = C.A;
         const int cu0 = C.u0, cu1 = C.u1;
         float2 X0 = C.X[0], X1 = C.X[1];
@@ -1612,13 +1617,14 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
             // the buffer and its zero pads
             co = min(max(cu0 - ua, -2), pw - 1);
             xu0 = max(uL, cu0 + kColU);
+            rva = co - __umul24(va, pw);
+            fva = (float)va;
+            fvb = (float)(vb - 1);
         }
         const bool wide = xu0 <= uH;
         const float sm = C.sm, sh = C.sh, cl = C.cl, ch = C.ch;
-        const float fva = (float)va, fvb = (float)(vb - 1);
-        const int rva = co - __umul24(va, pw);           // ray offset of row k: k pw + rva
         // f of the lower face of the lane's voxel q, stepped by TL levels
-        const float dfl = (float)TL * svz;
+        const float dfl = wv[j].dfl;
         float fl = fmaf((float)lz, svz, f00);
         int ssrc = 0;                                    // the source's level in the tile
         if constexpr (CAREFUL) ssrc = src_slab(zS, G.oz, G.ivz) - zs;
@@ -1683,7 +1689,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                         const double qy = G.oy + ((double)wiy + 0.5) * G.vy - V[1];
                         const double A0 = fma(qx, V[12], qy * V[13]);
                         for (int u = xu0; u <= uH; ++u) {
-                            const float2 xi = col_interval(G, V, ldu(G.cdxy + (size_t)view * G.nu, (unsigned)u), A0,
+                            const float2 xi = col_interval(G, V, f4xy(ldu(G.cdxy + (size_t)view * G.nu, (unsigned)u)), A0,
                                                            fma(qx, V[6], qy * V[7]), u, ix, iy,
                                                            src_slab(V[0], G.ox, G.ivx), src_slab(V[1], G.oy, G.ivy),
                                                            0.5 * G.vx, 0.5 * G.vy);
@@ -1789,6 +1795,9 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                         W.u1 = wu1;
                         W.v0 = wv0;
                         W.v1 = wv1;
+                        W.fv0 = (float)wv0;
+                        W.fv1 = (float)(wv1 - 1);
+                        W.dfl = (float)TL * (float)svz;
                         const bool fast = (wu1 - wu0) * (wv1 - wv0) <= kColR && wv1 - wv0 <= kColV;
                         W.flags = (fast ? 1 : 0) | ((G.view_flags[tl.view] & 1) ? 2 : 0);
                     }
@@ -1836,6 +1845,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                 C.u0 = u0;
                 C.u1 = u1;
                 C.co = min(u0 - wu0, max(1, wu1 - wu0) - 1);    // u0 >= wu0
+                C.rva = C.co - wv0 * max(1, wu1 - wu0);
                 // at most two bins, and at most two rows at every level: the
                 // rows of a voxel span hi - lo = fh s - fl s' + (ch - cl),
                 // which is convex in the level, so its largest value is at the
@@ -1867,7 +1877,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                     const int u = u0 + i;
                     float2 xi = make_float2(INFINITY, -INFINITY);
                     if (u <= u1) {
-                        xi = col_interval(G, V, ldu(G.cdxy + (size_t)tl.view * G.nu, (unsigned)u), A, B, u, jx, jy,
+                        xi = col_interval(G, V, f4xy(ldu(G.cdxy + (size_t)tl.view * G.nu, (unsigned)u)), A, B, u, jx, jy,
                                           skx, sky, phx, phy);
                         xi.x = ldexpf(xi.x, G.colk_e);
                         xi.y = ldexpf(xi.y, G.colk_e);
