@@ -31,20 +31,20 @@ enum { kPar2D = 0, kFanFlat = 1, kFanCurved = 2, kCone = 3 };
 constexpr int kConeV = 4;
 
 // Voxel-column tile of that kernel: CX x CY columns of TZ voxels in z, 256
-// lanes, each lane VZ voxels of a column (levels l, l + TZ / VZ, ...): four,
-// or TZ when TZ < 4.  More voxels a lane share its per-view work (the window's
-// staging, the view's constants) among more voxels; with four the 256^3 cone's
-// back-projection took 2.18 ms per launch against 2.80 with two, and eight
-// (2.15 ms) needs 119 registers and four work-groups per CU.  TZ is the
-// largest power of two up to 32 whose tiles waste at most 1/8 of the voxels
-// over the box's nz (at least 1).
-constexpr int kColVoxels = 4;       // voxels a lane at most
-__host__ __device__ inline int col_vz(int tz) { return tz >= 4 ? 4 : tz; }
+// lanes, each lane VZ voxels of a column (levels l, l + TZ / VZ, ...): eight,
+// or TZ when TZ < 8.  More voxels a lane share its per-view work (the window's
+// staging, the view's constants) among more voxels: on the 256^3 cone's
+// back-projection, 2.80 ms per launch with two, 2.18 with four; after the
+// voxel path's later cuts 1.89 with four and 1.85 with eight (119 registers,
+// four work-groups per CU).  TZ is the largest power of two up to 32 whose
+// tiles waste at most 1/8 of the voxels over the box's nz (at least 1).
+constexpr int kColVoxels = 8;       // voxels a lane at most
+__host__ __device__ inline int col_vz(int tz) { return tz >= 8 ? 8 : tz; }
 __host__ __device__ inline void col_tile_shape(int nz, int& tz, int& cx, int& cy) {
     int t = 32;
     while (t > 1 && ((nz + t - 1) / t) * t - nz > nz / 8) t >>= 1;
     tz = t;
-    const int nc = 256 / (t / col_vz(t));    // 32 .. 256 columns
+    const int nc = 256 / (t / col_vz(t));    // 64 .. 256 columns
     int lg = 0;
     while ((1 << lg) < nc) ++lg;
     cx = 1 << ((lg + 1) / 2);

@@ -1423,7 +1423,7 @@ __global__ __launch_bounds__(256, 6) void k_back3(DGeom G, BA a) {
 // voxel face (the small direction components that the float32 bounds of the
 // general kernel lose).  A zero direction component (the kernels' rule)
 // keeps the ray in the source's slab of that axis.
-constexpr int kColWG = 5;         // resident work-groups per CU the register budget is set for (96 VGPRs)
+constexpr int kColWG = 4;         // resident work-groups per CU the register budget is set for (128 VGPRs)
 constexpr int kColR = 512;        // rays of a view's window staged at once (fast path: the whole window)
 constexpr int kColV = 128;        // rows of a view's window staged at once
 constexpr int kColU = 2;          // X intervals kept per (view, column); wider columns form the rest
