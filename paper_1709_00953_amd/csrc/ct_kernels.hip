@@ -214,6 +214,33 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
         const unsigned long long bu = __ballot((ax == 0 ? R.dy : R.dx) >= 0.0);
         slab_axis = (bu == ~0ull || bu == 0ull) ? ax : -1;
     }
+    // 3D fused forward: the same walk along an xy axis A where every ray of
+    // the chunk moves at most one voxel along the other xy axis B and along z
+    // per slab of A (at most 45 degrees from A in both planes, in units of
+    // the pitches, with a margin), and all go one way along B and one way
+    // along z (signs of the direction components after the kernels' zero
+    // test, as the walk takes them).
+    if constexpr (MODE == 1 && DIMS == 3) {
+        const int kk = ch.k0 + max(0, min(lane, ch.cnt - 1));
+        const double* V = view_of(G, ch.view);
+        const double u = ((double)(ch.u0 + kk % ch.w) - 0.5 * (double)(G.nu - 1)) * G.pu;
+        const double v = ((double)(ch.v0 + kk / ch.w) - 0.5 * (double)(G.nv - 1)) * G.pv;
+        double D[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            D[c] = fma(v, V[9 + c], fma(u, V[6 + c], V[15] * V[12 + c]));
+            if (fabsf((float)(D[c] * V[16])) <= kAxisEpsF) D[c] = 0.0;
+        }
+        const double m = 1.0 + 1e-6;
+        const bool cx = fabs(D[0]) * G.vy >= m * fabs(D[1]) * G.vx && fabs(D[0]) * G.vz >= m * fabs(D[2]) * G.vx;
+        const bool cy = fabs(D[1]) * G.vx >= m * fabs(D[0]) * G.vy && fabs(D[1]) * G.vz >= m * fabs(D[2]) * G.vy;
+        const unsigned long long bx = __ballot(cx), by = __ballot(cy);
+        const int ax = bx == ~0ull ? 0 : (by == ~0ull ? 1 : -1);
+        if (ax >= 0) {
+            const unsigned long long bu = __ballot(D[1 - ax] >= 0.0), bz = __ballot(D[2] >= 0.0);
+            slab_axis = ((bu == ~0ull || bu == 0ull) && (bz == ~0ull || bz == 0ull)) ? ax : -1;
+        }
+    }
 
     float acc = 0.f, acc2 = 0.f;
     unsigned cnt = 0;
@@ -415,6 +442,167 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                     };
                     if (__ballot(!up) == 0ull) walk(std::integral_constant<int, 1>{});
                     else walk(std::integral_constant<int, 2>{});
+                }
+            }
+        }
+        if constexpr (MODE == 1 && DIMS == 3) {
+            if (hit && slab_axis >= 0) {
+                // 3D slab walk.  Along the major xy axis A the ray crosses one
+                // slab of voxels per step; within a slab it moves by at most
+                // one voxel along the other xy axis B and along z, so it meets
+                // at most four voxels there, (B, B + 1) x (z, z + 1): two
+                // 16-byte loads of the copy whose fast axis is B ([z][A][B])
+                // fetch them.  B and z are handled alike, each kept as the
+                // float64 distance to its next plane in the direction of
+                // travel (then rounded), so crossings keep their precision
+                // however small the component; the slab's length splits at the
+                // two crossings (each clamped to the slab).
+                walked = true;
+                const int A = slab_axis, B = 1 - slab_axis;
+                const int nx = b1[0] - b0[0], ny = b1[1] - b0[1], nz = b1[2] - b0[2];
+                const int nA = A == 0 ? nx : ny, nB = A == 0 ? ny : nx, nAB = nx * ny;
+                const int Q = (nA + K - 1) / K;
+                const int S0 = __builtin_amdgcn_readfirstlane(piece) * Q, S1 = min(nA, S0 + Q);
+                const int nS = S1 - S0;                    // uniform per wave
+                if (nS > 0) {
+                    const int grp = __builtin_amdgcn_readfirstlane(en.group);
+                    const int cs = xg_copy(nx, ny, nz);
+                    const float2* xgc = uniform_ptr(a.xg + (size_t)grp * (size_t)a.xg_stride +
+                                                    (A == 0 ? (size_t)cs : (size_t)0));
+                    const double ia = h[A] * fabs(id[A]);  // mm of ray per slab
+                    const double hiA = fma((double)b1[A], h[A], org[A]);
+                    const double Cs = ((d[A] > 0.0 ? lo[A] : hiA) - o[A]) * id[A];
+                    const double tref = fma((double)S0, ia, Cs);
+                    double tlo = fmax(t0 - tref, 0.0);
+                    double thi = fmin(t1, fma((double)S1, ia, Cs)) - tref;
+                    const bool empty = !(thi > tlo);
+                    // minor axes B and z: voxel at tref, its fractional position,
+                    // voxels per mm of ray and mm of ray per voxel
+                    int jb = 0, jz = 0;
+                    double fb64 = 0.5, fz64 = 0.5, idb64 = 1e30, idz64 = 1e30;
+                    float dbf = 0.f, dzf = 0.f;
+                    if (empty) {
+                        tlo = 0.0;
+                        thi = 0.0;
+                    } else {
+                        if (d[B] == 0.0) {
+                            jb = zs[B];                    // the ray stays in slab zs of B
+                        } else {
+                            const double pb = (fma(tref, d[B], o[B]) - lo[B]) * ih[B];
+                            const double fl = floor(pb);
+                            jb = (int)fl;
+                            fb64 = pb - fl;
+                            dbf = (float)(d[B] * ih[B]);
+                            idb64 = fmax(fmin(h[B] * id[B], 1e30), -1e30);
+                        }
+                        if (d[2] == 0.0) {
+                            jz = zs[2];
+                        } else {
+                            const double pz = (fma(tref, d[2], o[2]) - lo[2]) * ih[2];
+                            const double fl = floor(pz);
+                            jz = (int)fl;
+                            fz64 = pz - fl;
+                            dzf = (float)(d[2] * ih[2]);
+                            idz64 = fmax(fmin(h[2] * id[2], 1e30), -1e30);
+                        }
+                    }
+                    // the wave walks the slabs that some lane's ray overlaps
+                    // (its lanes' ranges widened by one slab; a uniform binary
+                    // search over ballots, lanes without overlap neutral)
+                    int ulo = nS, uhi = 0;
+                    if (!empty) {
+                        const double iia = fabs(d[A]) * ih[A];
+                        ulo = max(0, (int)floor(tlo * iia) - 1);
+                        uhi = min(nS, (int)ceil(thi * iia) + 1);
+                    }
+                    int us = 0, ue = nS;
+                    for (int hi = nS; us < hi;) {
+                        const int mid = (us + hi) >> 1;
+                        if (__ballot(ulo <= mid)) hi = mid;
+                        else us = mid + 1;
+                    }
+                    for (int lo2 = 0; lo2 < ue;) {
+                        const int mid = (lo2 + ue) >> 1;
+                        if (__ballot(uhi > mid)) lo2 = mid + 1;
+                        else ue = mid;
+                    }
+                    const bool up = d[B] >= 0.0, upz = d[2] >= 0.0;
+                    const double gb64 = up ? 1.0 - fb64 : fb64, gz64 = upz ? 1.0 - fz64 : fz64;
+                    const float gb = (float)gb64, gz = (float)gz64;
+                    const float nfs = (float)((up ? gb64 : -gb64) * idb64);
+                    const float nzs = (float)((upz ? gz64 : -gz64) * idz64);
+                    const float idb = (float)idb64, idz = (float)idz64;
+                    const float ias = (float)ia, tl = (float)tlo, th = (float)thi;
+                    const int rstep = d[A] > 0.0 ? nB : -nB;
+                    // element index of (slab S0 + us, jb, jz); the padding keeps it positive
+                    int row = (d[A] > 0.0 ? S0 : nA - 1 - S0) * nB + us * rstep + jb + jz * nAB +
+                              xg_pad(nx, ny, nz);
+                    float uf = (float)us;
+                    float ts = __builtin_amdgcn_fmed3f(uf * ias, tl, th);
+                    float fb = up ? floorf(fmaf(ts, dbf, -gb)) + 1.f : floorf(fmaf(ts, dbf, gb));
+                    float fz = upz ? floorf(fmaf(ts, dzf, -gz)) + 1.f : floorf(fmaf(ts, dzf, gz));
+                    // DB, DZ 1: every lane's ray goes up B (z), so the lower
+                    // voxel of a slab's pair is the one it starts in; 2: down
+                    auto walk3 = [&](auto dirb, auto dirz) {
+                        constexpr int DB = decltype(dirb)::value, DZ = decltype(dirz)::value;
+                        for (int u = us; u < ue; u += U) {
+                            int sid[U];
+                            float l00[U], l01[U], l10[U], l11[U];   // [B lower, upper][z lower, upper]
+#pragma unroll
+                            for (int q = 0; q < U; ++q) {
+                                // slabs past S1 get zero lengths (tau clamped to th)
+                                uf += 1.f;
+                                const float te = __builtin_amdgcn_fmed3f(uf * ias, tl, th);
+                                const float fbe = DB == 1 ? floorf(fmaf(te, dbf, -gb)) + 1.f
+                                                          : floorf(fmaf(te, dbf, gb));
+                                const float fze = DZ == 1 ? floorf(fmaf(te, dzf, -gz)) + 1.f
+                                                          : floorf(fmaf(te, dzf, gz));
+                                const float lb = DB == 1 ? fb : fbe, lz = DZ == 1 ? fz : fze;
+                                const float tc = __builtin_amdgcn_fmed3f(
+                                    DB == 1 ? fmaf(lb, idb, nfs) : fmaf(lb + 1.f, idb, nfs), ts, te);
+                                const float tz = __builtin_amdgcn_fmed3f(
+                                    DZ == 1 ? fmaf(lz, idz, nzs) : fmaf(lz + 1.f, idz, nzs), ts, te);
+                                // in the first B voxel on [ts, tc], the second on
+                                // [tc, te]; the first z level on [ts, tz], the second
+                                // on [tz, te]
+                                const float lf[2][2] = {{fminf(tc, tz) - ts, fmaxf(tc - tz, 0.f)},
+                                                        {fmaxf(tz - tc, 0.f), te - fmaxf(tc, tz)}};
+                                constexpr int bl = DB == 1 ? 0 : 1, zl = DZ == 1 ? 0 : 1;
+                                l00[q] = lf[bl][zl];
+                                l01[q] = lf[bl][1 - zl];
+                                l10[q] = lf[1 - bl][zl];
+                                l11[q] = lf[1 - bl][1 - zl];
+                                sid[q] = row + (int)lb + (int)lz * nAB;
+                                row += rstep;
+                                ts = te;
+                                fb = fbe;
+                                fz = fze;
+                            }
+#pragma unroll
+                            for (int q = 0; q < U; ++q) {
+                                const XG2 vl = ld_xg2(xgc, (unsigned)sid[q]);
+                                const XG2 vh = ld_xg2(xgc, (unsigned)(sid[q] + nAB));
+                                acc = fmaf(l00[q], vl.x0, acc);
+                                acc = fmaf(l10[q], vl.x1, acc);
+                                acc = fmaf(l01[q], vh.x0, acc);
+                                acc = fmaf(l11[q], vh.x1, acc);
+                                acc2 = fmaf(l00[q], vl.g0, acc2);
+                                acc2 = fmaf(l10[q], vl.g1, acc2);
+                                acc2 = fmaf(l01[q], vh.g0, acc2);
+                                acc2 = fmaf(l11[q], vh.g1, acc2);
+                            }
+                        }
+                    };
+                    using I1 = std::integral_constant<int, 1>;
+                    using I2 = std::integral_constant<int, 2>;
+                    const bool bup = __ballot(!up) == 0ull, zup = __ballot(!upz) == 0ull;
+                    if (bup) {
+                        if (zup) walk3(I1{}, I1{});
+                        else walk3(I1{}, I2{});
+                    } else {
+                        if (zup) walk3(I2{}, I1{});
+                        else walk3(I2{}, I2{});
+                    }
                 }
             }
         }
