@@ -1643,6 +1643,10 @@ struct WinView {
 
 __device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ float rflf(float v) { return __int_as_float(rfl(__float_as_int(v))); }
+__device__ __forceinline__ double rfld(double v) {
+    const long long b = __double_as_longlong(v);
+    return __longlong_as_double(((long long)(unsigned)rfl((int)(b >> 32)) << 32) | (unsigned)rfl((int)b));
+}
 
 // The fields of a WinView that the staging needs, in scalar registers.
 struct WinS {
@@ -1816,6 +1820,46 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
         float fl = fmaf((float)lz, svz, f00);
         int ssrc = 0;                                    // the source's level in the tile
         if constexpr (CAREFUL) ssrc = src_slab(zS, G.oz, G.ivz) - zs;
+        if constexpr (FAST && !CAREFUL) {
+            if (Ws.flags & 4) {
+                // every voxel of the view has at most two rows and every
+                // column at most two bins: rows k0 and k0 + 1 of every voxel
+                // (as in the two-row branch below), the lane's voxels in one
+                // straight run with no test, so that their reads of LDS are
+                // issued together.  A voxel outside the box reads inside the
+                // buffers (its row is clamped to the window, its column's
+                // offset to the window's width) and its sum is dropped.
+                // the lower face of voxel q over the source: level zs + lz + q TL
+                // (the level passes through an empty asm statement, so that its
+                // conversions are formed here rather than held across the views)
+                const double ozs = rfld(G.oz - zS);
+                int zl0 = zs + lz;
+                asm volatile("" : "+v"(zl0));
+#pragma unroll
+                for (int q = 0; q < kColVZ; ++q) {
+                    if (q > 0) fl += dfl;
+                    const float lo = fmaf(-fabsf(fl), sh, fmaf(fl, sm, cl));
+                    const int k0 = (int)__builtin_amdgcn_fmed3f(ceilf(lo), fva, fvb);
+                    const int rA = __umul24(k0, pw) + rva, rB = rA + pw;
+                    // the row constants and the four rays, read together
+                    const double iA = SIv[k0], iB = SIv[k0 + 1];
+                    const float r0 = R[rA], r1 = R[rA + 1], r2 = R[rB], r3 = R[rB + 1];
+                    const double zfl = fma((double)(zl0 + q * TL), G.vz, ozs);
+                    const double pA = fma(zfl, iA, -A), pB = fma(zfl, iB, -A);
+                    const float pfA = (float)pA, rfA = (float)fma(G.vz, iA, pA);
+                    const float pfB = (float)pB, rfB = (float)fma(G.vz, iB, pB);
+                    const float zlA = fminf(pfA, rfA), zhA = fmaxf(pfA, rfA);
+                    const float zlB = fminf(pfB, rfB), zhB = fmaxf(pfB, rfB);
+                    float acc = accv[q];
+                    acc = fmaf(col_clip(X0, zlA, zhA), r0, acc);
+                    acc = fmaf(col_clip(X1, zlA, zhA), r1, acc);
+                    acc = fmaf(col_clip(X0, zlB, zhB), r2, acc);
+                    acc = fmaf(col_clip(X1, zlB, zhB), r3, acc);
+                    accv[q] = acc;
+                }
+                return;
+            }
+        }
 #pragma unroll
         for (int q = 0; q < kColVZ; ++q) {
             if (q > 0) fl += dfl;
