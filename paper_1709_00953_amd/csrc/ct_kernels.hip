@@ -1709,7 +1709,14 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
     // per row, and the row after a staged part (zeroed by stage()), stay
     // inside it (the row loops below)
     __shared__ float sRb[2][2 * kColR + 4];
-    __shared__ double sI[2][kColV + 1];          // 2^e sdd / D_z of its rows; one more read, not used
+    // per row of a staged part: 2^e sdd / D_z (one more read, not used) and,
+    // 8 KiB-apart in the same record so that one address serves both, the
+    // float32 widths vz 2^e sdd / D_z of the row and the next (0 past the part)
+    struct RowC {
+        double isv[kColV + 1];
+        float2 w[kColV + 1];
+    };
+    __shared__ RowC sI[2];
     __shared__ double zlev[32];                  // height of the lower face of each level of the tile
     __shared__ double sh[4];
     const int t = threadIdx.x;
@@ -1736,7 +1743,10 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
     for (int q = 0; q < kColVZ; ++q) valid[q] = colv && q < VZ && lz + q * TL < nvz;
     // every value of sRb and sI is zero or one written by stage(): finite
     for (int i = t; i < 2 * (2 * kColR + 4); i += 256) (&sRb[0][0])[i] = 0.f;
-    for (int i = t; i < 2 * (kColV + 1); i += 256) (&sI[0][0])[i] = 0.0;
+    for (int i = t; i < 2 * (kColV + 1); i += 256) {
+        sI[i / (kColV + 1)].isv[i % (kColV + 1)] = 0.0;
+        sI[i / (kColV + 1)].w[i % (kColV + 1)] = make_float2(0.f, 0.f);
+    }
     if (t < 32) zlev[t] = fma((double)(zs + t), G.vz, G.oz);
 
     int e0 = 0, e1 = a.n_ent;
@@ -1773,7 +1783,12 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
         // the row after the part reads zeros (and two more floats)
         for (int i = t; i < pw + 2; i += 256) sRb[b][2 + nr + i] = 0.f;
         const double* isv = G.cisv + (size_t)view * G.nv;
-        for (int i = t; i < nrow; i += 256) sI[b][i] = ldu(isv, (unsigned)(va + i));
+        for (int i = t; i < nrow; i += 256) {
+            const double s0 = ldu(isv, (unsigned)(va + i));
+            const double s1 = i + 1 < nrow ? ldu(isv, (unsigned)(va + i + 1)) : 0.0;
+            sI[b].isv[i] = s0;
+            sI[b].w[i] = make_float2((float)(G.vz * s0), (float)(G.vz * s1));
+        }
     };
 
     float accv[kColVZ];
@@ -1787,7 +1802,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                     int ub, int va, int vb) {
         constexpr bool FAST = decltype(fast_c)::value, CAREFUL = decltype(careful_c)::value;
         const float* R = &sRb[b][2];
-        const double* SIv = sI[b] - va;                  // row k at SIv[k]
+        const double* SIv = sI[b].isv - va;              // row k at SIv[k]
         const double zS = wv[j].zS;
         const float svz = wv[j].svz, f00 = wv[j].f00, asvz = fabsf(svz);
         int rva = C.rva;
@@ -1829,25 +1844,42 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                 // issued together.  A voxel outside the box reads inside the
                 // buffers (its row is clamped to the window, its column's
                 // offset to the window's width) and its sum is dropped.
-                // the lower face of voxel q over the source: level zs + lz + q TL
-                // (the level passes through an empty asm statement, so that its
-                // conversions are formed here rather than held across the views)
-                const double ozs = rfld(G.oz - zS);
+                // the lower face of voxel q over the source, stepped by TL
+                // levels (the level passes through an empty asm statement, so
+                // that the first is formed here rather than held across the views)
                 int zl0 = zs + lz;
                 asm volatile("" : "+v"(zl0));
+                double zfl = fma((double)zl0, G.vz, rfld(G.oz - zS));
+                const double dzq = (double)TL * G.vz;
+                // byte addresses: row k's first ray at Rb - 4 pw nk, its row
+                // constants at Sb - 8 nk (nk = -k, the negated ceiling being a
+                // floor of the negation)
+                const char* Rb = reinterpret_cast<const char*>(R) + 4 * rva;
+                const char* Sb = reinterpret_cast<const char*>(sI[b].isv);
+                const int m4pw = -4 * pw;
+                const float fnv0 = (float)(-va), fnv1 = (float)(1 - vb);
 #pragma unroll
                 for (int q = 0; q < kColVZ; ++q) {
-                    if (q > 0) fl += dfl;
+                    if (q > 0) {
+                        fl += dfl;
+                        zfl += dzq;
+                    }
                     const float lo = fmaf(-fabsf(fl), sh, fmaf(fl, sm, cl));
-                    const int k0 = (int)__builtin_amdgcn_fmed3f(ceilf(lo), fva, fvb);
-                    const int rA = __umul24(k0, pw) + rva, rB = rA + pw;
+                    // -k0, k0 = ceil(lo) clamped to the window's rows (the
+                    // clamp to integer bounds commutes with the floor)
+                    const int nk = (int)floorf(__builtin_amdgcn_fmed3f(-lo, fnv1, fnv0));
+                    const char* ra = Rb + __mul24(nk, m4pw);
+                    const char* sa = Sb + __mul24(nk, -8) - 8 * va;
                     // the row constants and the four rays, read together
-                    const double iA = SIv[k0], iB = SIv[k0 + 1];
-                    const float r0 = R[rA], r1 = R[rA + 1], r2 = R[rB], r3 = R[rB + 1];
-                    const double zfl = fma((double)(zl0 + q * TL), G.vz, ozs);
-                    const double pA = fma(zfl, iA, -A), pB = fma(zfl, iB, -A);
-                    const float pfA = (float)pA, rfA = (float)fma(G.vz, iA, pA);
-                    const float pfB = (float)pB, rfB = (float)fma(G.vz, iB, pB);
+                    const double iA = *reinterpret_cast<const double*>(sa);
+                    const double iB = *reinterpret_cast<const double*>(sa + 8);
+                    const float2 wAB = *reinterpret_cast<const float2*>(sa + offsetof(RowC, w));
+                    const float r0 = *reinterpret_cast<const float*>(ra);
+                    const float r1 = *reinterpret_cast<const float*>(ra + 4);
+                    const float r2 = *reinterpret_cast<const float*>(ra + 4 * pw);
+                    const float r3 = *reinterpret_cast<const float*>(ra + 4 * pw + 4);
+                    const float pfA = (float)fma(zfl, iA, -A), pfB = (float)fma(zfl, iB, -A);
+                    const float rfA = pfA + wAB.x, rfB = pfB + wAB.y;
                     const float zlA = fminf(pfA, rfA), zhA = fmaxf(pfA, rfA);
                     const float zlB = fminf(pfB, rfB), zhB = fmaxf(pfB, rfB);
                     float acc = accv[q];
