@@ -83,7 +83,7 @@ __device__ __forceinline__ T ldu(const T* base, unsigned i) {
 }
 
 // Two adjacent (x, g) pairs of a J-local copy, elements i and i + 1: one
-// 16-byte load from an 8-byte aligned address.
+// 16-byte load from an 8-byte aligned address (ld_xg2b: at byte offset 8 i).
 struct __attribute__((aligned(8))) XG2 {
     float x0, g0, x1, g1;
 };
@@ -95,6 +95,15 @@ __device__ __forceinline__ XG2 ld_xg2(const float2* base, unsigned i) {
 #else
     const float2 a = base[i], b = base[i + 1];     // host pass: never executed
     return XG2{a.x, a.y, b.x, b.y};
+#endif
+}
+__device__ __forceinline__ XG2 ld_xg2b(const float2* base, unsigned off) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    using GP = const __attribute__((address_space(1))) char*;
+    using GT = const __attribute__((address_space(1))) XG2*;
+    return *(GT)((GP)base + off);
+#else
+    return ld_xg2(base, off / 8u);                 // host pass: never executed
 #endif
 }
 
@@ -219,7 +228,8 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
     // per slab of A (at most 45 degrees from A in both planes, in units of
     // the pitches, with a margin), and all go one way along B and one way
     // along z (signs of the direction components after the kernels' zero
-    // test, as the walk takes them).
+    // test, as the walk takes them), in a box whose z slab holds fewer than
+    // 2^23 voxels (the walk's index products are 24-bit).
     if constexpr (MODE == 1 && DIMS == 3) {
         const int kk = ch.k0 + max(0, min(lane, ch.cnt - 1));
         const double* V = view_of(G, ch.view);
@@ -236,7 +246,8 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
         const bool cy = fabs(D[1]) * G.vx >= m * fabs(D[0]) * G.vy && fabs(D[1]) * G.vz >= m * fabs(D[2]) * G.vy;
         const unsigned long long bx = __ballot(cx), by = __ballot(cy);
         const int ax = bx == ~0ull ? 0 : (by == ~0ull ? 1 : -1);
-        if (ax >= 0) {
+        const int nab = (a.box.x1 - a.box.x0) * (a.box.y1 - a.box.y0);
+        if (ax >= 0 && nab < (1 << 23)) {
             const unsigned long long bu = __ballot(D[1 - ax] >= 0.0), bz = __ballot(D[2] >= 0.0);
             slab_axis = ((bu == ~0ull || bu == 0ull) && (bz == ~0ull || bz == 0ull)) ? ax : -1;
         }
@@ -534,6 +545,7 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                     const float idb = (float)idb64, idz = (float)idz64;
                     const float ias = (float)ia, tl = (float)tlo, th = (float)thi;
                     const int rstep = d[A] > 0.0 ? nB : -nB;
+                    const unsigned nAB8 = 8u * (unsigned)nAB;
                     // element index of (slab S0 + us, jb, jz); the padding keeps it positive
                     int row = (d[A] > 0.0 ? S0 : nA - 1 - S0) * nB + us * rstep + jb + jz * nAB +
                               xg_pad(nx, ny, nz);
@@ -564,15 +576,18 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                                     DZ == 1 ? fmaf(lz, idz, nzs) : fmaf(lz + 1.f, idz, nzs), ts, te);
                                 // in the first B voxel on [ts, tc], the second on
                                 // [tc, te]; the first z level on [ts, tz], the second
-                                // on [tz, te]
-                                const float lf[2][2] = {{fminf(tc, tz) - ts, fmaxf(tc - tz, 0.f)},
-                                                        {fmaxf(tz - tc, 0.f), te - fmaxf(tc, tz)}};
+                                // on [tz, te]: the first voxel to min(tc, tz), the last
+                                // from max(tc, tz), the one between them (one of the
+                                // two mixed ones, the other 0) on [min, max]
+                                const float mn = fminf(tc, tz), mx = fmaxf(tc, tz);
+                                const float lf[2][2] = {{mn - ts, tc - mn}, {tz - mn, te - mx}};
                                 constexpr int bl = DB == 1 ? 0 : 1, zl = DZ == 1 ? 0 : 1;
                                 l00[q] = lf[bl][zl];
                                 l01[q] = lf[bl][1 - zl];
                                 l10[q] = lf[1 - bl][zl];
                                 l11[q] = lf[1 - bl][1 - zl];
-                                sid[q] = row + (int)lb + (int)lz * nAB;
+                                // byte offset (nAB < 2^23, lz small: 24-bit product)
+                                sid[q] = (int)((unsigned)(row + (int)lb + __mul24((int)lz, nAB)) << 3);
                                 row += rstep;
                                 ts = te;
                                 fb = fbe;
@@ -580,8 +595,8 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                             }
 #pragma unroll
                             for (int q = 0; q < U; ++q) {
-                                const XG2 vl = ld_xg2(xgc, (unsigned)sid[q]);
-                                const XG2 vh = ld_xg2(xgc, (unsigned)(sid[q] + nAB));
+                                const XG2 vl = ld_xg2b(xgc, (unsigned)sid[q]);
+                                const XG2 vh = ld_xg2b(xgc, (unsigned)sid[q] + nAB8);
                                 acc = fmaf(l00[q], vl.x0, acc);
                                 acc = fmaf(l10[q], vl.x1, acc);
                                 acc = fmaf(l01[q], vh.x0, acc);
