@@ -1631,6 +1631,7 @@ constexpr int kColR = 512;        // rays of a view's window staged at once (fas
 constexpr int kColV = 128;        // rows of a view's window staged at once
 constexpr int kColU = 2;          // X intervals kept per (view, column); wider columns form the rest
 constexpr int kColVZ = kColVoxels;  // voxels a lane at most (col_tile_shape)
+constexpr int kColTiles = 1024;   // a group's tiles listed in LDS (more: each round walks the entries)
 
 // Per (view, column) of a round.
 struct ColView {
@@ -1733,6 +1734,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
     };
     __shared__ RowC sI[2];
     __shared__ double zlev[32];                  // height of the lower face of each level of the tile
+    __shared__ int tix[kColTiles];               // the group's tiles (indices into the tile list)
     __shared__ double sh[4];
     const int t = threadIdx.x;
     int TZ, CX, CY;
@@ -1774,6 +1776,25 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
         const int rb = get_entry(a, e).rb;
         nt += G.rb_tile_ptr[rb + 1] - G.rb_tile_ptr[rb];
     }
+    // the group's tiles, listed once in LDS (thread i finds tile i), so that a
+    // round's set-up reads its tile without walking the entries
+    const bool listed = nt <= kColTiles;
+    if (listed) {
+        for (int i = t; i < nt; i += 256) {
+            int e = e0, off = i;
+            for (;;) {
+                const int rb = get_entry(a, e).rb;
+                const int p0 = G.rb_tile_ptr[rb], cnt = G.rb_tile_ptr[rb + 1] - p0;
+                if (off < cnt) {
+                    tix[i] = p0 + off;
+                    break;
+                }
+                off -= cnt;
+                ++e;
+            }
+        }
+    }
+    __syncthreads();
 
     // rays [0, nr) (rows of pw bins from (ua, va)) and rows [0, nrow) of a
     // window part of `view` into buffer b
@@ -1787,22 +1808,41 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
         // row of element i: (i + 1/2) / pw lies at least 1/(2 pw) from an
         // integer, far beyond the rounding of rcp and the product for i < 2^12
         const float ipw = __builtin_amdgcn_rcpf((float)pw);
-        for (int i = t; i < nr; i += 256) {
-            const int row = (int)(((float)i + 0.5f) * ipw);
-            const int iu = ua + (i - __umul24(row, pw)), iv = va + row;
-            const float q2 = ldu(reinterpret_cast<const float*>(dxy + iu), 2u);   // D~_x^2 + D~_y^2
-            const float z = ldu(dz, (unsigned)iv);
-            const float nrm = __builtin_amdgcn_sqrtf(fmaf(z, z, q2));
-            sRb[b][2 + i] = nrm * ldu(rview, (unsigned)(iv * G.nu + iu));
+        // a part holds at most 2 x 256 rays and 256 rows: each thread's two
+        // rays and its row constants are loaded first, then written, so their
+        // loads wait once
+        static_assert(kColR <= 2 * 256 && kColV < 256, "two rays and one row a thread");
+        const double* isv = G.cisv + (size_t)view * G.nv;
+        float q2[2], z[2], rr[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int i = t + 256 * k;
+            q2[k] = 0.f;
+            z[k] = 0.f;
+            rr[k] = 0.f;
+            if (i < nr) {
+                const int row = (int)(((float)i + 0.5f) * ipw);
+                const int iu = ua + (i - __umul24(row, pw)), iv = va + row;
+                q2[k] = ldu(reinterpret_cast<const float*>(dxy + iu), 2u);   // D~_x^2 + D~_y^2
+                z[k] = ldu(dz, (unsigned)iv);
+                rr[k] = ldu(rview, (unsigned)(iv * G.nu + iu));
+            }
+        }
+        double s0 = 0.0, s1 = 0.0;
+        if (t < nrow) {
+            s0 = ldu(isv, (unsigned)(va + t));
+            if (t + 1 < nrow) s1 = ldu(isv, (unsigned)(va + t + 1));
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int i = t + 256 * k;
+            if (i < nr) sRb[b][2 + i] = __builtin_amdgcn_sqrtf(fmaf(z[k], z[k], q2[k])) * rr[k];
         }
         // the row after the part reads zeros (and two more floats)
         for (int i = t; i < pw + 2; i += 256) sRb[b][2 + nr + i] = 0.f;
-        const double* isv = G.cisv + (size_t)view * G.nv;
-        for (int i = t; i < nrow; i += 256) {
-            const double s0 = ldu(isv, (unsigned)(va + i));
-            const double s1 = i + 1 < nrow ? ldu(isv, (unsigned)(va + i + 1)) : 0.0;
-            sI[b].isv[i] = s0;
-            sI[b].w[i] = make_float2((float)(G.vz * s0), (float)(G.vz * s1));
+        if (t < nrow) {
+            sI[b].isv[t] = s0;
+            sI[b].w[t] = make_float2((float)(G.vz * s0), (float)(G.vz * s1));
         }
     };
 
@@ -2009,17 +2049,21 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
             phy *= 0.5;
             const int j = pt >> lgNC, cc = pt & (NC - 1);
             if (j < nvr) {
-                int e = e0, off = base + j;
                 Tile tl{};
-                for (;;) {
-                    const int rb = get_entry(a, e).rb;
-                    const int cnt = G.rb_tile_ptr[rb + 1] - G.rb_tile_ptr[rb];
-                    if (off < cnt) {
-                        tl = G.tiles[G.rb_tile_ptr[rb] + off];
-                        break;
+                if (listed) {
+                    tl = G.tiles[tix[base + j]];
+                } else {
+                    int e = e0, off = base + j;
+                    for (;;) {
+                        const int rb = get_entry(a, e).rb;
+                        const int cnt = G.rb_tile_ptr[rb + 1] - G.rb_tile_ptr[rb];
+                        if (off < cnt) {
+                            tl = G.tiles[G.rb_tile_ptr[rb] + off];
+                            break;
+                        }
+                        off -= cnt;
+                        ++e;
                     }
-                    off -= cnt;
-                    ++e;
                 }
                 const double* V = view_of(G, tl.view);
                 const double sdd = V[15];
