@@ -543,6 +543,12 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                     const float nfs = (float)((up ? gb64 : -gb64) * idb64);
                     const float nzs = (float)((upz ? gz64 : -gz64) * idz64);
                     const float idb = (float)idb64, idz = (float)idz64;
+                    // going up, the voxel at tau is floor(tau d + 1 - g) (the +1
+                    // folded into the offset); going down, the crossing of the
+                    // plane above voxel l is at (l + 1) id - g id, the id folded
+                    // into the offset too
+                    const float gb1 = up ? 1.f - gb : gb, gz1 = upz ? 1.f - gz : gz;
+                    const float nfs1 = up ? nfs : nfs + idb, nzs1 = upz ? nzs : nzs + idz;
                     const float ias = (float)ia, tl = (float)tlo, th = (float)thi;
                     const int rstep = d[A] > 0.0 ? nB : -nB;
                     const unsigned nAB8 = 8u * (unsigned)nAB;
@@ -551,8 +557,8 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                               xg_pad(nx, ny, nz);
                     float uf = (float)us;
                     float ts = __builtin_amdgcn_fmed3f(uf * ias, tl, th);
-                    float fb = up ? floorf(fmaf(ts, dbf, -gb)) + 1.f : floorf(fmaf(ts, dbf, gb));
-                    float fz = upz ? floorf(fmaf(ts, dzf, -gz)) + 1.f : floorf(fmaf(ts, dzf, gz));
+                    float fb = floorf(fmaf(ts, dbf, gb1));
+                    float fz = floorf(fmaf(ts, dzf, gz1));
                     // DB, DZ 1: every lane's ray goes up B (z), so the lower
                     // voxel of a slab's pair is the one it starts in; 2: down
                     auto walk3 = [&](auto dirb, auto dirz) {
@@ -565,15 +571,11 @@ __device__ __forceinline__ void fwd_body(const DGeom& G, const FA& a, const int 
                                 // slabs past S1 get zero lengths (tau clamped to th)
                                 uf += 1.f;
                                 const float te = __builtin_amdgcn_fmed3f(uf * ias, tl, th);
-                                const float fbe = DB == 1 ? floorf(fmaf(te, dbf, -gb)) + 1.f
-                                                          : floorf(fmaf(te, dbf, gb));
-                                const float fze = DZ == 1 ? floorf(fmaf(te, dzf, -gz)) + 1.f
-                                                          : floorf(fmaf(te, dzf, gz));
+                                const float fbe = floorf(fmaf(te, dbf, gb1));
+                                const float fze = floorf(fmaf(te, dzf, gz1));
                                 const float lb = DB == 1 ? fb : fbe, lz = DZ == 1 ? fz : fze;
-                                const float tc = __builtin_amdgcn_fmed3f(
-                                    DB == 1 ? fmaf(lb, idb, nfs) : fmaf(lb + 1.f, idb, nfs), ts, te);
-                                const float tz = __builtin_amdgcn_fmed3f(
-                                    DZ == 1 ? fmaf(lz, idz, nzs) : fmaf(lz + 1.f, idz, nzs), ts, te);
+                                const float tc = __builtin_amdgcn_fmed3f(fmaf(lb, idb, nfs1), ts, te);
+                                const float tz = __builtin_amdgcn_fmed3f(fmaf(lz, idz, nzs1), ts, te);
                                 // in the first B voxel on [ts, tc], the second on
                                 // [tc, te]; the first z level on [ts, tz], the second
                                 // on [tz, te]: the first voxel to min(tc, tz), the last
