@@ -1633,7 +1633,7 @@ constexpr int kColR = 512;        // rays of a view's window staged at once (fas
 constexpr int kColV = 128;        // rows of a view's window staged at once
 constexpr int kColU = 2;          // X intervals kept per (view, column); wider columns form the rest
 constexpr int kColVZ = kColVoxels;  // voxels a lane at most (col_tile_shape)
-constexpr int kColTiles = 1024;   // a group's tiles listed in LDS (more: each round walks the entries)
+constexpr int kColTiles = 512;    // a group's tiles listed in LDS (more: each round walks the entries)
 
 // Per (view, column) of a round.
 struct ColView {
@@ -1736,7 +1736,8 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
     };
     __shared__ RowC sI[2];
     __shared__ double zlev[32];                  // height of the lower face of each level of the tile
-    __shared__ int tix[kColTiles];               // the group's tiles (indices into the tile list)
+    // the group's tiles: view, u0 | u1 << 16, v0 | v1 << 16
+    __shared__ int3 tix[kColTiles];
     __shared__ double sh[4];
     const int t = threadIdx.x;
     int TZ, CX, CY;
@@ -1779,8 +1780,9 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
         nt += G.rb_tile_ptr[rb + 1] - G.rb_tile_ptr[rb];
     }
     // the group's tiles, listed once in LDS (thread i finds tile i), so that a
-    // round's set-up reads its tile without walking the entries
-    const bool listed = nt <= kColTiles;
+    // round's set-up reads its tile, and loads its view, without walking the
+    // entries or loading the tile (detectors of at most 65535 bins and rows)
+    const bool listed = nt <= kColTiles && G.nu <= 65535 && G.nv <= 65535;
     if (listed) {
         for (int i = t; i < nt; i += 256) {
             int e = e0, off = i;
@@ -1788,7 +1790,8 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                 const int rb = get_entry(a, e).rb;
                 const int p0 = G.rb_tile_ptr[rb], cnt = G.rb_tile_ptr[rb + 1] - p0;
                 if (off < cnt) {
-                    tix[i] = p0 + off;
+                    const Tile tt = G.tiles[p0 + off];
+                    tix[i] = make_int3(tt.view, tt.u0 | (tt.u1 << 16), tt.v0 | (tt.v1 << 16));
                     break;
                 }
                 off -= cnt;
@@ -2053,7 +2056,9 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
             if (j < nvr) {
                 Tile tl{};
                 if (listed) {
-                    tl = G.tiles[tix[base + j]];
+                    const int3 tc = tix[base + j];
+                    tl = Tile{tc.x, tc.y & 0xffff, (int)((unsigned)tc.y >> 16), tc.z & 0xffff,
+                              (int)((unsigned)tc.z >> 16)};
                 } else {
                     int e = e0, off = base + j;
                     for (;;) {
