@@ -1738,6 +1738,7 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
     __shared__ double zlev[32];                  // height of the lower face of each level of the tile
     // the group's tiles: view, u0 | u1 << 16, v0 | v1 << 16
     __shared__ int3 tix[kColTiles];
+    __shared__ int wvote[4];                     // a wave's vote: some column not two rows, two bins
     __shared__ double sh[4];
     const int t = threadIdx.x;
     int TZ, CX, CY;
@@ -2194,12 +2195,16 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
                     }
                 }
                 // where the view slot's NC lanes lie in one wave (NC <= 64, a
-                // power of two); else each voxel decides with a vote
+                // power of two) its column lane 0 sets the flag; else (the
+                // slot spans NC / 64 whole waves) each wave leaves its vote
+                // for the slot's waves to be combined after the barrier
                 const unsigned long long bal = __ballot(!simple);
                 if (NC <= 64) {
                     const unsigned long long slot = (NC == 64 ? ~0ull : ((1ull << NC) - 1ull))
                                                     << ((pt & 63) & ~(NC - 1));
                     if (cc == 0 && (bal & slot) == 0ull) wv[j].flags |= 4;
+                } else if ((pt & 63) == 0) {
+                    wvote[pt >> 6] = bal != 0ull ? 1 : 0;
                 }
                 const int skx = src_slab(V[0], G.ox, G.ivx), sky = src_slab(V[1], G.oy, G.ivy);
 #pragma unroll
@@ -2217,6 +2222,17 @@ __device__ __forceinline__ void back3c_body(const DGeom& G, const BA& a, const i
             }
         }
         __syncthreads();
+        if (NC > 64) {
+            // a view slot of NC / 64 waves: two rows and two bins where none
+            // of its waves voted otherwise
+            if (t < nvr) {
+                const int wps = NC >> 6;
+                bool any = false;
+                for (int w = t * wps; w < (t + 1) * wps; ++w) any = any || wvote[w] != 0;
+                if (!any) wv[t].flags |= 4;
+            }
+            __syncthreads();
+        }
         // the round's views, one barrier each: the next view's window is staged
         // while this one's is gathered
         WinS W = win_s(wv[0]);
