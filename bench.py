@@ -56,6 +56,8 @@ PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 COUNTERS = {
     ("fan2d_512", "back"): {"fetch": 21810.0, "write": 2112.0, "valu": 1.179e7,
                             "profile": "profiles/fan2d_512_back_projection_hbm_traffic.md"},
+    ("cone3d_256", "back"): {"fetch": 187089.4, "write": 132013.0, "valu": 7.841e8,
+                             "profile": "profiles/cone3d_256_counters.md"},
 }
 SERVE_FAN = (256, 384, 512, 768, 1024)
 SERVE_CONE = (64, 96, 128, 160, 192)
