@@ -1302,7 +1302,7 @@ __device__ __forceinline__ void view_params3(const DGeom& G, const Tile& tl, con
     if (P.fu1 > P.fu0 && P.fv1 > P.fv0) {
         const double ua = ((double)P.fu0 - c0u) * G.pu, ub = ((double)(P.fu1 - 1) - c0u) * G.pu;
         const double va = ((double)P.fv0 - c0v) * G.pv, vb = ((double)(P.fv1 - 1) - c0v) * G.pv;
-        bool near = false;
+        int nm = 0;                                  // the axes that have such rays
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const double c = V[12 + k], eu = V[6 + k] * isdd, ev = V[9 + k] * isdd;
@@ -1310,9 +1310,9 @@ __device__ __forceinline__ void view_params3(const DGeom& G, const Tile& tl, con
             const double d10 = fma(va, ev, fma(ub, eu, c)), d11 = fma(vb, ev, fma(ub, eu, c));
             const double lo = fmin(fmin(d00, d01), fmin(d10, d11));
             const double hi = fmax(fmax(d00, d01), fmax(d10, d11));
-            near = near || (lo < kNearAxis && hi > -kNearAxis);
+            if (lo < kNearAxis && hi > -kNearAxis) nm |= 1 << k;
         }
-        if (near) P.flags |= 4;
+        if (nm) P.flags |= 4 | (nm << 8);
     }
     // plus the float32 rounding of the voxel's shadow centre and half-extent
     // (|beta| <= a few thousand bins)
@@ -1372,6 +1372,41 @@ __device__ __forceinline__ float clip3_precise(const double* V, double u, double
             const float a = (float)(num - h[k]) * ik, b = (float)(num + h[k]) * ik;
             lo = fmaxf(lo, fminf(a, b));
             hi = fminf(hi, fmaxf(a, b));
+        }
+    }
+    return fmaxf(hi - lo, 0.f);
+}
+
+// The same with only the axes of mask nm (those whose window holds a ray
+// with a small or zero component) in float64; the other axes' rays all have
+// components of at least kNearAxis, so their bounds take the staged float32
+// form (q0, q1, q2 as in clip3) on du, dv rounded from float64.
+__device__ __forceinline__ float clip3_mixed(const double* V, double u, double v, double Av, double Bu,
+                                             double Bv, const double h[3], const int vi[3], const int sk[3],
+                                             int nm, const float4& q0, const float4& q1, const float4& q2) {
+    const double isdd = V[16];
+    const double du = fma(-Av, u * isdd, Bu), dv = fma(-Av, v * isdd, Bv);
+    const float duf = (float)du, dvf = (float)dv;
+    const float al[3] = {q0.x, q0.y, q0.z}, be[3] = {q1.x, q1.y, q1.z}, w[3] = {q0.w, q1.w, q2.x};
+    float lo = -INFINITY, hi = INFINITY;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (nm & (1 << k)) {
+            const double Dk = fma(v, V[9 + k], fma(u, V[6 + k], V[15] * V[12 + k]));
+            const float dk = (float)(Dk * isdd);
+            if (fabsf(dk) <= kAxisEpsF) {
+                if (vi[k] != sk[k]) hi = -INFINITY;
+            } else {
+                const double num = fma(du, V[6 + k], dv * V[9 + k]);
+                const float ik = __builtin_amdgcn_rcpf(dk);
+                const float a = (float)(num - h[k]) * ik, b = (float)(num + h[k]) * ik;
+                lo = fmaxf(lo, fminf(a, b));
+                hi = fminf(hi, fmaxf(a, b));
+            }
+        } else {
+            const float sk2 = fmaf(duf, al[k], dvf * be[k]);
+            lo = fmaxf(lo, sk2 - w[k]);
+            hi = fminf(hi, sk2 + w[k]);
         }
     }
     return fmaxf(hi - lo, 0.f);
@@ -1545,12 +1580,20 @@ __device__ __forceinline__ void back3_body(const DGeom& G, const BA& a, const in
                                           fma((double)oz * G.vz, V[11], fma((double)oy * G.vy, V[10], (double)ox * G.vx * V[9]));
                         const double Av = At + fma((double)oz * G.vz, V[14], fma((double)oy * G.vy, V[13], (double)ox * G.vx * V[12]));
                         const double h64[3] = {0.5 * G.vx, 0.5 * G.vy, 0.5 * G.vz};
+                        const int nm = (__builtin_amdgcn_readfirstlane(P.flags) >> 8) & 7;
                         for (int iv = va; iv <= vb; ++iv) {
                             const double v = ((double)iv - c0v) * pv;
                             for (int iu = ua; iu <= ub; ++iu) {
-                                const float4 q2 = lds_f4(rc2, ((iv - cv0) * pw + (iu - cu0)) * 16);
+                                const int lbc = ((iv - cv0) * pw + (iu - cu0)) * 16;
+                                const float4 q2 = lds_f4(rc2, lbc);
                                 const double u = ((double)iu - c0u) * pu;
-                                acc = fmaf(clip3_precise(V, u, v, Av, Bu, Bv, h64, vi, P.sk), q2.y, acc);
+                                if (nm == 7) {
+                                    acc = fmaf(clip3_precise(V, u, v, Av, Bu, Bv, h64, vi, P.sk), q2.y, acc);
+                                } else {
+                                    const float4 q0 = lds_f4(rc0, lbc), q1 = lds_f4(rc1, lbc);
+                                    acc = fmaf(clip3_mixed(V, u, v, Av, Bu, Bv, h64, vi, P.sk, nm, q0, q1, q2),
+                                               q2.y, acc);
+                                }
                             }
                         }
                     } else {
